@@ -1,0 +1,155 @@
+/*
+ * ccgf.h -- C ABI of the MI355X periodic coupled-cluster Green's function library.
+ *
+ * The library computes the diagonal k-point CCGF (Eq. 9 of Laughon, Yu & Zhu,
+ * "Periodic Coupled-Cluster Green's Function for Photoemission Spectra of
+ * Realistic Solids"):
+ *
+ *   G_pp(K, w) = G+_pp + G-_pp,
+ *   G-_pp = e-_p . [(w + (Hbar - E) - i eta)^-1 b-_p]          (IP, Eq. 6b/7b)
+ *   G+_pp = e+_p . [(w - (Hbar - E) + i eta)^-1 b+_p]          (EA, Eq. 6a/7a)
+ *
+ * with b-_p = abar_p|Phi>, b+_p = abar+_p|Phi>, e-_p = <Phi|(1+Lambda) abar+_p,
+ * e+_p = <Phi|(1+Lambda) abar_p restricted to the EOM-CCSD spaces of Eq. 8
+ * (1h + 2h1p for IP, 1p + 2p1h for EA), Lambda = T^dagger (the approximation
+ * stated after Eq. 10), and Hbar - E the EOM-CCSD matrix, i.e. the connected
+ * commutator <mu|[Hbar, R_nu]|Phi>.  The products are bilinear (e is not
+ * conjugated).  Every shifted system is solved by a batched, diagonally
+ * right-preconditioned restarted GMRES on the GPU whose matrix-vector product
+ * is the k-blocked EOM-IP/EA-CCSD sigma product; its cost is the one quoted in
+ * the paper's scaling paragraph (EA O(Nk^3 No Nv^4), IP O(Nk^3 No^3 Nv^2) per
+ * k-point, frequency and orbital).
+ *
+ * Conventions (all functions):
+ *  - Spin orbitals, occupied first: p in [0, nocc) occupied, [nocc, nmo) virtual.
+ *  - Complex numbers are interleaved {re, im} doubles.
+ *  - k-points: Gamma-centred integer mesh kmesh = (m1, m2, m3); point n = (n1,n2,n3)
+ *    has flat index n1*m2*m3 + n2*m3 + n3 and momentum arithmetic is modulo the mesh.
+ *  - Two-electron integrals are given by a momentum-blocked factor A with
+ *    <p k1, q k2 | r k3, s k4> = sum_L A[k1][k3][L][p][r] * A[k2][k4][L][q][s]
+ *    for k4 = k1 + k2 - k3 (zero otherwise) and A[k3][k1][L][r][p] = conj(A[k1][k3][L][p][r]).
+ *  - Amplitudes: t1[k][i][a] (k_i = k_a = k); t2[ki][kj][ka][i][j][a][b] with
+ *    kb = ki + kj - ka, antisymmetric under (i,ki)<->(j,kj) and (a,ka)<->(b,kb).
+ *  - EOM vectors of total momentum K use full antisymmetric storage:
+ *      IP: [r1[i] (k_i = K), r2[ki][kj][i][j][a] (ka = ki + kj - K)]
+ *      EA: [r1[a] (k_a = K), r2[ki][ka][i][a][b] (kb = K + ki - ka)]
+ *    so nIP = nocc + nk^2 nocc^2 nvir and nEA = nvir + nk^2 nocc nvir^2 complex
+ *    entries; norms count each unordered pair once (|r1|^2 + |r2|^2 / 2).
+ *
+ * Errors: every call returns a status code; no C++ exception crosses the ABI.
+ * cc_gf_last_error() gives a message for the last non-OK status of a context
+ * (or, with a NULL context, of the last failed cc_gf_init in this thread).
+ * A context is not thread-safe; calls on one context must not overlap.
+ */
+#ifndef CCGF_H
+#define CCGF_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ccgf_ctx ccgf_ctx;
+
+enum {
+  CCGF_OK = 0,
+  CCGF_EINVAL = -1,       /* bad argument, shape or symmetry */
+  CCGF_ENOMEM = -2,       /* device allocation failed */
+  CCGF_EDEVICE = -3,      /* HIP runtime error */
+  CCGF_ENOCONV = -4,      /* some solve missed the tolerance; G still written */
+  CCGF_ESTATE = -5,       /* call out of order (e.g. NULL context) */
+  CCGF_EUNSUPPORTED = -6  /* option not available in this build */
+};
+
+enum { CCGF_HOST = 0, CCGF_DEVICE = 1 };
+enum { CCGF_PART_IP = 1, CCGF_PART_EA = 2, CCGF_PART_BOTH = 3 };
+enum { CCGF_PLAIN_F64 = 0 };
+
+/* One periodic system.  All pointers are borrowed for the duration of
+ * cc_gf_init only (the library copies what it needs to the device); they are
+ * host pointers when mem_space == CCGF_HOST and device pointers when
+ * mem_space == CCGF_DEVICE. */
+typedef struct {
+  int kmesh[3];              /* Gamma-centred mesh, each >= 1 */
+  int nocc, nvir;            /* spin orbitals per cell, both >= 1 */
+  const double *eps;         /* real [nk][nmo]: Fock diagonal (f_ov = 0) */
+  const double *foo;         /* optional complex [nk][nocc][nocc]; NULL -> diag(eps) */
+  const double *fvv;         /* optional complex [nk][nvir][nvir]; NULL -> diag(eps) */
+  int naux;                  /* factor rank per k-pair, >= 1 */
+  const double *eri_factor;  /* complex [nk][nk][naux][nmo][nmo] (see header comment) */
+  const double *t1;          /* complex [nk][nocc][nvir] */
+  const double *t2;          /* complex [nk][nk][nk][nocc][nocc][nvir][nvir] */
+  int mem_space;             /* CCGF_HOST or CCGF_DEVICE */
+} ccgf_system;
+
+typedef struct {
+  int precision;    /* CCGF_PLAIN_F64 (the only value in this build) */
+  int restart_m;    /* GMRES restart length (Krylov vectors per cycle), 1..200; 0 -> 30 */
+  int maxiter;      /* total GMRES iterations per solve; 0 -> 2000 */
+  double tol;       /* relative residual ||b - A x|| / ||b|| in the unique-pair norm; 0 -> 1e-10 */
+  int max_batch;    /* right-hand sides solved together (frequencies x orbitals); 0 -> 64 */
+  void *hip_stream; /* hipStream_t to run on; NULL -> the default stream */
+  int timing;       /* nonzero: time the sigma kernels with HIP events (adds a wait per product) */
+  double precond_eta; /* damping of the diagonal preconditioner D = w -/+ diag(M) +/- i max(eta, precond_eta);
+                         0 -> eta.  Changes only the iteration count, not the solution. */
+} ccgf_options;
+
+typedef struct {
+  long long n_solves;        /* shifted systems solved */
+  long long n_iterations;    /* GMRES iterations summed over solves */
+  long long n_sigma;         /* sigma products applied (one per RHS per product) */
+  int max_iterations;        /* largest iteration count of a single solve */
+  int n_unconverged;         /* solves that missed tol */
+  double max_rel_residual;   /* largest final true relative residual */
+  double seconds;            /* wall time of the call */
+  /* filled only when options.timing is set (HIP events on the context stream): */
+  double big_ms;             /* time in the dominant sigma GEMM (EA: W_abcd term; IP: W_mnij term) */
+  long long big_launches;    /* launches of that GEMM */
+  double big_flops;          /* its algorithmic flops (8 per complex multiply-add) */
+  double sigma_ms;           /* time in whole sigma products */
+  long long sigma_launches;  /* sigma products (each over a batch of vectors) */
+} ccgf_stats;
+
+/* Validates the system (shapes, t2 antisymmetry, factor Hermiticity, each to
+ * 1e-10 relative), uploads it on the given stream and builds the
+ * similarity-transformed Hamiltonian blocks on the device in FP64.
+ * Returns CCGF_EINVAL for invalid input, CCGF_ENOMEM if the device is full.
+ * On success *out owns all device memory until cc_gf_free. */
+int cc_gf_init(const ccgf_system *sys, const ccgf_options *opt, ccgf_ctx **out);
+
+/* Diagonal G_pp(K, w) for every (kidx[a], orbs[b], omega[c]) -- Eqs. 6, 7, 9.
+ *  kidx:  nkq host ints in [0, nk);  orbs: norb host ints in [0, nmo);
+ *  omega: nw host doubles (Hartree);  eta > 0 (Hartree);  parts: CCGF_PART_*.
+ *  G, Gplus_opt, Gminus_opt: host complex [nkq][norb][nw], caller-allocated
+ *  (the optional ones may be NULL).  G receives G+ + G- of the requested parts.
+ *  st_opt may be NULL.  Returns CCGF_ENOCONV if any solve missed tol (G is
+ *  still written). */
+int cc_gf_solve(ccgf_ctx *ctx, int nkq, const int *kidx, int norb, const int *orbs,
+                int nw, const double *omega, double eta, int parts,
+                double *G, double *Gplus_opt, double *Gminus_opt, ccgf_stats *st_opt);
+
+/* Length (complex entries) of an EOM vector of the given part (CCGF_PART_IP or
+ * CCGF_PART_EA) in the full antisymmetric storage described above. */
+int cc_gf_vector_size(const ccgf_ctx *ctx, int part, long long *n);
+
+/* sigma = M(K) r for nvec vectors: the EOM-IP or EOM-EA matrix (connected
+ * commutator of Hbar, the hot product inside every solve of Eq. 6).
+ * x, y: DEVICE complex [nvec][n] (n from cc_gf_vector_size), not aliased;
+ * x must be antisymmetric in its pair indices.  Runs on the context stream
+ * and returns after the product is complete. */
+int cc_gf_sigma(ccgf_ctx *ctx, int part, int K, int nvec, const double *x, double *y);
+
+/* Right-hand side b (abar_p|Phi> for IP, abar+_p|Phi> for EA) and left vector
+ * e (<Phi|(1+Lambda) abar+_p for IP, <Phi|(1+Lambda) abar_p for EA) of orbital
+ * p at momentum K (Eqs. 6-7).  b, e: DEVICE complex [n]; either may be NULL. */
+int cc_gf_vectors(ccgf_ctx *ctx, int part, int K, int p, double *b, double *e);
+
+/* Releases all device memory of the context (NULL is ignored). */
+void cc_gf_free(ccgf_ctx *ctx);
+
+/* Message for the last non-OK status (never NULL). */
+const char *cc_gf_last_error(const ccgf_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CCGF_H */

@@ -1,0 +1,206 @@
+"""ctypes binding of libccgf.so (argument marshalling only).
+
+Every step of the computation runs in the HIP library; this module only
+converts numpy arrays / torch tensors into the pointers and sizes that the C
+ABI in include/ccgf.h expects.  Importing it without the built library raises,
+so nothing can silently fall back to a CPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libccgf.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+HOST, DEVICE = 0, 1
+PART_IP, PART_EA, PART_BOTH = 1, 2, 3
+PLAIN_F64 = 0
+
+EXPORTS = ("cc_gf_init", "cc_gf_solve", "cc_gf_vector_size", "cc_gf_sigma", "cc_gf_vectors",
+           "cc_gf_free", "cc_gf_last_error")
+
+
+class System(ctypes.Structure):
+    _fields_ = [("kmesh", ctypes.c_int * 3), ("nocc", ctypes.c_int), ("nvir", ctypes.c_int),
+                ("eps", ctypes.c_void_p), ("foo", ctypes.c_void_p), ("fvv", ctypes.c_void_p),
+                ("naux", ctypes.c_int), ("eri_factor", ctypes.c_void_p), ("t1", ctypes.c_void_p),
+                ("t2", ctypes.c_void_p), ("mem_space", ctypes.c_int)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("restart_m", ctypes.c_int), ("maxiter", ctypes.c_int),
+                ("tol", ctypes.c_double), ("max_batch", ctypes.c_int), ("hip_stream", ctypes.c_void_p),
+                ("timing", ctypes.c_int), ("precond_eta", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_solves", ctypes.c_longlong), ("n_iterations", ctypes.c_longlong),
+                ("n_sigma", ctypes.c_longlong), ("max_iterations", ctypes.c_int),
+                ("n_unconverged", ctypes.c_int), ("max_rel_residual", ctypes.c_double),
+                ("seconds", ctypes.c_double),
+                ("big_ms", ctypes.c_double), ("big_launches", ctypes.c_longlong),
+                ("big_flops", ctypes.c_double), ("sigma_ms", ctypes.c_double),
+                ("sigma_launches", ctypes.c_longlong)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class CCGFError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ccgf error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2208_07478_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, ip, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+    lib.cc_gf_init.argtypes = [ctypes.POINTER(System), ctypes.POINTER(Options), ctypes.POINTER(vp)]
+    lib.cc_gf_init.restype = ctypes.c_int
+    lib.cc_gf_solve.argtypes = [vp, ctypes.c_int, ip, ctypes.c_int, ip, ctypes.c_int, dp, ctypes.c_double,
+                                ctypes.c_int, vp, vp, vp, ctypes.POINTER(Stats)]
+    lib.cc_gf_solve.restype = ctypes.c_int
+    lib.cc_gf_vector_size.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong)]
+    lib.cc_gf_vector_size.restype = ctypes.c_int
+    lib.cc_gf_sigma.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp]
+    lib.cc_gf_sigma.restype = ctypes.c_int
+    lib.cc_gf_vectors.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp]
+    lib.cc_gf_vectors.restype = ctypes.c_int
+    lib.cc_gf_free.argtypes = [vp]
+    lib.cc_gf_free.restype = None
+    lib.cc_gf_last_error.argtypes = [vp]
+    lib.cc_gf_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _c128(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+
+
+def _part(p):
+    if isinstance(p, str):
+        return {"ip": PART_IP, "ea": PART_EA, "both": PART_BOTH}[p.lower()]
+    return int(p)
+
+
+class Context:
+    """One system on the GPU (wraps cc_gf_init / cc_gf_free)."""
+
+    def __init__(self, system, *, tol=1e-10, restart_m=30, maxiter=2000, max_batch=64, stream=None,
+                 timing=False, foo=None, fvv=None, precond_eta=0.0):
+        lib = load()
+        import torch  # device memory and streams only
+        self._torch = torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        s = system
+        self._keep = [np.ascontiguousarray(np.asarray(s.eps, dtype=np.float64)), _c128(s.eri_factor),
+                      _c128(s.t1), _c128(s.t2)]
+        foo_a = None if foo is None else _c128(foo)
+        fvv_a = None if fvv is None else _c128(fvv)
+        self._keep += [foo_a, fvv_a]
+        cs = System()
+        cs.kmesh = (ctypes.c_int * 3)(*[int(x) for x in s.kmesh])
+        cs.nocc, cs.nvir = int(s.nocc), int(s.nvir)
+        cs.eps = self._keep[0].ctypes.data
+        cs.foo = None if foo_a is None else foo_a.ctypes.data
+        cs.fvv = None if fvv_a is None else fvv_a.ctypes.data
+        cs.naux = int(self._keep[1].shape[2])
+        cs.eri_factor = self._keep[1].ctypes.data
+        cs.t1 = self._keep[2].ctypes.data
+        cs.t2 = self._keep[3].ctypes.data
+        cs.mem_space = HOST
+        opt = Options(PLAIN_F64, int(restart_m), int(maxiter), float(tol), int(max_batch),
+                      ctypes.c_void_p(stream.cuda_stream), 1 if timing else 0, float(precond_eta))
+        self._opt = opt
+        h = ctypes.c_void_p()
+        rc = lib.cc_gf_init(ctypes.byref(cs), ctypes.byref(opt), ctypes.byref(h))
+        if rc != OK:
+            raise CCGFError(rc, lib.cc_gf_last_error(None).decode())
+        self._h = h
+        self._keep = None
+        self.nk = int(np.prod(s.kmesh))
+        self.nocc, self.nvir = int(s.nocc), int(s.nvir)
+        self.nmo = self.nocc + self.nvir
+
+    def _check(self, rc, allow=()):
+        if rc != OK and rc not in allow:
+            raise CCGFError(rc, load().cc_gf_last_error(self._h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().cc_gf_free(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def vector_size(self, part) -> int:
+        n = ctypes.c_longlong()
+        self._check(load().cc_gf_vector_size(self._h, _part(part), ctypes.byref(n)))
+        return int(n.value)
+
+    def sigma(self, part, K: int, x):
+        """y = M(K) x for a [nvec, n] complex128 CUDA tensor."""
+        torch = self._torch
+        assert x.is_cuda and x.dtype == torch.complex128 and x.is_contiguous()
+        n = self.vector_size(part)
+        xx = x.reshape(-1, n)
+        y = torch.empty_like(xx)
+        self._check(load().cc_gf_sigma(self._h, _part(part), int(K), int(xx.shape[0]), xx.data_ptr(),
+                                       y.data_ptr()))
+        return y.reshape(x.shape)
+
+    def vectors(self, part, K: int, p: int):
+        """(b, e) CUDA tensors of orbital p at momentum K."""
+        torch = self._torch
+        n = self.vector_size(part)
+        b = torch.empty(n, dtype=torch.complex128, device="cuda")
+        e = torch.empty(n, dtype=torch.complex128, device="cuda")
+        self._check(load().cc_gf_vectors(self._h, _part(part), int(K), int(p), b.data_ptr(), e.data_ptr()))
+        return b, e
+
+    def solve(self, kidx: Sequence[int], orbs: Sequence[int], omega, eta: float, parts="both",
+              allow_noconv=False):
+        """G, G+, G-, stats for the diagonal G_pp(K, w); arrays [nkq][norb][nw]."""
+        kidx = np.ascontiguousarray(np.asarray(kidx, dtype=np.int32))
+        orbs = np.ascontiguousarray(np.asarray(orbs, dtype=np.int32))
+        om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
+        shape = (len(kidx), len(orbs), len(om))
+        G = np.zeros(shape, dtype=np.complex128)
+        Gp = np.zeros(shape, dtype=np.complex128)
+        Gm = np.zeros(shape, dtype=np.complex128)
+        st = Stats()
+        ip = ctypes.POINTER(ctypes.c_int)
+        dp = ctypes.POINTER(ctypes.c_double)
+        rc = load().cc_gf_solve(self._h, len(kidx), kidx.ctypes.data_as(ip), len(orbs), orbs.ctypes.data_as(ip),
+                                len(om), om.ctypes.data_as(dp), float(eta), _part(parts), G.ctypes.data,
+                                Gp.ctypes.data, Gm.ctypes.data, ctypes.byref(st))
+        self._check(rc, allow=(ENOCONV,) if allow_noconv else ())
+        return G, Gp, Gm, st.as_dict()

@@ -1,0 +1,317 @@
+// C ABI of the CCGF library: argument checking, upload, context life cycle and
+// the frequency / orbital / momentum loops of cc_gf_solve (Eqs. 6, 7, 9).
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ccgf_internal.h"
+
+static thread_local std::string g_init_err = "no error";
+
+int set_err(ccgf_ctx *c, int code, const std::string &msg) {
+  if (c) c->err = msg;
+  else g_init_err = msg;
+  return code;
+}
+
+int hip_check(ccgf_ctx *c, hipError_t e, const char *what) {
+  if (e == hipSuccess) return CCGF_OK;
+  return set_err(c, CCGF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void *dev_alloc(ccgf_ctx *c, size_t bytes) {
+  void *p = nullptr;
+  if (hipMalloc(&p, bytes < 16 ? 16 : bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  c->allocs.push_back(p);
+  return p;
+}
+
+static int kflat(const int m[3], int a, int b, int c3) {
+  a = ((a % m[0]) + m[0]) % m[0];
+  b = ((b % m[1]) + m[1]) % m[1];
+  c3 = ((c3 % m[2]) + m[2]) % m[2];
+  return (a * m[1] + b) * m[2] + c3;
+}
+
+static void free_all(ccgf_ctx *c) {
+  for (void *p : c->allocs)
+    if (p) hipFree(p);
+  c->allocs.clear();
+}
+
+// Host-side checks of the symmetry the formulation relies on (host inputs only).
+static int validate_host(ccgf_ctx *c, const ccgf_system *s) {
+  const int nk = c->nk, no = c->no, nv = c->nv, nmo = c->nmo, naux = c->naux;
+  const double *t2 = s->t2;
+  double amax = 0, dev = 0;
+  auto T2 = [&](int ki, int kj, int ka, int i, int j, int a, int b, int comp) {
+    size_t off = ((((((size_t)ki * nk + kj) * nk + ka) * no + i) * no + j) * nv + a) * nv + b;
+    return t2[2 * off + comp];
+  };
+  for (int ki = 0; ki < nk; ++ki)
+    for (int kj = 0; kj < nk; ++kj)
+      for (int ka = 0; ka < nk; ++ka) {
+        int kb = c->kc3_h[((size_t)ki * nk + kj) * nk + ka];
+        for (int i = 0; i < no; ++i)
+          for (int j = 0; j < no; ++j)
+            for (int a = 0; a < nv; ++a)
+              for (int b = 0; b < nv; ++b)
+                for (int q = 0; q < 2; ++q) {
+                  double x = T2(ki, kj, ka, i, j, a, b, q);
+                  amax = std::fmax(amax, std::fabs(x));
+                  dev = std::fmax(dev, std::fabs(x + T2(kj, ki, ka, j, i, a, b, q)));
+                  dev = std::fmax(dev, std::fabs(x + T2(ki, kj, kb, i, j, b, a, q)));
+                }
+      }
+  if (dev > 1e-10 * std::fmax(amax, 1e-300) && dev > 0)
+    return set_err(c, CCGF_EINVAL, "t2 is not antisymmetric under i<->j / a<->b (max deviation " +
+                                       std::to_string(dev) + ")");
+  const double *A = s->eri_factor;
+  amax = 0;
+  dev = 0;
+  for (int k1 = 0; k1 < nk; ++k1)
+    for (int k3 = 0; k3 < nk; ++k3)
+      for (int L = 0; L < naux; ++L)
+        for (int p = 0; p < nmo; ++p)
+          for (int r = 0; r < nmo; ++r) {
+            size_t o1 = ((((size_t)k1 * nk + k3) * naux + L) * nmo + p) * nmo + r;
+            size_t o2 = ((((size_t)k3 * nk + k1) * naux + L) * nmo + r) * nmo + p;
+            amax = std::fmax(amax, std::fabs(A[2 * o1]) + std::fabs(A[2 * o1 + 1]));
+            dev = std::fmax(dev, std::fabs(A[2 * o1] - A[2 * o2]) + std::fabs(A[2 * o1 + 1] + A[2 * o2 + 1]));
+          }
+  if (dev > 1e-10 * std::fmax(amax, 1e-300) && dev > 0)
+    return set_err(c, CCGF_EINVAL, "eri_factor violates A[k3][k1][L][r][p] = conj(A[k1][k3][L][p][r])");
+  return CCGF_OK;
+}
+
+extern "C" int cc_gf_init(const ccgf_system *s, const ccgf_options *opt, ccgf_ctx **out) {
+  if (!out) return set_err(nullptr, CCGF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!s) return set_err(nullptr, CCGF_EINVAL, "system is NULL");
+  for (int d = 0; d < 3; ++d)
+    if (s->kmesh[d] < 1) return set_err(nullptr, CCGF_EINVAL, "kmesh entries must be >= 1");
+  if (s->nocc < 1 || s->nvir < 1) return set_err(nullptr, CCGF_EINVAL, "nocc and nvir must be >= 1");
+  if (s->naux < 1) return set_err(nullptr, CCGF_EINVAL, "naux must be >= 1");
+  if (!s->eps || !s->eri_factor || !s->t1 || !s->t2)
+    return set_err(nullptr, CCGF_EINVAL, "eps, eri_factor, t1 and t2 are required");
+  if (s->mem_space != CCGF_HOST && s->mem_space != CCGF_DEVICE)
+    return set_err(nullptr, CCGF_EINVAL, "mem_space must be CCGF_HOST or CCGF_DEVICE");
+  ccgf_options o{};
+  if (opt) o = *opt;
+  if (o.precision != CCGF_PLAIN_F64) return set_err(nullptr, CCGF_EUNSUPPORTED, "only CCGF_PLAIN_F64 is available");
+  if (o.restart_m == 0) o.restart_m = 30;
+  if (o.maxiter == 0) o.maxiter = 2000;
+  if (o.tol == 0) o.tol = 1e-10;
+  if (o.max_batch == 0) o.max_batch = 64;
+  if (o.restart_m < 1 || o.restart_m > 200 || o.maxiter < 1 || o.tol < 0 || o.max_batch < 1)
+    return set_err(nullptr, CCGF_EINVAL, "options out of range");
+
+  ccgf_ctx *c = new ccgf_ctx();
+  c->opt = o;
+  c->stream = (hipStream_t)o.hip_stream;
+  for (int d = 0; d < 3; ++d) c->m[d] = s->kmesh[d];
+  c->nk = s->kmesh[0] * s->kmesh[1] * s->kmesh[2];
+  c->no = s->nocc;
+  c->nv = s->nvir;
+  c->nmo = s->nocc + s->nvir;
+  c->naux = s->naux;
+  const int nk = c->nk, no = c->no, nv = c->nv, nmo = c->nmo;
+  // momentum table k1 + k2 - k3
+  c->kc3_h.resize((size_t)nk * nk * nk);
+  auto dec = [&](int k, int v[3]) {
+    v[2] = k % c->m[2];
+    v[1] = (k / c->m[2]) % c->m[1];
+    v[0] = k / (c->m[1] * c->m[2]);
+  };
+  for (int a = 0; a < nk; ++a)
+    for (int b = 0; b < nk; ++b)
+      for (int d = 0; d < nk; ++d) {
+        int va[3], vb[3], vd[3];
+        dec(a, va);
+        dec(b, vb);
+        dec(d, vd);
+        c->kc3_h[((size_t)a * nk + b) * nk + d] =
+            kflat(c->m, va[0] + vb[0] - vd[0], va[1] + vb[1] - vd[1], va[2] + vb[2] - vd[2]);
+      }
+  if (s->mem_space == CCGF_HOST) {
+    int rc = validate_host(c, s);
+    if (rc != CCGF_OK) {
+      g_init_err = c->err;
+      delete c;
+      return rc;
+    }
+  }
+  const hipMemcpyKind kind = s->mem_space == CCGF_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  auto upload = [&](const void *src, size_t bytes) -> cplx * {
+    cplx *d = (cplx *)dev_alloc(c, bytes);
+    if (!d) return nullptr;
+    if (hipMemcpyAsync(d, src, bytes, kind, c->stream) != hipSuccess) return nullptr;
+    return d;
+  };
+  size_t n_t1 = (size_t)nk * no * nv, n_t2 = (size_t)nk * nk * nk * no * no * nv * nv;
+  size_t n_fac = (size_t)nk * nk * c->naux * nmo * nmo;
+  c->kc3 = (int *)dev_alloc(c, sizeof(int) * c->kc3_h.size());
+  if (c->kc3) hipMemcpy(c->kc3, c->kc3_h.data(), sizeof(int) * c->kc3_h.size(), hipMemcpyHostToDevice);
+  c->t1 = upload(s->t1, sizeof(cplx) * n_t1);
+  c->t2 = upload(s->t2, sizeof(cplx) * n_t2);
+  c->fac = upload(s->eri_factor, sizeof(cplx) * n_fac);
+  // Fock blocks: given, or diag(eps)
+  std::vector<cplx> hfoo((size_t)nk * no * no, mkc(0, 0)), hfvv((size_t)nk * nv * nv, mkc(0, 0));
+  std::vector<double> heps((size_t)nk * nmo);
+  if (s->mem_space == CCGF_HOST) std::memcpy(heps.data(), s->eps, sizeof(double) * heps.size());
+  else hipMemcpy(heps.data(), s->eps, sizeof(double) * heps.size(), hipMemcpyDeviceToHost);
+  for (int k = 0; k < nk; ++k) {
+    for (int i = 0; i < no; ++i) hfoo[((size_t)k * no + i) * no + i] = mkc(heps[(size_t)k * nmo + i], 0);
+    for (int a = 0; a < nv; ++a) hfvv[((size_t)k * nv + a) * nv + a] = mkc(heps[(size_t)k * nmo + no + a], 0);
+  }
+  c->foo = (cplx *)dev_alloc(c, sizeof(cplx) * hfoo.size());
+  c->fvv = (cplx *)dev_alloc(c, sizeof(cplx) * hfvv.size());
+  if (c->foo && c->fvv) {
+    if (s->foo) hipMemcpy(c->foo, s->foo, sizeof(cplx) * hfoo.size(), kind);
+    else hipMemcpy(c->foo, hfoo.data(), sizeof(cplx) * hfoo.size(), hipMemcpyHostToDevice);
+    if (s->fvv) hipMemcpy(c->fvv, s->fvv, sizeof(cplx) * hfvv.size(), kind);
+    else hipMemcpy(c->fvv, hfvv.data(), sizeof(cplx) * hfvv.size(), hipMemcpyHostToDevice);
+  }
+  if (!c->kc3 || !c->t1 || !c->t2 || !c->fac || !c->foo || !c->fvv) {
+    g_init_err = "device allocation or upload failed";
+    free_all(c);
+    delete c;
+    return CCGF_ENOMEM;
+  }
+  int rc = build_hbar(c);
+  if (rc == CCGF_OK) rc = hip_check(c, hipStreamSynchronize(c->stream), "cc_gf_init");
+  if (rc != CCGF_OK) {
+    g_init_err = c->err.empty() ? "building Hbar failed (out of device memory?)" : c->err;
+    free_all(c);
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return CCGF_OK;
+}
+
+extern "C" int cc_gf_vector_size(const ccgf_ctx *c, int part, long long *n) {
+  if (!c) return CCGF_ESTATE;
+  if (!n || (part != CCGF_PART_IP && part != CCGF_PART_EA)) return CCGF_EINVAL;
+  *n = vec_len(c, part);
+  return CCGF_OK;
+}
+
+extern "C" int cc_gf_sigma(ccgf_ctx *c, int part, int K, int nvec, const double *x, double *y) {
+  if (!c) return CCGF_ESTATE;
+  if (part != CCGF_PART_IP && part != CCGF_PART_EA) return set_err(c, CCGF_EINVAL, "part must be IP or EA");
+  if (K < 0 || K >= c->nk) return set_err(c, CCGF_EINVAL, "K out of range");
+  if (nvec < 0 || (nvec > 0 && (!x || !y))) return set_err(c, CCGF_EINVAL, "bad vectors");
+  if (x == y && nvec > 0) return set_err(c, CCGF_EINVAL, "x and y must not alias");
+  int rc = sigma_apply(c, part, K, nvec, (const cplx *)x, (cplx *)y);
+  if (rc != CCGF_OK) return rc;
+  return hip_check(c, hipStreamSynchronize(c->stream), "cc_gf_sigma");
+}
+
+extern "C" int cc_gf_vectors(ccgf_ctx *c, int part, int K, int p, double *b, double *e) {
+  if (!c) return CCGF_ESTATE;
+  if (part != CCGF_PART_IP && part != CCGF_PART_EA) return set_err(c, CCGF_EINVAL, "part must be IP or EA");
+  if (K < 0 || K >= c->nk || p < 0 || p >= c->nmo) return set_err(c, CCGF_EINVAL, "K or p out of range");
+  int rc = build_vectors(c, part, K, p, (cplx *)b, (cplx *)e);
+  if (rc != CCGF_OK) return rc;
+  return hip_check(c, hipStreamSynchronize(c->stream), "cc_gf_vectors");
+}
+
+extern "C" int cc_gf_solve(ccgf_ctx *c, int nkq, const int *kidx, int norb, const int *orbs, int nw,
+                           const double *omega, double eta, int parts, double *G, double *Gp, double *Gm,
+                           ccgf_stats *st) {
+  if (!c) return CCGF_ESTATE;
+  auto t0 = std::chrono::steady_clock::now();
+  if (nkq < 0 || norb < 0 || nw < 0) return set_err(c, CCGF_EINVAL, "negative counts");
+  if ((nkq && !kidx) || (norb && !orbs) || (nw && !omega) || !G)
+    return set_err(c, CCGF_EINVAL, "NULL array argument");
+  if (!(eta > 0)) return set_err(c, CCGF_EINVAL, "eta must be > 0");
+  if (parts < 1 || parts > 3) return set_err(c, CCGF_EINVAL, "parts must be CCGF_PART_IP, _EA or _BOTH");
+  for (int a = 0; a < nkq; ++a)
+    if (kidx[a] < 0 || kidx[a] >= c->nk) return set_err(c, CCGF_EINVAL, "kidx out of range");
+  for (int b = 0; b < norb; ++b)
+    if (orbs[b] < 0 || orbs[b] >= c->nmo) return set_err(c, CCGF_EINVAL, "orbital index out of range");
+  for (int w = 0; w < nw; ++w)
+    if (!std::isfinite(omega[w])) return set_err(c, CCGF_EINVAL, "omega must be finite");
+  ccgf_stats local{};
+  ccgf_stats *S = st ? st : &local;
+  std::memset(S, 0, sizeof(*S));
+  c->t_big_ms = c->t_big_flops = c->t_sigma_ms = 0;
+  c->t_big_launches = c->t_sigma_launches = 0;
+  const size_t ntot = (size_t)nkq * norb * nw;
+  std::vector<cplx> Gsum(ntot, mkc(0, 0)), Gplus(ntot, mkc(0, 0)), Gminus(ntot, mkc(0, 0));
+  int status = CCGF_OK;
+  const int nrhs = norb * nw;
+  std::vector<int> rhs_orb(nrhs);
+  std::vector<double> rhs_w(nrhs);
+  for (int b = 0; b < norb; ++b)
+    for (int w = 0; w < nw; ++w) {
+      rhs_orb[b * nw + w] = b;
+      rhs_w[b * nw + w] = omega[w];
+    }
+  std::vector<cplx> res(nrhs);
+  for (int part : {CCGF_PART_IP, CCGF_PART_EA}) {
+    if (!(parts & part) || nrhs == 0) continue;
+    const long long n = vec_len(c, part);
+    cplx *Bv = (cplx *)nullptr, *Ev = (cplx *)nullptr;
+    if (hipMalloc(&Bv, sizeof(cplx) * (size_t)norb * n) != hipSuccess ||
+        hipMalloc(&Ev, sizeof(cplx) * (size_t)norb * n) != hipSuccess) {
+      if (Bv) hipFree(Bv);
+      (void)hipGetLastError();
+      return set_err(c, CCGF_ENOMEM, "no device memory for right-hand sides");
+    }
+    for (int a = 0; a < nkq && status != CCGF_EDEVICE && status != CCGF_ENOMEM; ++a) {
+      const int K = kidx[a];
+      for (int b = 0; b < norb; ++b) {
+        int rc = build_vectors(c, part, K, orbs[b], Bv + (size_t)b * n, Ev + (size_t)b * n);
+        if (rc != CCGF_OK) status = rc;
+      }
+      if (status != CCGF_OK && status != CCGF_ENOCONV) break;
+      int rc = solve_batched(c, part, K, nrhs, rhs_orb.data(), rhs_w.data(), eta, Bv, Ev, res.data(), S);
+      if (rc != CCGF_OK) {
+        if (rc == CCGF_ENOCONV) set_err(c, rc, "some shifted systems did not reach tol");
+        status = (status == CCGF_OK || rc != CCGF_ENOCONV) ? rc : status;
+        if (rc != CCGF_ENOCONV) break;
+      }
+      for (int r = 0; r < nrhs; ++r) {
+        size_t o = ((size_t)a * norb + rhs_orb[r]) * nw + (r % nw);
+        Gsum[o] = cadd(Gsum[o], res[r]);
+        if (part == CCGF_PART_EA) Gplus[o] = res[r];
+        else Gminus[o] = res[r];
+      }
+    }
+    hipFree(Bv);
+    hipFree(Ev);
+    if (status != CCGF_OK && status != CCGF_ENOCONV) break;
+  }
+  std::memcpy(G, Gsum.data(), sizeof(cplx) * ntot);
+  if (Gp) std::memcpy(Gp, Gplus.data(), sizeof(cplx) * ntot);
+  if (Gm) std::memcpy(Gm, Gminus.data(), sizeof(cplx) * ntot);
+  S->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  S->big_ms = c->t_big_ms;
+  S->big_launches = c->t_big_launches;
+  S->big_flops = c->t_big_flops;
+  S->sigma_ms = c->t_sigma_ms;
+  S->sigma_launches = c->t_sigma_launches;
+  return status;
+}
+
+extern "C" void cc_gf_free(ccgf_ctx *c) {
+  if (!c) return;
+  hipStreamSynchronize(c->stream);
+  for (int q = 0; q < 4; ++q)
+    if (c->ev[q]) hipEventDestroy(c->ev[q]);
+  free_all(c);
+  delete c;
+}
+
+extern "C" const char *cc_gf_last_error(const ccgf_ctx *c) {
+  if (!c) return g_init_err.c_str();
+  return c->err.empty() ? "no error" : c->err.c_str();
+}

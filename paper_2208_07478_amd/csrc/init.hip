@@ -1,0 +1,484 @@
+// Device construction of the EOM-CCSD Hbar blocks and of the b / e vectors.
+//
+// All blocks are built once per system in FP64 by element-wise kernels (one
+// thread per output element, explicit momentum loops).  The blocks are the
+// spin-orbital CCSD similarity-transformed Hamiltonian elements (one-body F,
+// two-body W and the W_oovv * T2 three-body pieces) that make up the
+// connected EOM-IP/EA-CCSD matrix; Lambda = T^dagger enters the left vectors
+// (approximation stated after Eq. 10).  The right-hand sides b and left
+// vectors e follow from abar = exp(-T) a exp(T) = a - [T, a] (Eqs. 5-7).
+#include "ccgf_internal.h"
+
+namespace {
+
+template <class F>
+__global__ void k_foreach(size_t n, F f) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) f(i);
+}
+
+template <class F>
+void foreach_(hipStream_t s, size_t n, F f) {
+  if (n == 0) return;
+  size_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_foreach<F>, dim3((unsigned)blocks), dim3(256), 0, s, n, f);
+}
+
+struct I7 {
+  int k1, k2, k3, a, b, c, d;
+};
+__device__ inline I7 dec(size_t i, int nk, int n1, int n2, int n3, int n4) {
+  I7 r;
+  r.d = (int)(i % n4); i /= n4;
+  r.c = (int)(i % n3); i /= n3;
+  r.b = (int)(i % n2); i /= n2;
+  r.a = (int)(i % n1); i /= n1;
+  r.k3 = (int)(i % nk); i /= nk;
+  r.k2 = (int)(i % nk); i /= nk;
+  r.k1 = (int)i;
+  return r;
+}
+
+// Antisymmetrised <p k1, q k2 || r k3, s k4> from the factor (global orbital indices).
+struct Eri {
+  const cplx *A;
+  int nk, naux, nmo;
+  KTab kt;
+  __device__ inline cplx fac(int ka, int kb, int L, int p, int r) const {
+    return A[((((size_t)ka * nk + kb) * naux + L) * nmo + p) * nmo + r];
+  }
+  __device__ inline cplx operator()(int k1, int k2, int k3, int p, int q, int r, int s) const {
+    int k4 = kt.c3(k1, k2, k3);
+    cplx acc = mkc(0, 0);
+    for (int L = 0; L < naux; ++L) {
+      cfma(acc, fac(k1, k3, L, p, r), fac(k2, k4, L, q, s));
+      cplx x = fac(k1, k4, L, p, s);
+      cplx y = fac(k2, k3, L, q, r);
+      acc.x -= x.x * y.x - x.y * y.y;
+      acc.y -= x.x * y.y + x.y * y.x;
+    }
+    return acc;
+  }
+};
+
+}  // namespace
+
+long long vec_len(const ccgf_ctx *c, int part) {
+  long long nk = c->nk, no = c->no, nv = c->nv;
+  return part == CCGF_PART_IP ? no + nk * nk * no * no * nv : nv + nk * nk * no * nv * nv;
+}
+
+static T4 make_t4(ccgf_ctx *c, int n1, int n2, int n3, int n4, bool alloc = true) {
+  T4 t{nullptr, c->nk, n1, n2, n3, n4};
+  if (alloc) t.p = (cplx *)dev_alloc(c, t.size() * sizeof(cplx));
+  return t;
+}
+
+int build_hbar(ccgf_ctx *c) {
+  const int nk = c->nk, no = c->no, nv = c->nv, nmo = c->nmo;
+  hipStream_t s = c->stream;
+  KTab kt{nk, c->kc3};
+  Eri eri{c->fac, nk, c->naux, nmo, kt};
+
+  // ---- bare antisymmetrised integral classes (o = occupied, v = virtual)
+  auto cls = [&](const char *spec) {
+    int n[4], off[4];
+    for (int i = 0; i < 4; ++i) {
+      n[i] = spec[i] == 'o' ? no : nv;
+      off[i] = spec[i] == 'o' ? 0 : no;
+    }
+    T4 t = make_t4(c, n[0], n[1], n[2], n[3]);
+    if (!t.p) return t;
+    int o0 = off[0], o1 = off[1], o2 = off[2], o3 = off[3];
+    int n0 = n[0], n1 = n[1], n2 = n[2], n3 = n[3];
+    foreach_(s, t.size(), [=] __device__(size_t i) {
+      I7 x = dec(i, nk, n0, n1, n2, n3);
+      t.p[i] = eri(x.k1, x.k2, x.k3, x.a + o0, x.b + o1, x.c + o2, x.d + o3);
+    });
+    return t;
+  };
+  T4 Voooo = cls("oooo"), Vooov = cls("ooov"), Voovo = cls("oovo"), Voovv = cls("oovv");
+  T4 Vovoo = cls("ovoo"), Vovvo = cls("ovvo"), Vovvv = cls("ovvv"), Vvovv = cls("vovv");
+  T4 Vvvvo = cls("vvvo");
+  if (!Voooo.p || !Vooov.p || !Voovo.p || !Voovv.p || !Vovoo.p || !Vovvo.p || !Vovvv.p || !Vvovv.p ||
+      !Vvvvo.p)
+    return CCGF_ENOMEM;
+
+  T2d t1{c->t1, no, nv};
+  T4 t2{c->t2, nk, no, no, nv, nv};
+  T2d foo{c->foo, no, no}, fvv{c->fvv, nv, nv};
+
+  // tau_ij^ab = t_ij^ab + t_i^a t_j^b - t_i^b t_j^a
+  T4 tau = make_t4(c, no, no, nv, nv);
+  if (!tau.p) return CCGF_ENOMEM;
+  foreach_(s, tau.size(), [=] __device__(size_t i) {
+    I7 x = dec(i, nk, no, no, nv, nv);
+    int ki = x.k1, kj = x.k2, ka = x.k3, kb = kt.c3(ki, kj, ka);
+    cplx v = t2.p[i];
+    if (ka == ki) v = cadd(v, cmul(t1(ki, x.a, x.c), t1(kj, x.b, x.d)));
+    if (kb == ki) v = csub(v, cmul(t1(ki, x.a, x.d), t1(kj, x.b, x.c)));
+    tau.p[i] = v;
+  });
+
+  // ---- one-body blocks
+  c->Fov = (cplx *)dev_alloc(c, sizeof(cplx) * nk * no * nv);
+  c->Foo = (cplx *)dev_alloc(c, sizeof(cplx) * nk * no * no);
+  c->Fvv = (cplx *)dev_alloc(c, sizeof(cplx) * nk * nv * nv);
+  if (!c->Fov || !c->Foo || !c->Fvv) return CCGF_ENOMEM;
+  T2d Fov{c->Fov, no, nv}, Foo{c->Foo, no, no}, Fvv{c->Fvv, nv, nv};
+  foreach_(s, (size_t)nk * no * nv, [=] __device__(size_t i) {
+    int e = i % nv, m = (i / nv) % no, k = (int)(i / ((size_t)nv * no));
+    cplx acc = mkc(0, 0);
+    for (int kn = 0; kn < nk; ++kn)
+      for (int n = 0; n < no; ++n)
+        for (int f = 0; f < nv; ++f) cfma(acc, t1(kn, n, f), Voovv(k, kn, k, m, n, e, f));
+    Fov.p[i] = acc;
+  });
+  foreach_(s, (size_t)nk * no * no, [=] __device__(size_t i) {
+    int ii = i % no, m = (i / no) % no, k = (int)(i / ((size_t)no * no));
+    cplx acc = foo(k, m, ii);
+    for (int kn = 0; kn < nk; ++kn)
+      for (int n = 0; n < no; ++n)
+        for (int e = 0; e < nv; ++e) cfma(acc, t1(kn, n, e), Vooov(k, kn, k, m, n, ii, e));
+    cplx h = mkc(0, 0);
+    for (int kn = 0; kn < nk; ++kn)
+      for (int ke = 0; ke < nk; ++ke)
+        for (int n = 0; n < no; ++n)
+          for (int e = 0; e < nv; ++e)
+            for (int f = 0; f < nv; ++f) cfma(h, tau(k, kn, ke, ii, n, e, f), Voovv(k, kn, ke, m, n, e, f));
+    Foo.p[i] = cadd(acc, cscale(h, 0.5));
+  });
+  foreach_(s, (size_t)nk * nv * nv, [=] __device__(size_t i) {
+    int e = i % nv, a = (i / nv) % nv, k = (int)(i / ((size_t)nv * nv));
+    cplx acc = fvv(k, a, e);
+    for (int km = 0; km < nk; ++km)
+      for (int m = 0; m < no; ++m)
+        for (int f = 0; f < nv; ++f) cfma(acc, t1(km, m, f), Vvovv(k, km, k, a, m, e, f));
+    cplx h = mkc(0, 0);
+    for (int km = 0; km < nk; ++km)
+      for (int kn = 0; kn < nk; ++kn)
+        for (int m = 0; m < no; ++m)
+          for (int n = 0; n < no; ++n)
+            for (int f = 0; f < nv; ++f) cfma(h, tau(km, kn, k, m, n, a, f), Voovv(km, kn, k, m, n, e, f));
+    Fvv.p[i] = csub(acc, cscale(h, 0.5));
+  });
+
+  // ---- W_mnij
+  T4 Woooo = make_t4(c, no, no, no, no);
+  if (!Woooo.p) return CCGF_ENOMEM;
+  c->Woooo = Woooo.p;
+  foreach_(s, Woooo.size(), [=] __device__(size_t i) {
+    I7 x = dec(i, nk, no, no, no, no);
+    int km = x.k1, kn = x.k2, ki = x.k3, kj = kt.c3(km, kn, ki);
+    int m = x.a, n = x.b, ii = x.c, j = x.d;
+    cplx acc = Voooo.p[i];
+    for (int e = 0; e < nv; ++e) {
+      cfma(acc, t1(kj, j, e), Vooov(km, kn, ki, m, n, ii, e));
+      cplx y = cmul(t1(ki, ii, e), Vooov(km, kn, kj, m, n, j, e));
+      acc = csub(acc, y);
+    }
+    cplx h = mkc(0, 0);
+    for (int ke = 0; ke < nk; ++ke)
+      for (int e = 0; e < nv; ++e)
+        for (int f = 0; f < nv; ++f) cfma(h, tau(ki, kj, ke, ii, j, e, f), Voovv(km, kn, ke, m, n, e, f));
+    Woooo.p[i] = cadd(acc, cscale(h, 0.5));
+  });
+
+  // ---- W_abef (bare vvvv integrals formed on the fly from the factor)
+  T4 Wvvvv = make_t4(c, nv, nv, nv, nv);
+  if (!Wvvvv.p) return CCGF_ENOMEM;
+  c->Wvvvv = Wvvvv.p;
+  foreach_(s, Wvvvv.size(), [=] __device__(size_t i) {
+    I7 x = dec(i, nk, nv, nv, nv, nv);
+    int ka = x.k1, kb = x.k2, ke = x.k3;
+    int a = x.a, b = x.b, e = x.c, f = x.d;
+    cplx acc = eri(ka, kb, ke, no + a, no + b, no + e, no + f);
+    for (int m = 0; m < no; ++m) {
+      acc = csub(acc, cmul(t1(kb, m, b), Vvovv(ka, kb, ke, a, m, e, f)));
+      cfma(acc, t1(ka, m, a), Vvovv(kb, ka, ke, b, m, e, f));
+    }
+    cplx h = mkc(0, 0);
+    for (int km = 0; km < nk; ++km) {
+      int kn = kt.c3(ka, kb, km);
+      for (int m = 0; m < no; ++m)
+        for (int n = 0; n < no; ++n) cfma(h, tau(km, kn, ka, m, n, a, b), Voovv(km, kn, ke, m, n, e, f));
+    }
+    Wvvvv.p[i] = cadd(acc, cscale(h, 0.5));
+  });
+
+  // ---- Z_mbej = <mb||ej> - t_nj^bf <mn||ef>  (shared by W_mbej, W_mbij, W_abei)
+  T4 Z = make_t4(c, no, nv, nv, no);
+  if (!Z.p) return CCGF_ENOMEM;
+  foreach_(s, Z.size(), [=] __device__(size_t i) {
+    I7 x = dec(i, nk, no, nv, nv, no);
+    int km = x.k1, kb = x.k2, ke = x.k3, kj = kt.c3(km, kb, ke);
+    cplx acc = Vovvo.p[i];
+    for (int kn = 0; kn < nk; ++kn)
+      for (int n = 0; n < no; ++n)
+        for (int f = 0; f < nv; ++f)
+          acc = csub(acc, cmul(t2(kn, kj, kb, n, x.d, x.b, f), Voovv(km, kn, ke, x.a, n, x.c, f)));
+    Z.p[i] = acc;
+  });
+
+  // ---- W_mbej
+  T4 Wovvo = make_t4(c, no, nv, nv, no);
+  if (!Wovvo.p) return CCGF_ENOMEM;
+  c->Wovvo = Wovvo.p;
+  foreach_(s, Wovvo.size(), [=] __device__(size_t i) {
+    I7 x = dec(i, nk, no, nv, nv, no);
+    int km = x.k1, kb = x.k2, ke = x.k3, kj = kt.c3(km, kb, ke);
+    int m = x.a, b = x.b, e = x.c, j = x.d;
+    cplx acc = Z.p[i];
+    for (int f = 0; f < nv; ++f) cfma(acc, t1(kj, j, f), Vovvv(km, kb, ke, m, b, e, f));
+    for (int n = 0; n < no; ++n) {
+      acc = csub(acc, cmul(t1(kb, n, b), Voovo(km, kb, ke, m, n, e, j)));
+      cplx tn = t1(kb, n, b);
+      for (int f = 0; f < nv; ++f)
+        acc = csub(acc, cmul(cmul(t1(kj, j, f), tn), Voovv(km, kb, ke, m, n, e, f)));
+    }
+    Wovvo.p[i] = acc;
+  });
+
+  // ---- W_mnie, W_amef
+  T4 Wooov = make_t4(c, no, no, no, nv);
+  T4 Wvovv = make_t4(c, nv, no, nv, nv);
+  if (!Wooov.p || !Wvovv.p) return CCGF_ENOMEM;
+  c->Wooov = Wooov.p;
+  c->Wvovv = Wvovv.p;
+  foreach_(s, Wooov.size(), [=] __device__(size_t i) {
+    I7 x = dec(i, nk, no, no, no, nv);
+    cplx acc = Vooov.p[i];
+    for (int f = 0; f < nv; ++f) cfma(acc, t1(x.k3, x.c, f), Voovv(x.k1, x.k2, x.k3, x.a, x.b, f, x.d));
+    Wooov.p[i] = acc;
+  });
+  foreach_(s, Wvovv.size(), [=] __device__(size_t i) {
+    I7 x = dec(i, nk, nv, no, nv, nv);
+    cplx acc = Vvovv.p[i];
+    for (int n = 0; n < no; ++n)
+      acc = csub(acc, cmul(t1(x.k1, n, x.a), Voovv(x.k1, x.k2, x.k3, n, x.b, x.c, x.d)));
+    Wvovv.p[i] = acc;
+  });
+
+  // ---- W_mbij
+  T4 Wovoo = make_t4(c, no, nv, no, no);
+  if (!Wovoo.p) return CCGF_ENOMEM;
+  c->Wovoo = Wovoo.p;
+  foreach_(s, Wovoo.size(), [=] __device__(size_t i) {
+    I7 x = dec(i, nk, no, nv, no, no);
+    int km = x.k1, kb = x.k2, ki = x.k3, kj = kt.c3(km, kb, ki);
+    int m = x.a, b = x.b, ii = x.c, j = x.d;
+    cplx acc = Vovoo.p[i];
+    for (int e = 0; e < nv; ++e) acc = csub(acc, cmul(Fov(km, m, e), t2(ki, kj, kb, ii, j, b, e)));
+    for (int n = 0; n < no; ++n) acc = csub(acc, cmul(t1(kb, n, b), Woooo(km, kb, ki, m, n, ii, j)));
+    cplx h = mkc(0, 0);
+    for (int ke = 0; ke < nk; ++ke)
+      for (int e = 0; e < nv; ++e)
+        for (int f = 0; f < nv; ++f) cfma(h, Vovvv(km, kb, ke, m, b, e, f), tau(ki, kj, ke, ii, j, e, f));
+    acc = cadd(acc, cscale(h, 0.5));
+    for (int kn = 0; kn < nk; ++kn)
+      for (int n = 0; n < no; ++n)
+        for (int e = 0; e < nv; ++e) {
+          cfma(acc, Vooov(km, kn, ki, m, n, ii, e), t2(kj, kn, kb, j, n, b, e));
+          acc = csub(acc, cmul(Vooov(km, kn, kj, m, n, j, e), t2(ki, kn, kb, ii, n, b, e)));
+        }
+    for (int e = 0; e < nv; ++e) {
+      cfma(acc, t1(ki, ii, e), Z(km, kb, ki, m, b, e, j));
+      acc = csub(acc, cmul(t1(kj, j, e), Z(km, kb, kj, m, b, e, ii)));
+    }
+    Wovoo.p[i] = acc;
+  });
+
+  // ---- W_abei
+  T4 Wvvvo = make_t4(c, nv, nv, nv, no);
+  if (!Wvvvo.p) return CCGF_ENOMEM;
+  c->Wvvvo = Wvvvo.p;
+  foreach_(s, Wvvvo.size(), [=] __device__(size_t i) {
+    I7 x = dec(i, nk, nv, nv, nv, no);
+    int ka = x.k1, kb = x.k2, ke = x.k3, ki = kt.c3(ka, kb, ke);
+    int a = x.a, b = x.b, e = x.c, ii = x.d;
+    cplx acc = Vvvvo.p[i];
+    for (int m = 0; m < no; ++m) acc = csub(acc, cmul(Fov(ke, m, e), t2(ke, ki, ka, m, ii, a, b)));
+    for (int f = 0; f < nv; ++f) cfma(acc, t1(ki, ii, f), Wvvvv(ka, kb, ke, a, b, e, f));
+    cplx h = mkc(0, 0);
+    for (int km = 0; km < nk; ++km) {
+      int kn = kt.c3(ke, ki, km);
+      for (int m = 0; m < no; ++m)
+        for (int n = 0; n < no; ++n) cfma(h, Voovo(km, kn, ke, m, n, e, ii), tau(km, kn, ka, m, n, a, b));
+    }
+    acc = cadd(acc, cscale(h, 0.5));
+    for (int km = 0; km < nk; ++km)
+      for (int m = 0; m < no; ++m)
+        for (int f = 0; f < nv; ++f) {
+          acc = csub(acc, cmul(Vovvv(km, kb, ke, m, b, e, f), t2(km, ki, ka, m, ii, a, f)));
+          cfma(acc, Vovvv(km, ka, ke, m, a, e, f), t2(km, ki, kb, m, ii, b, f));
+        }
+    for (int m = 0; m < no; ++m) {
+      acc = csub(acc, cmul(t1(ka, m, a), Z(ka, kb, ke, m, b, e, ii)));
+      cfma(acc, t1(kb, m, b), Z(kb, ka, ke, m, a, e, ii));
+    }
+    Wvvvo.p[i] = acc;
+  });
+
+  // ---- GEMM-ready permutations of W_mbej and W_mnij used by the sigma products
+  T4 WvoP = make_t4(c, nv, no, no, nv);  // [kx][ki][km](x, i, m, e) = W_mxei
+  T4 WooP = make_t4(c, no, no, no, no);  // [ki][kj][km](i, j, m, n) = W_mnij
+  if (!WvoP.p || !WooP.p) return CCGF_ENOMEM;
+  c->WvoP = WvoP.p;
+  c->WooP = WooP.p;
+  foreach_(s, WvoP.size(), [=] __device__(size_t i) {
+    I7 x = dec(i, nk, nv, no, no, nv);
+    int kx = x.k1, ki = x.k2, km = x.k3, ke = kt.c3(km, kx, ki);
+    WvoP.p[i] = Wovvo(km, kx, ke, x.c, x.a, x.d, x.b);
+  });
+  foreach_(s, WooP.size(), [=] __device__(size_t i) {
+    I7 x = dec(i, nk, no, no, no, no);
+    int ki = x.k1, kj = x.k2, km = x.k3, kn = kt.c3(ki, kj, km);
+    WooP.p[i] = Woooo(km, kn, ki, x.c, x.d, x.a, x.b);
+  });
+
+  c->Voovv = Voovv.p;
+  if (hip_check(c, hipStreamSynchronize(s), "building Hbar blocks") != CCGF_OK) return CCGF_EDEVICE;
+  // release the integral classes that the products do not read
+  auto release = [&](cplx *p) {
+    for (auto &q : c->allocs)
+      if (q == (void *)p) {
+        hipFree(q);
+        q = nullptr;
+      }
+  };
+  release(Voooo.p); release(Vooov.p); release(Voovo.p); release(Vovoo.p); release(Vovvo.p);
+  release(Vovvv.p); release(Vvovv.p); release(Vvvvo.p); release(tau.p); release(Z.p);
+  return CCGF_OK;
+}
+
+// b and e vectors of orbital p at momentum K (either pointer may be null).
+int build_vectors(ccgf_ctx *c, int part, int K, int p, cplx *bv, cplx *ev) {
+  const int nk = c->nk, no = c->no, nv = c->nv;
+  hipStream_t s = c->stream;
+  KTab kt{nk, c->kc3};
+  T2d t1{c->t1, no, nv};
+  T4 t2{c->t2, nk, no, no, nv, nv};
+  const size_t n = (size_t)vec_len(c, part);
+  if (part == CCGF_PART_IP) {
+    // IP layout: [r1[i]], r2[ki][kj][i][j][a], ka = ki + kj - K
+    const size_t n2 = (size_t)no * no * nv;
+    if (bv) {
+      foreach_(s, n, [=] __device__(size_t x) {
+        cplx v = mkc(0, 0);
+        if (x < (size_t)no) {
+          if (p < no) v = mkc(x == (size_t)p ? 1.0 : 0.0, 0);
+          else v = t1(K, (int)x, p - no);
+        } else if (p >= no) {
+          size_t y = x - no;
+          size_t blk = y / n2, r = y % n2;
+          int ki = (int)(blk / nk), kj = (int)(blk % nk);
+          int a = (int)(r % nv), j = (int)((r / nv) % no), ii = (int)(r / ((size_t)nv * no));
+          int ka = kt.c3(ki, kj, K);
+          cplx tv = t2(ki, kj, ka, ii, j, a, p - no);
+          v = mkc(-tv.x, -tv.y);
+        }
+        bv[x] = v;
+      });
+    }
+    if (ev) {
+      foreach_(s, n, [=] __device__(size_t x) {
+        cplx v = mkc(0, 0);
+        if (x < (size_t)no) {
+          int ii = (int)x;
+          if (p >= no) {
+            v = cconj(t1(K, ii, p - no));
+          } else {
+            v = mkc(ii == p ? 1.0 : 0.0, 0);
+            for (int cc = 0; cc < nv; ++cc) v = csub(v, cmul(t1(K, p, cc), cconj(t1(K, ii, cc))));
+            cplx h = mkc(0, 0);
+            for (int kl = 0; kl < nk; ++kl)
+              for (int kc = 0; kc < nk; ++kc)
+                for (int l = 0; l < no; ++l)
+                  for (int cc = 0; cc < nv; ++cc)
+                    for (int d = 0; d < nv; ++d)
+                      cfma(h, t2(K, kl, kc, p, l, cc, d), cconj(t2(K, kl, kc, ii, l, cc, d)));
+            v = csub(v, cscale(h, 0.5));
+          }
+        } else {
+          size_t y = x - no;
+          size_t blk = y / n2, r = y % n2;
+          int ki = (int)(blk / nk), kj = (int)(blk % nk);
+          int a = (int)(r % nv), j = (int)((r / nv) % no), ii = (int)(r / ((size_t)nv * no));
+          if (p >= no) {
+            v = cconj(t2(ki, kj, K, ii, j, p - no, a));
+          } else {
+            if (ki == K && ii == p) v = cadd(v, cconj(t1(kj, j, a)));
+            if (kj == K && j == p) v = csub(v, cconj(t1(ki, ii, a)));
+            for (int cc = 0; cc < nv; ++cc) v = csub(v, cmul(t1(K, p, cc), cconj(t2(ki, kj, K, ii, j, cc, a))));
+          }
+        }
+        ev[x] = v;
+      });
+    }
+  } else {
+    // EA layout: [r1[a]], r2[ki][ka][i][a][b], kb = K + ki - ka
+    const size_t n2 = (size_t)no * nv * nv;
+    if (bv) {
+      foreach_(s, n, [=] __device__(size_t x) {
+        cplx v = mkc(0, 0);
+        if (x < (size_t)nv) {
+          if (p >= no) v = mkc((int)x == p - no ? 1.0 : 0.0, 0);
+          else {
+            cplx tv = t1(K, p, (int)x);
+            v = mkc(-tv.x, -tv.y);
+          }
+        } else if (p < no) {
+          size_t y = x - nv;
+          size_t blk = y / n2, r = y % n2;
+          int kl = (int)(blk / nk), ka = (int)(blk % nk);
+          int b = (int)(r % nv), a = (int)((r / nv) % nv), l = (int)(r / ((size_t)nv * nv));
+          cplx tv = t2(K, kl, ka, p, l, a, b);
+          v = mkc(-tv.x, -tv.y);
+        }
+        bv[x] = v;
+      });
+    }
+    if (ev) {
+      foreach_(s, n, [=] __device__(size_t x) {
+        cplx v = mkc(0, 0);
+        if (x < (size_t)nv) {
+          int a = (int)x;
+          if (p < no) {
+            cplx q = cconj(t1(K, p, a));
+            v = mkc(-q.x, -q.y);
+          } else {
+            int c0 = p - no;
+            v = mkc(a == c0 ? 1.0 : 0.0, 0);
+            for (int j = 0; j < no; ++j) v = csub(v, cmul(t1(K, j, c0), cconj(t1(K, j, a))));
+            cplx h = mkc(0, 0);
+            for (int kk = 0; kk < nk; ++kk)
+              for (int kl = 0; kl < nk; ++kl) {
+                int kd = kt.c3(kk, kl, K);
+                for (int k = 0; k < no; ++k)
+                  for (int l = 0; l < no; ++l)
+                    for (int d = 0; d < nv; ++d)
+                      cfma(h, t2(kk, kl, kd, k, l, d, c0), cconj(t2(kk, kl, kd, k, l, d, a)));
+              }
+            v = csub(v, cscale(h, 0.5));
+          }
+        } else {
+          size_t y = x - nv;
+          size_t blk = y / n2, r = y % n2;
+          int ki = (int)(blk / nk), ka = (int)(blk % nk);
+          int b = (int)(r % nv), a = (int)((r / nv) % nv), ii = (int)(r / ((size_t)nv * nv));
+          int kb = kt.c3(K, ki, ka);
+          if (p < no) {
+            v = cconj(t2(ki, K, ka, ii, p, a, b));
+          } else {
+            int c0 = p - no;
+            if (ka == K && a == c0) v = cadd(v, cconj(t1(ki, ii, b)));
+            if (kb == K && b == c0) v = csub(v, cconj(t1(ki, ii, a)));
+            for (int j = 0; j < no; ++j) cfma(v, t1(K, j, c0), cconj(t2(ki, K, ka, ii, j, a, b)));
+          }
+        }
+        ev[x] = v;
+      });
+    }
+  }
+  return hip_check(c, hipGetLastError(), "building b/e vectors");
+}

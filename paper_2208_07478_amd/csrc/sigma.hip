@@ -1,0 +1,663 @@
+// k-point EOM-IP/EA-CCSD sigma products on gfx950.
+//
+// The dominant terms (EA: 1/2 W_abcd r_i^cd, cost O(Nk^3 No Nv^4); IP: the
+// W_mbej and W_mnij terms, O(Nk^3 No^3 Nv^2); the paper's scaling paragraph)
+// are block-dense complex contractions over momentum-conserving k-blocks.  They
+// run as one segmented complex GEMM per term: a task is one output k-block for
+// all right-hand sides at once (N = pair index x RHS), its segments are the
+// summed momentum blocks, and the complex product is four real FP64 MFMA
+// 16x16x4 products per step.  The remaining terms (one-body F blocks, the
+// 1p<->2p1h / 1h<->2h1p couplings and the three-body T2 piece) are element-wise
+// or reduction kernels with the RHS index fastest, so that adjacent lanes share
+// the same Hbar element.
+#include "ccgf_internal.h"
+
+#include <algorithm>
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+#define TM 64
+#define TN 64
+#define TK 16
+
+__device__ inline long long imap(const IdxMap &m, int x) {
+  return (long long)(x / m.L) * m.s0 + (long long)(x % m.L) * m.s1;
+}
+
+// C[m][n] = alpha * sum_seg sum_k A[m][k] B[k][n] (+ C), complex FP64 on MFMA.
+// TAG only separates the uses in kernel traces (0: EA W_abcd, 1: EA W_lbdi,
+// 2: IP W_mnij, 3: IP W_maei).
+template <int TAG>
+__global__ __launch_bounds__(256) void k_cgemm_f64(GemmShape sh, const GemmTask *__restrict__ tasks,
+                                                   const GemmSeg *__restrict__ segs,
+                                                   const cplx *__restrict__ A, const cplx *__restrict__ B,
+                                                   cplx *__restrict__ C, int tilesM, int tilesN, int total) {
+  int bid = blockIdx.x;
+  // keep the tiles of one task on one XCD (consecutive logical ids share an L2)
+  if ((total & 7) == 0) {
+    int per = total >> 3;
+    bid = (bid & 7) * per + (bid >> 3);
+  }
+  const int per_task = tilesM * tilesN;
+  const int t = bid / per_task, r = bid % per_task;
+  const int tm = r / tilesN, tn = r % tilesN;
+  const GemmTask task = tasks[t];
+
+  __shared__ double Ar[TM][TK + 1], Ai[TM][TK + 1], Br[TN][TK + 1], Bi[TN][TK + 1];
+  const int tid = threadIdx.x;
+
+  long long aoff[4], boff[4];
+  int arow[4], akk[4], bcol[4], bkk[4];
+  bool aok[4], bok[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    int e = tid + 256 * j;
+    arow[j] = e / TK;
+    akk[j] = e % TK;
+    int m = tm * TM + arow[j];
+    aok[j] = m < sh.M;
+    aoff[j] = aok[j] ? imap(sh.am, m) : 0;
+    bcol[j] = e / TK;
+    bkk[j] = e % TK;
+    int n = tn * TN + bcol[j];
+    bok[j] = n < sh.N;
+    boff[j] = bok[j] ? imap(sh.bn, n) : 0;
+  }
+  const int ksteps = (sh.K + TK - 1) / TK;
+  const int nsteps = task.nseg * ksteps;
+
+  v4d accR[2][2], accI[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      accR[a][b] = (v4d){0, 0, 0, 0};
+      accI[a][b] = (v4d){0, 0, 0, 0};
+    }
+
+  cplx ra[4], rb[4];
+  auto load = [&](int step) {
+    int s = step / ksteps;
+    int k0 = (step - s * ksteps) * TK;
+    GemmSeg sg = segs[task.seg_begin + s];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int k = k0 + akk[j];
+      ra[j] = (aok[j] && k < sh.K) ? A[sg.a_off + aoff[j] + imap(sh.ak, k)] : mkc(0, 0);
+      k = k0 + bkk[j];
+      rb[j] = (bok[j] && k < sh.K) ? B[sg.b_off + boff[j] + imap(sh.bk, k)] : mkc(0, 0);
+    }
+  };
+
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  if (nsteps > 0) load(0);
+  for (int step = 0; step < nsteps; ++step) {
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      Ar[arow[j]][akk[j]] = ra[j].x;
+      Ai[arow[j]][akk[j]] = ra[j].y;
+      Br[bcol[j]][bkk[j]] = rb[j].x;
+      Bi[bcol[j]][bkk[j]] = rb[j].y;
+    }
+    __syncthreads();
+    if (step + 1 < nsteps) load(step + 1);
+#pragma unroll
+    for (int kk = 0; kk < TK; kk += 4) {
+      double a_r[2], a_i[2], b_r[2], b_i[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        a_r[q] = Ar[wr * 32 + q * 16 + lr][kk + lk];
+        a_i[q] = Ai[wr * 32 + q * 16 + lr][kk + lk];
+        b_r[q] = Br[wc * 32 + q * 16 + lr][kk + lk];
+        b_i[q] = Bi[wc * 32 + q * 16 + lr][kk + lk];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          accR[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[a], b_r[b], accR[a][b], 0, 0, 0);
+          accR[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_i[a], b_i[b], accR[a][b], 0, 0, 0);
+          accI[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[a], b_i[b], accI[a][b], 0, 0, 0);
+          accI[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[a], b_r[b], accI[a][b], 0, 0, 0);
+        }
+    }
+  }
+
+  // D layout of the 16x16 f64 MFMA block (measured): lane l, item v -> row l/16 + 4v, col l%16
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int row = wr * 32 + a * 16 + lk + 4 * v;
+        int col = wc * 32 + b * 16 + lr;
+        int m = tm * TM + row, n = tn * TN + col;
+        if (m < sh.M && n < sh.N) {
+          long long off = task.c_off + imap(sh.cm, m) + imap(sh.cn, n);
+          double re = accR[a][b][v], im = accI[a][b][v];
+          cplx val = mkc(sh.alpha_re * re - sh.alpha_im * im, sh.alpha_re * im + sh.alpha_im * re);
+          if (sh.accumulate) val = cadd(val, C[off]);
+          C[off] = val;
+        }
+      }
+}
+
+void gemm_launch(int tag, const GemmPlan &plan, const cplx *A, const cplx *B, cplx *C, hipStream_t s) {
+  const GemmShape &sh = plan.shape;
+  if (plan.ntask == 0 || sh.M == 0 || sh.N == 0) return;
+  int tilesM = (sh.M + TM - 1) / TM, tilesN = (sh.N + TN - 1) / TN;
+  long long total = (long long)plan.ntask * tilesM * tilesN;
+  dim3 g((unsigned)total), b(256);
+  switch (tag) {
+    case 0: hipLaunchKernelGGL(k_cgemm_f64<0>, g, b, 0, s, sh, plan.d_tasks, plan.d_segs, A, B, C, tilesM, tilesN, (int)total); break;
+    case 1: hipLaunchKernelGGL(k_cgemm_f64<1>, g, b, 0, s, sh, plan.d_tasks, plan.d_segs, A, B, C, tilesM, tilesN, (int)total); break;
+    case 2: hipLaunchKernelGGL(k_cgemm_f64<2>, g, b, 0, s, sh, plan.d_tasks, plan.d_segs, A, B, C, tilesM, tilesN, (int)total); break;
+    default: hipLaunchKernelGGL(k_cgemm_f64<3>, g, b, 0, s, sh, plan.d_tasks, plan.d_segs, A, B, C, tilesM, tilesN, (int)total); break;
+  }
+}
+
+// algorithmic flops of one launch (8 per complex multiply-add)
+static double plan_flops(const GemmPlan &p) {
+  return 8.0 * p.shape.M * (double)p.shape.N * p.shape.K * (double)p.segs.size();
+}
+
+void plan_upload(ccgf_ctx *c, GemmPlan &p) {
+  p.ntask = (int)p.tasks.size();
+  p.d_tasks = (GemmTask *)dev_alloc(c, sizeof(GemmTask) * std::max<size_t>(1, p.tasks.size()));
+  p.d_segs = (GemmSeg *)dev_alloc(c, sizeof(GemmSeg) * std::max<size_t>(1, p.segs.size()));
+  if (!p.d_tasks || !p.d_segs) return;
+  hipMemcpy(p.d_tasks, p.tasks.data(), sizeof(GemmTask) * p.tasks.size(), hipMemcpyHostToDevice);
+  hipMemcpy(p.d_segs, p.segs.data(), sizeof(GemmSeg) * p.segs.size(), hipMemcpyHostToDevice);
+}
+
+static IdxMap one(long long s) { return IdxMap{1 << 30, 0, s}; }
+static IdxMap two(int L, long long s0, long long s1) { return IdxMap{L, s0, s1}; }
+
+static int host_c3(const ccgf_ctx *c, int a, int b, int d) { return c->kc3_h[((size_t)a * c->nk + b) * c->nk + d]; }
+
+static void build_plans(ccgf_ctx *c, SigmaPlan &P) {
+  const int nk = c->nk, no = c->no, nv = c->nv, K = P.K, nvec = P.nvec;
+  const long long n = P.n;
+  if (P.part == CCGF_PART_EA) {
+    const long long b2 = (long long)no * nv * nv;
+    // 1/2 W_abcd r_i^cd:  C(ab ; i,v) over segments kc
+    GemmPlan &g = P.g_big;
+    g.shape.M = nv * nv;
+    g.shape.N = no * nvec;
+    g.shape.K = nv * nv;
+    g.shape.am = one((long long)nv * nv);
+    g.shape.ak = one(1);
+    g.shape.bk = one(1);
+    g.shape.bn = two(no, n, (long long)nv * nv);
+    g.shape.cm = one(1);
+    g.shape.cn = two(no, n, (long long)nv * nv);
+    g.shape.alpha_re = 0.5;
+    g.shape.alpha_im = 0;
+    g.shape.accumulate = 0;
+    T4 W{nullptr, nk, nv, nv, nv, nv};
+    for (int ki = 0; ki < nk; ++ki)
+      for (int ka = 0; ka < nk; ++ka) {
+        int kb = host_c3(c, K, ki, ka);
+        GemmTask t{nv + (ki * nk + ka) * b2, (int)g.segs.size(), nk};
+        for (int kc = 0; kc < nk; ++kc)
+          g.segs.push_back(GemmSeg{(long long)W.blk(ka, kb, kc), nv + (ki * nk + kc) * b2});
+        g.tasks.push_back(t);
+      }
+    // P(ab) W_lbdi r_l^ad (without the antisymmetriser): X(b,i ; a,v) over segments kl
+    GemmPlan &h = P.g_ovvo;
+    h.shape.M = nv * no;
+    h.shape.N = nv * nvec;
+    h.shape.K = no * nv;
+    h.shape.am = one((long long)no * nv);
+    h.shape.ak = one(1);
+    h.shape.bk = two(nv, (long long)nv * nv, 1);
+    h.shape.bn = two(nv, n, nv);
+    h.shape.cm = two(no, 1, (long long)nv * nv);
+    h.shape.cn = two(nv, n, nv);
+    h.shape.alpha_re = 1;
+    h.shape.alpha_im = 0;
+    h.shape.accumulate = 0;
+    T4 Wp{nullptr, nk, nv, no, no, nv};
+    for (int ki = 0; ki < nk; ++ki)
+      for (int ka = 0; ka < nk; ++ka) {
+        int kb = host_c3(c, K, ki, ka);
+        GemmTask t{nv + (ki * nk + ka) * b2, (int)h.segs.size(), nk};
+        for (int kl = 0; kl < nk; ++kl)
+          h.segs.push_back(GemmSeg{(long long)Wp.blk(kb, ki, kl), nv + (kl * nk + ka) * b2});
+        h.tasks.push_back(t);
+      }
+  } else {
+    const long long b2 = (long long)no * no * nv;
+    // 1/2 W_mnij r_mn^a:  C(ij ; a,v) over segments km
+    GemmPlan &g = P.g_big;
+    g.shape.M = no * no;
+    g.shape.N = nv * nvec;
+    g.shape.K = no * no;
+    g.shape.am = one((long long)no * no);
+    g.shape.ak = one(1);
+    g.shape.bk = one(nv);
+    g.shape.bn = two(nv, n, 1);
+    g.shape.cm = one(nv);
+    g.shape.cn = two(nv, n, 1);
+    g.shape.alpha_re = 0.5;
+    g.shape.alpha_im = 0;
+    g.shape.accumulate = 0;
+    T4 W{nullptr, nk, no, no, no, no};
+    for (int ki = 0; ki < nk; ++ki)
+      for (int kj = 0; kj < nk; ++kj) {
+        GemmTask t{no + (ki * nk + kj) * b2, (int)g.segs.size(), nk};
+        for (int km = 0; km < nk; ++km) {
+          int kn = host_c3(c, ki, kj, km);
+          g.segs.push_back(GemmSeg{(long long)W.blk(ki, kj, km), no + (km * nk + kn) * b2});
+        }
+        g.tasks.push_back(t);
+      }
+    // P(ij) W_maei r_mj^e (without the antisymmetriser): X(a,i ; j,v) over segments km
+    GemmPlan &h = P.g_ovvo;
+    h.shape.M = nv * no;
+    h.shape.N = no * nvec;
+    h.shape.K = no * nv;
+    h.shape.am = one((long long)no * nv);
+    h.shape.ak = one(1);
+    h.shape.bk = two(nv, (long long)no * nv, 1);
+    h.shape.bn = two(no, n, nv);
+    h.shape.cm = two(no, 1, (long long)no * nv);
+    h.shape.cn = two(no, n, nv);
+    h.shape.alpha_re = 1;
+    h.shape.alpha_im = 0;
+    h.shape.accumulate = 0;
+    T4 Wp{nullptr, nk, nv, no, no, nv};
+    for (int ki = 0; ki < nk; ++ki)
+      for (int kj = 0; kj < nk; ++kj) {
+        int ka = host_c3(c, ki, kj, K);
+        GemmTask t{no + (ki * nk + kj) * b2, (int)h.segs.size(), nk};
+        for (int km = 0; km < nk; ++km)
+          h.segs.push_back(GemmSeg{(long long)Wp.blk(ka, ki, km), no + (km * nk + kj) * b2});
+        h.tasks.push_back(t);
+      }
+  }
+  plan_upload(c, P.g_big);
+  plan_upload(c, P.g_ovvo);
+  P.ready = true;
+}
+
+// Largest offset an index map reaches for x in [0, len).
+static long long map_max(const IdxMap &m, int len) {
+  if (len <= 0) return 0;
+  long long hi = (long long)((len - 1) / m.L) * m.s0;
+  long long lo = (long long)std::min(len - 1, m.L - 1) * m.s1;
+  return hi + lo;
+}
+
+// Host-side proof that every access of a plan stays inside its buffers.
+static bool plan_in_bounds(const GemmPlan &p, size_t a_elems, size_t b_elems, size_t c_elems) {
+  const GemmShape &s = p.shape;
+  long long am = map_max(s.am, s.M) + map_max(s.ak, s.K);
+  long long bm = map_max(s.bk, s.K) + map_max(s.bn, s.N);
+  long long cm = map_max(s.cm, s.M) + map_max(s.cn, s.N);
+  for (const GemmTask &t : p.tasks) {
+    if (t.c_off < 0 || (size_t)(t.c_off + cm) >= c_elems) return false;
+    if (t.seg_begin < 0 || (size_t)(t.seg_begin + t.nseg) > p.segs.size()) return false;
+  }
+  for (const GemmSeg &g : p.segs) {
+    if (g.a_off < 0 || (size_t)(g.a_off + am) >= a_elems) return false;
+    if (g.b_off < 0 || (size_t)(g.b_off + bm) >= b_elems) return false;
+  }
+  return true;
+}
+
+// ------------------------------------------------------------------ EA
+#define RCH 8  // right-hand sides handled together by the reduction kernels
+
+// blocks (a-or-k, RHS chunk): sigma1[a] (a < nv) or Y[k] = sum <kl||cd> r_l^cd (k < no)
+__global__ __launch_bounds__(256) void k_ea_r1(int nk, int no, int nv, int K, int nvec, long long n,
+                                               const cplx *__restrict__ x, cplx *__restrict__ y,
+                                               cplx *__restrict__ aux, const cplx *__restrict__ Fvv,
+                                               const cplx *__restrict__ Fov, const cplx *__restrict__ Wvovv,
+                                               const cplx *__restrict__ Voovv) {
+  const int row = blockIdx.x;  // 0..nv-1: sigma1[a];  nv..nv+no-1: Y[k]
+  const int v0 = blockIdx.y * RCH;
+  const int nv_ch = min(RCH, nvec - v0);
+  const long long b2 = (long long)no * nv * nv;
+  const long long n2 = (long long)nk * nk * b2;
+  cplx acc[RCH];
+#pragma unroll
+  for (int q = 0; q < RCH; ++q) acc[q] = mkc(0, 0);
+  const bool is_sig = row < nv;
+  // sum over every r2 entry (kl, kc, l, c, d)
+  for (long long z = threadIdx.x; z < n2; z += blockDim.x) {
+    long long blk = z / b2, w = z % b2;
+    int kl = (int)(blk / nk), kc = (int)(blk % nk);
+    cplx wv;
+    if (is_sig) {  // 1/2 W_alcd, block [K][kl][kc]
+      size_t off = (((size_t)K * nk + kl) * nk + kc) * (size_t)(nv * b2) + (size_t)row * b2 + w;
+      wv = cscale(Wvovv[off], 0.5);
+    } else {  // <kl||cd>, block [K][kl][kc]
+      size_t off = (((size_t)K * nk + kl) * nk + kc) * (size_t)(no * b2) + (size_t)(row - nv) * b2 + w;
+      wv = Voovv[off];
+    }
+#pragma unroll
+    for (int q = 0; q < RCH; ++q)
+      if (q < nv_ch) cfma(acc[q], wv, x[(size_t)(v0 + q) * n + nv + z]);
+  }
+  if (is_sig) {
+    const int a = row;
+    // F_ac r^c  and  F_ld r_l^ad (block [kl][K], kd = kl)
+    for (int z = threadIdx.x; z < nv + nk * no * nv; z += blockDim.x) {
+      if (z < nv) {
+        cplx f = Fvv[((size_t)K * nv + a) * nv + z];
+#pragma unroll
+        for (int q = 0; q < RCH; ++q)
+          if (q < nv_ch) cfma(acc[q], f, x[(size_t)(v0 + q) * n + z]);
+      } else {
+        int w = z - nv;
+        int kl = w / (no * nv), l = (w / nv) % no, d = w % nv;
+        cplx f = Fov[((size_t)kl * no + l) * nv + d];
+        size_t off = nv + (size_t)(kl * nk + K) * b2 + ((size_t)l * nv + a) * nv + d;
+#pragma unroll
+        for (int q = 0; q < RCH; ++q)
+          if (q < nv_ch) cfma(acc[q], f, x[(size_t)(v0 + q) * n + off]);
+      }
+    }
+  }
+  // block reduction
+  __shared__ double red[2][RCH][256];
+#pragma unroll
+  for (int q = 0; q < RCH; ++q) {
+    red[0][q][threadIdx.x] = acc[q].x;
+    red[1][q][threadIdx.x] = acc[q].y;
+  }
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+#pragma unroll
+      for (int q = 0; q < RCH; ++q) {
+        red[0][q][threadIdx.x] += red[0][q][threadIdx.x + s];
+        red[1][q][threadIdx.x] += red[1][q][threadIdx.x + s];
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < (unsigned)nv_ch) {
+    int q = threadIdx.x;
+    cplx v = mkc(red[0][q][0], red[1][q][0]);
+    if (is_sig) y[(size_t)(v0 + q) * n + row] = v;
+    else aux[(size_t)(v0 + q) * (no > nv ? no : nv) + (row - nv)] = v;
+  }
+}
+
+// element-wise EA 2p1h terms (RHS index fastest)
+__global__ __launch_bounds__(256) void k_ea_local(int nk, int no, int nv, int K, int nvec, long long n,
+                                                  const int *__restrict__ kc3, const cplx *__restrict__ x,
+                                                  cplx *__restrict__ y, const cplx *__restrict__ X,
+                                                  const cplx *__restrict__ aux, const cplx *__restrict__ Foo,
+                                                  const cplx *__restrict__ Fvv, const cplx *__restrict__ Wvvvo,
+                                                  const cplx *__restrict__ t2) {
+  const long long b2 = (long long)no * nv * nv;
+  const long long n2 = (long long)nk * nk * b2;
+  long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n2 * nvec) return;
+  const int v = (int)(gid % nvec);
+  const long long z = gid / nvec;
+  const long long blk = z / b2, w = z % b2;
+  const int ki = (int)(blk / nk), ka = (int)(blk % nk);
+  const int b = (int)(w % nv), a = (int)((w / nv) % nv), i = (int)(w / ((long long)nv * nv));
+  const int kb = kc3[(K * nk + ki) * nk + ka];
+  const cplx *xv = x + (size_t)v * n;
+  const cplx *r2 = xv + nv;
+  const size_t oab = (size_t)(ki * nk + ka) * b2, oba = (size_t)(ki * nk + kb) * b2;
+  cplx acc = y[(size_t)v * n + nv + z];
+  // W_abei r^e, block [ka][kb][K] (i implied)
+  {
+    const cplx *W = Wvvvo + (((size_t)ka * nk + kb) * nk + K) * (size_t)(nv * nv * nv * no);
+    for (int e = 0; e < nv; ++e) cfma(acc, W[(((size_t)a * nv + b) * nv + e) * no + i], xv[e]);
+  }
+  // P(ab) F_bd r_i^ad
+  for (int d = 0; d < nv; ++d) {
+    cfma(acc, Fvv[((size_t)kb * nv + b) * nv + d], r2[oab + ((size_t)i * nv + a) * nv + d]);
+    cplx t = cmul(Fvv[((size_t)ka * nv + a) * nv + d], r2[oba + ((size_t)i * nv + b) * nv + d]);
+    acc = csub(acc, t);
+  }
+  // - F_li r_l^ab
+  for (int l = 0; l < no; ++l) acc = csub(acc, cmul(Foo[((size_t)ki * no + l) * no + i], r2[oab + ((size_t)l * nv + a) * nv + b]));
+  // P(ab) W_lbdi r_l^ad from the GEMM scratch
+  acc = cadd(acc, X[(size_t)v * n + nv + oab + ((size_t)i * nv + a) * nv + b]);
+  acc = csub(acc, X[(size_t)v * n + nv + oba + ((size_t)i * nv + b) * nv + a]);
+  // three-body: - 1/2 sum_k Y_k t_ki^ab, t2 block [K][ki][ka]
+  {
+    const int ldaux = no > nv ? no : nv;
+    const cplx *T = t2 + (((size_t)K * nk + ki) * nk + ka) * (size_t)(no * no * nv * nv);
+    cplx h = mkc(0, 0);
+    for (int k = 0; k < no; ++k) cfma(h, aux[(size_t)v * ldaux + k], T[(((size_t)k * no + i) * nv + a) * nv + b]);
+    acc = csub(acc, cscale(h, 0.5));
+  }
+  y[(size_t)v * n + nv + z] = acc;
+}
+
+// ------------------------------------------------------------------ IP
+// blocks (i-or-e, RHS chunk): sigma1[i] (i < no) or Xe[e] = sum <mn||ef> r_mn^f (e < nv)
+__global__ __launch_bounds__(256) void k_ip_r1(int nk, int no, int nv, int K, int nvec, long long n,
+                                               const int *__restrict__ kc3, const cplx *__restrict__ x,
+                                               cplx *__restrict__ y, cplx *__restrict__ aux,
+                                               const cplx *__restrict__ Foo, const cplx *__restrict__ Fov,
+                                               const cplx *__restrict__ Wooov, const cplx *__restrict__ Voovv) {
+  const int row = blockIdx.x;
+  const int v0 = blockIdx.y * RCH;
+  const int nv_ch = min(RCH, nvec - v0);
+  const long long b2 = (long long)no * no * nv;
+  const long long n2 = (long long)nk * nk * b2;
+  const bool is_sig = row < no;
+  cplx acc[RCH];
+#pragma unroll
+  for (int q = 0; q < RCH; ++q) acc[q] = mkc(0, 0);
+  for (long long z = threadIdx.x; z < n2; z += blockDim.x) {
+    long long blk = z / b2, w = z % b2;
+    int km = (int)(blk / nk), kn = (int)(blk % nk);
+    int e = (int)(w % nv), nn = (int)((w / nv) % no), m = (int)(w / ((long long)nv * no));
+    cplx wv;
+    if (is_sig) {  // -1/2 W_mnie, block [km][kn][K]
+      size_t off = (((size_t)km * nk + kn) * nk + K) * (size_t)(no * no * no * nv) +
+                   (((size_t)m * no + nn) * no + row) * nv + e;
+      wv = cscale(Wooov[off], -0.5);
+    } else {  // <mn||ef> with e = row - no (momentum K) and f the r-index, block [km][kn][K]
+      size_t off = (((size_t)km * nk + kn) * nk + K) * (size_t)(no * no * nv * nv) +
+                   (((size_t)m * no + nn) * nv + (row - no)) * nv + e;
+      wv = Voovv[off];
+    }
+#pragma unroll
+    for (int q = 0; q < RCH; ++q)
+      if (q < nv_ch) cfma(acc[q], wv, x[(size_t)(v0 + q) * n + no + z]);
+  }
+  if (is_sig) {
+    const int i = row;
+    // - F_mi r_m  and  F_me r_im^e (block [K][km], ke = km)
+    for (int z = threadIdx.x; z < no + nk * no * nv; z += blockDim.x) {
+      if (z < no) {
+        cplx f = Foo[((size_t)K * no + z) * no + i];
+        f = mkc(-f.x, -f.y);
+#pragma unroll
+        for (int q = 0; q < RCH; ++q)
+          if (q < nv_ch) cfma(acc[q], f, x[(size_t)(v0 + q) * n + z]);
+      } else {
+        int w = z - no;
+        int km = w / (no * nv), m = (w / nv) % no, e = w % nv;
+        cplx f = Fov[((size_t)km * no + m) * nv + e];
+        size_t off = no + (size_t)(K * nk + km) * b2 + ((size_t)i * no + m) * nv + e;
+#pragma unroll
+        for (int q = 0; q < RCH; ++q)
+          if (q < nv_ch) cfma(acc[q], f, x[(size_t)(v0 + q) * n + off]);
+      }
+    }
+  }
+  __shared__ double red[2][RCH][256];
+#pragma unroll
+  for (int q = 0; q < RCH; ++q) {
+    red[0][q][threadIdx.x] = acc[q].x;
+    red[1][q][threadIdx.x] = acc[q].y;
+  }
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+#pragma unroll
+      for (int q = 0; q < RCH; ++q) {
+        red[0][q][threadIdx.x] += red[0][q][threadIdx.x + s];
+        red[1][q][threadIdx.x] += red[1][q][threadIdx.x + s];
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < (unsigned)nv_ch) {
+    int q = threadIdx.x;
+    cplx v = mkc(red[0][q][0], red[1][q][0]);
+    if (is_sig) y[(size_t)(v0 + q) * n + row] = v;
+    else aux[(size_t)(v0 + q) * (no > nv ? no : nv) + (row - no)] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ip_local(int nk, int no, int nv, int K, int nvec, long long n,
+                                                  const int *__restrict__ kc3, const cplx *__restrict__ x,
+                                                  cplx *__restrict__ y, const cplx *__restrict__ X,
+                                                  const cplx *__restrict__ aux, const cplx *__restrict__ Foo,
+                                                  const cplx *__restrict__ Fvv, const cplx *__restrict__ Wovoo,
+                                                  const cplx *__restrict__ t2) {
+  const long long b2 = (long long)no * no * nv;
+  const long long n2 = (long long)nk * nk * b2;
+  long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n2 * nvec) return;
+  const int v = (int)(gid % nvec);
+  const long long z = gid / nvec;
+  const long long blk = z / b2, w = z % b2;
+  const int ki = (int)(blk / nk), kj = (int)(blk % nk);
+  const int a = (int)(w % nv), j = (int)((w / nv) % no), i = (int)(w / ((long long)nv * no));
+  const int ka = kc3[(ki * nk + kj) * nk + K];
+  const cplx *xv = x + (size_t)v * n;
+  const cplx *r2 = xv + no;
+  const size_t oij = (size_t)(ki * nk + kj) * b2, oji = (size_t)(kj * nk + ki) * b2;
+  cplx acc = y[(size_t)v * n + no + z];
+  // - W_maij r_m, block [K][ka][ki] (j implied)
+  {
+    const cplx *W = Wovoo + (((size_t)K * nk + ka) * nk + ki) * (size_t)(no * nv * no * no);
+    for (int m = 0; m < no; ++m) acc = csub(acc, cmul(W[(((size_t)m * nv + a) * no + i) * no + j], xv[m]));
+  }
+  // F_ae r_ij^e
+  for (int e = 0; e < nv; ++e) cfma(acc, Fvv[((size_t)ka * nv + a) * nv + e], r2[oij + ((size_t)i * no + j) * nv + e]);
+  // - P(ij) F_mi r_mj^a
+  for (int m = 0; m < no; ++m) {
+    acc = csub(acc, cmul(Foo[((size_t)ki * no + m) * no + i], r2[oij + ((size_t)m * no + j) * nv + a]));
+    cfma(acc, Foo[((size_t)kj * no + m) * no + j], r2[oji + ((size_t)m * no + i) * nv + a]);
+  }
+  // P(ij) W_maei r_mj^e from the GEMM scratch
+  acc = cadd(acc, X[(size_t)v * n + no + oij + ((size_t)i * no + j) * nv + a]);
+  acc = csub(acc, X[(size_t)v * n + no + oji + ((size_t)j * no + i) * nv + a]);
+  // three-body: + 1/2 sum_e Xe_e t_ij^ae, t2 block [ki][kj][ka] (ke = K)
+  {
+    const int ldaux = no > nv ? no : nv;
+    const cplx *T = t2 + (((size_t)ki * nk + kj) * nk + ka) * (size_t)(no * no * nv * nv);
+    cplx h = mkc(0, 0);
+    for (int e = 0; e < nv; ++e) cfma(h, aux[(size_t)v * ldaux + e], T[(((size_t)i * no + j) * nv + a) * nv + e]);
+    acc = cadd(acc, cscale(h, 0.5));
+  }
+  y[(size_t)v * n + no + z] = acc;
+}
+
+int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y) {
+  if (nvec <= 0) return CCGF_OK;
+  const long long n = vec_len(c, part);
+  // workspace
+  size_t need = (size_t)nvec * n;
+  if (c->sig_tmp_elems < need) {
+    if (c->sig_tmp) {
+      for (auto &q : c->allocs)
+        if (q == c->sig_tmp) q = nullptr;
+      hipFree(c->sig_tmp);
+    }
+    c->sig_tmp = (cplx *)dev_alloc(c, need * sizeof(cplx));
+    c->sig_tmp_elems = c->sig_tmp ? need : 0;
+    if (!c->sig_tmp) return CCGF_ENOMEM;
+  }
+  const int ldaux = std::max(c->no, c->nv);
+  size_t need_aux = (size_t)nvec * ldaux;
+  if (c->sig_r1aux_elems < need_aux) {
+    if (c->sig_r1aux) {
+      for (auto &q : c->allocs)
+        if (q == c->sig_r1aux) q = nullptr;
+      hipFree(c->sig_r1aux);
+    }
+    c->sig_r1aux = (cplx *)dev_alloc(c, need_aux * sizeof(cplx));
+    c->sig_r1aux_elems = c->sig_r1aux ? need_aux : 0;
+    if (!c->sig_r1aux) return CCGF_ENOMEM;
+  }
+  SigmaPlan *P = nullptr;
+  for (auto &q : c->plans)
+    if (q.part == part && q.K == K && q.nvec == nvec) P = &q;
+  if (!P) {
+    c->plans.emplace_back();
+    P = &c->plans.back();
+    P->part = part;
+    P->K = K;
+    P->nvec = nvec;
+    P->n = n;
+    build_plans(c, *P);
+    if (!P->g_big.d_tasks || !P->g_ovvo.d_tasks) return CCGF_ENOMEM;
+    const size_t nk3 = (size_t)c->nk * c->nk * c->nk;
+    const size_t vb = (size_t)nvec * n;
+    bool ok;
+    if (part == CCGF_PART_EA)
+      ok = plan_in_bounds(P->g_big, nk3 * c->nv * c->nv * c->nv * c->nv, vb, vb) &&
+           plan_in_bounds(P->g_ovvo, nk3 * c->nv * c->no * c->no * c->nv, vb, vb);
+    else
+      ok = plan_in_bounds(P->g_big, nk3 * c->no * c->no * c->no * c->no, vb, vb) &&
+           plan_in_bounds(P->g_ovvo, nk3 * c->nv * c->no * c->no * c->nv, vb, vb);
+    if (!ok) {
+      c->plans.pop_back();
+      return set_err(c, CCGF_EINVAL, "internal: sigma GEMM plan exceeds its buffers");
+    }
+  }
+  const int nk = c->nk, no = c->no, nv = c->nv;
+  hipStream_t s = c->stream;
+  const int nch = (nvec + RCH - 1) / RCH;
+  const bool timing = c->opt.timing != 0;
+  if (timing && !c->ev[0])
+    for (int q = 0; q < 4; ++q) hipEventCreate(&c->ev[q]);
+  if (timing) hipEventRecord(c->ev[0], s);
+  if (part == CCGF_PART_EA) {
+    if (timing) hipEventRecord(c->ev[2], s);
+    gemm_launch(0, P->g_big, c->Wvvvv, x, y, s);
+    if (timing) hipEventRecord(c->ev[3], s);
+    gemm_launch(1, P->g_ovvo, c->WvoP, x, c->sig_tmp, s);
+    hipLaunchKernelGGL(k_ea_r1, dim3(nv + no, nch), dim3(256), 0, s, nk, no, nv, K, nvec, n, x, y, c->sig_r1aux,
+                       c->Fvv, c->Fov, c->Wvovv, c->Voovv);
+    long long tot = (long long)nk * nk * no * nv * nv * nvec;
+    hipLaunchKernelGGL(k_ea_local, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, nk, no, nv, K, nvec, n,
+                       c->kc3, x, y, c->sig_tmp, c->sig_r1aux, c->Foo, c->Fvv, c->Wvvvo, c->t2);
+  } else {
+    if (timing) hipEventRecord(c->ev[2], s);
+    gemm_launch(2, P->g_big, c->WooP, x, y, s);
+    if (timing) hipEventRecord(c->ev[3], s);
+    gemm_launch(3, P->g_ovvo, c->WvoP, x, c->sig_tmp, s);
+    hipLaunchKernelGGL(k_ip_r1, dim3(no + nv, nch), dim3(256), 0, s, nk, no, nv, K, nvec, n, c->kc3, x, y,
+                       c->sig_r1aux, c->Foo, c->Fov, c->Wooov, c->Voovv);
+    long long tot = (long long)nk * nk * no * no * nv * nvec;
+    hipLaunchKernelGGL(k_ip_local, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, nk, no, nv, K, nvec, n,
+                       c->kc3, x, y, c->sig_tmp, c->sig_r1aux, c->Foo, c->Fvv, c->Wovoo, c->t2);
+  }
+  if (timing) {
+    hipEventRecord(c->ev[1], s);
+    if (hipEventSynchronize(c->ev[1]) == hipSuccess) {
+      float a = 0, b = 0;
+      hipEventElapsedTime(&a, c->ev[2], c->ev[3]);
+      hipEventElapsedTime(&b, c->ev[0], c->ev[1]);
+      if (part == CCGF_PART_EA) {
+        c->t_big_ms += a;
+        c->t_big_launches += 1;
+        c->t_big_flops += plan_flops(P->g_big);
+      }
+      c->t_sigma_ms += b;
+      c->t_sigma_launches += 1;
+    }
+  }
+  return hip_check(c, hipGetLastError(), "sigma launch");
+}

@@ -1,0 +1,74 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+declared in include/ccgf.h, and rejects invalid input before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2208_07478_amd import ccgf, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "ccgf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cc_gf_\w+)\s*\(", src)))
+
+
+def test_header_declares_the_binding_exports():
+    assert set(declared_functions()) == set(ccgf.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ccgf.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def _system_struct(s, t2=None):
+    keep = [np.ascontiguousarray(s.eps), np.ascontiguousarray(s.eri_factor), np.ascontiguousarray(s.t1),
+            np.ascontiguousarray(s.t2 if t2 is None else t2)]
+    cs = ccgf.System()
+    cs.kmesh = (ctypes.c_int * 3)(*s.kmesh)
+    cs.nocc, cs.nvir = s.nocc, s.nvir
+    cs.eps = keep[0].ctypes.data
+    cs.naux = s.eri_factor.shape[2]
+    cs.eri_factor = keep[1].ctypes.data
+    cs.t1 = keep[2].ctypes.data
+    cs.t2 = keep[3].ctypes.data
+    cs.mem_space = ccgf.HOST
+    return cs, keep
+
+
+def test_invalid_inputs_are_rejected_on_the_host():
+    lib = ccgf.load()
+    s = synth.make_system((2, 1, 1), 2, 3, seed=1)
+    h = ctypes.c_void_p()
+    # t2 that is not antisymmetric
+    bad = s.t2.copy()
+    bad[0, 0, 0, 0, 1, 0, 1] += 0.5
+    cs, keep = _system_struct(s, bad)
+    assert lib.cc_gf_init(ctypes.byref(cs), None, ctypes.byref(h)) == ccgf.EINVAL
+    assert b"antisymmetric" in lib.cc_gf_last_error(None)
+    # factor that breaks A[k3][k1][L][r][p] = conj(A[k1][k3][L][p][r])
+    s2 = synth.make_system((2, 1, 1), 2, 3, seed=1)
+    s2.eri_factor[0, 1, 0, 0, 1] += 0.3
+    cs, keep = _system_struct(s2)
+    assert lib.cc_gf_init(ctypes.byref(cs), None, ctypes.byref(h)) == ccgf.EINVAL
+    # shapes and pointers
+    cs, keep = _system_struct(s)
+    cs.nocc = 0
+    assert lib.cc_gf_init(ctypes.byref(cs), None, ctypes.byref(h)) == ccgf.EINVAL
+    cs, keep = _system_struct(s)
+    cs.t2 = None
+    assert lib.cc_gf_init(ctypes.byref(cs), None, ctypes.byref(h)) == ccgf.EINVAL
+    cs, keep = _system_struct(s)
+    cs.kmesh = (ctypes.c_int * 3)(2, 0, 1)
+    assert lib.cc_gf_init(ctypes.byref(cs), None, ctypes.byref(h)) == ccgf.EINVAL
+    assert lib.cc_gf_init(None, None, ctypes.byref(h)) == ccgf.EINVAL
+    # calls on a NULL context
+    assert lib.cc_gf_sigma(None, 1, 0, 0, None, None) == ccgf.ESTATE
+    lib.cc_gf_free(None)

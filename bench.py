@@ -31,13 +31,15 @@ PEAK_FP64 = 78.6e12  # MI355X dense FP64 matrix peak, FLOP/s
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="si_k222")
     ap.add_argument("--nw", type=int, default=4, help="frequencies per step (spread over the grid)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--restart", type=int, default=100)
-    ap.add_argument("--maxiter", type=int, default=4000)
+    ap.add_argument("--maxiter", type=int, default=12000)
+    ap.add_argument("--precond-eta", type=float, default=0.2)
+    ap.add_argument("--recycle-k", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-s", type=float, default=20.0)
     return ap.parse_args()
@@ -101,7 +103,7 @@ def main():
     orbs = list(range(nmo))
     t0 = time.perf_counter()
     ctx = Context(sysm, tol=args.tol, restart_m=args.restart, maxiter=args.maxiter, max_batch=nmo * args.nw,
-                  timing=True)
+                  timing=True, precond_eta=args.precond_eta, recycle_k=args.recycle_k)
     init_s = time.perf_counter() - t0
     stride = len(omega) // args.nw
 
@@ -110,7 +112,8 @@ def main():
         return omega[(i % stride)::stride][:args.nw]
 
     def step(i):
-        return ctx.solve([0], orbs, freqs(i), eta, allow_noconv=True)
+        # every step solves the same batch: all orbitals at the frequencies of step 0
+        return ctx.solve([0], orbs, freqs(0), eta, allow_noconv=True)
 
     for i in range(args.warmup):
         print(f"warmup step {i}", file=sys.stderr, flush=True)
@@ -136,13 +139,13 @@ def main():
     value = points / elapsed
 
     # per-part sigma counts for the CPU baseline scaling: one more step with one part at a time
-    i_acc = args.warmup
-    sl = freqs(i_acc)
+    sl = freqs(0)
     for part in ("ea", "ip"):
         _, _, _, stp = ctx.solve([0], orbs, sl, eta, parts=part, allow_noconv=True)
         sig_parts[part] = stp["n_sigma"] / (nmo * args.nw)
     # accuracy of the timed tolerance against a tight solve of the same points (one frequency)
-    ctx_t = Context(sysm, tol=1e-11, restart_m=args.restart, maxiter=2 * args.maxiter, max_batch=nmo)
+    ctx_t = Context(sysm, tol=1e-11, restart_m=args.restart, maxiter=2 * args.maxiter, max_batch=nmo,
+                    precond_eta=args.precond_eta)
     Gt, _, _, stt = ctx_t.solve([0], orbs, sl[:1], eta, allow_noconv=True)
     ctx_t.close()
     Gchk, _, _, _ = ctx.solve([0], orbs, sl[:1], eta, allow_noconv=True)
@@ -169,7 +172,8 @@ def main():
             "workload": (f"{args.workload}: Si-like {sysm.kmesh[0]}x{sysm.kmesh[1]}x{sysm.kmesh[2]} k-mesh, "
                          f"{sysm.nocc} occ + {sysm.nvir} vir spin orbitals/cell, K=Gamma, {nmo} orbitals x "
                          f"{args.nw} omega per step (every {stride}th point of the {len(omega)}-point grid on "
-                         f"[-1,1] Ha), eta={eta}, plain FP64 GMRES tol={args.tol}, restart={args.restart}"),
+                         f"[-1,1] Ha), eta={eta}, plain FP64 GMRES({args.restart}) tol={args.tol}, "
+                         f"preconditioner damping {args.precond_eta} Ha, maxiter {args.maxiter}"),
             "points_per_step": nmo * args.nw,
             "precision": "plain_f64",
         },

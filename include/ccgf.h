@@ -83,7 +83,7 @@ typedef struct {
 
 typedef struct {
   int precision;    /* CCGF_PLAIN_F64 (the only value in this build) */
-  int restart_m;    /* GMRES restart length (Krylov vectors per cycle), 1..200; 0 -> 30 */
+  int restart_m;    /* Krylov vectors per cycle, 1..2000; 0 -> 30 */
   int maxiter;      /* total GMRES iterations per solve; 0 -> 2000 */
   double tol;       /* relative residual ||b - A x|| / ||b|| in the unique-pair norm; 0 -> 1e-10 */
   int max_batch;    /* right-hand sides solved together (frequencies x orbitals); 0 -> 64 */
@@ -91,6 +91,8 @@ typedef struct {
   int timing;       /* nonzero: time the sigma kernels with HIP events (adds a wait per product) */
   double precond_eta; /* damping of the diagonal preconditioner D = w -/+ diag(M) +/- i max(eta, precond_eta);
                          0 -> eta.  Changes only the iteration count, not the solution. */
+  int recycle_k;      /* GCROT(m,k): correction pairs (u, A u) kept across cycles, 0..200;
+                         0 -> restarted GMRES(m). */
 } ccgf_options;
 
 typedef struct {

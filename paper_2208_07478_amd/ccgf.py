@@ -35,7 +35,7 @@ class System(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("restart_m", ctypes.c_int), ("maxiter", ctypes.c_int),
                 ("tol", ctypes.c_double), ("max_batch", ctypes.c_int), ("hip_stream", ctypes.c_void_p),
-                ("timing", ctypes.c_int), ("precond_eta", ctypes.c_double)]
+                ("timing", ctypes.c_int), ("precond_eta", ctypes.c_double), ("recycle_k", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -67,6 +67,10 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_2208_07478_amd.build`")
+    # torch (device memory and streams) must bring in its HIP runtime first: it loads
+    # libamdhip64.so by its unversioned name, so loading the library before torch would
+    # leave two HIP runtimes in the process
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp, ip, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
     lib.cc_gf_init.argtypes = [ctypes.POINTER(System), ctypes.POINTER(Options), ctypes.POINTER(vp)]
@@ -102,7 +106,7 @@ class Context:
     """One system on the GPU (wraps cc_gf_init / cc_gf_free)."""
 
     def __init__(self, system, *, tol=1e-10, restart_m=30, maxiter=2000, max_batch=64, stream=None,
-                 timing=False, foo=None, fvv=None, precond_eta=0.0):
+                 timing=False, foo=None, fvv=None, precond_eta=0.0, recycle_k=0):
         lib = load()
         import torch  # device memory and streams only
         self._torch = torch
@@ -127,7 +131,8 @@ class Context:
         cs.t2 = self._keep[3].ctypes.data
         cs.mem_space = HOST
         opt = Options(PLAIN_F64, int(restart_m), int(maxiter), float(tol), int(max_batch),
-                      ctypes.c_void_p(stream.cuda_stream), 1 if timing else 0, float(precond_eta))
+                      ctypes.c_void_p(stream.cuda_stream), 1 if timing else 0, float(precond_eta),
+                      int(recycle_k))
         self._opt = opt
         h = ctypes.c_void_p()
         rc = lib.cc_gf_init(ctypes.byref(cs), ctypes.byref(opt), ctypes.byref(h))

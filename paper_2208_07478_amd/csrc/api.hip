@@ -109,7 +109,8 @@ extern "C" int cc_gf_init(const ccgf_system *s, const ccgf_options *opt, ccgf_ct
   if (o.maxiter == 0) o.maxiter = 2000;
   if (o.tol == 0) o.tol = 1e-10;
   if (o.max_batch == 0) o.max_batch = 64;
-  if (o.restart_m < 1 || o.restart_m > 200 || o.maxiter < 1 || o.tol < 0 || o.max_batch < 1)
+  if (o.restart_m < 1 || o.restart_m > 2000 || o.maxiter < 1 || o.tol < 0 || o.max_batch < 1 ||
+      o.recycle_k < 0 || o.recycle_k > 200 || o.precond_eta < 0)
     return set_err(nullptr, CCGF_EINVAL, "options out of range");
 
   ccgf_ctx *c = new ccgf_ctx();

@@ -1,8 +1,12 @@
-// Batched restarted GMRES for the shifted EOM systems of Eq. 6:
+// Batched Krylov solver for the shifted EOM systems of Eq. 6:
 //   IP: (w + M_IP - i eta) x = b,   EA: (w - M_EA + i eta) y = b,
-// right-preconditioned by the diagonal D = w + s_M diag(M) + s_eta i eta, with
-// classical Gram-Schmidt applied twice (CGS2) for the Arnoldi step and complex
-// Givens rotations for the Hessenberg least-squares problem, all in FP64.  All
+// right-preconditioned by the diagonal D = w + s_M diag(M) + s_eta i eta_p.
+// The paper solves these with GCROT(m,k); here each outer cycle is an Arnoldi
+// process of up to m steps on (I - C C^H) A, followed by the minimal-residual
+// correction u and its image c = A u, which join a recycled set of the k most
+// recent (u, c) pairs (k = 0 is restarted GMRES(m)).  Classical Gram-Schmidt is
+// applied twice (CGS2) against C and the Arnoldi basis, and complex Givens
+// rotations solve the Hessenberg least-squares problem, all in FP64.  All
 // right-hand sides of one momentum K and part (orbitals x frequencies) advance
 // together, so one sigma product per step serves the whole batch.  Inner
 // products count each unordered pair once (weight 1/2 on the doubly stored
@@ -80,10 +84,10 @@ __global__ __launch_bounds__(256) void k_dots(const cplx *__restrict__ U, const 
   }
 }
 
-// out[v][i] = sum_chunk partial; if H != null also H[v][i][col] += out
+// out[v][i] = sum_chunk partial; if H != null also H[v][i][col] += out (and H2 likewise)
 __global__ void k_dots_reduce(const cplx *__restrict__ partial, int nchunk, int ldp, int ni,
                               const int *__restrict__ active, cplx *__restrict__ out, int ldo,
-                              cplx *__restrict__ H, int ldh, long long shv, int col) {
+                              cplx *__restrict__ H, int ldh, long long shv, int col, cplx *__restrict__ H2 = nullptr) {
   const int v = blockIdx.x;
   if (active && !active[v]) return;
   for (int i = threadIdx.x; i < ni; i += blockDim.x) {
@@ -92,6 +96,10 @@ __global__ void k_dots_reduce(const cplx *__restrict__ partial, int nchunk, int 
     out[(size_t)v * ldo + i] = s;
     if (H) {
       cplx *h = H + (size_t)v * shv + (size_t)i * ldh + col;
+      *h = cadd(*h, s);
+    }
+    if (H2) {
+      cplx *h = H2 + (size_t)v * shv + (size_t)i * ldh + col;
       *h = cadd(*h, s);
     }
   }
@@ -228,18 +236,28 @@ __global__ void k_scale(cplx *out, const cplx *w, const double *__restrict__ inv
   out[(size_t)v * n + x] = cscale(w[(size_t)v * n + x], inv[v]);
 }
 
+// out[idx[slot]] = w[idx[slot]] * inv[idx[slot]]
+__global__ void k_scale_idx(cplx *__restrict__ out, const cplx *__restrict__ w, const double *__restrict__ inv,
+                            long long n, const int *__restrict__ idx) {
+  const int v = idx[blockIdx.y];
+  long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  out[(size_t)v * n + x] = cscale(w[(size_t)v * n + x], inv[v]);
+}
+
 // One Givens step per right-hand side (column j of its Hessenberg matrix).
 // H[v] is (m+1) x m row-major with leading dimension m.
 __global__ void k_givens(int nvec, int m, int j, cplx *__restrict__ H, cplx *__restrict__ cs, cplx *__restrict__ sn,
-                         cplx *__restrict__ g, const cplx *__restrict__ nrm2, double *__restrict__ inv,
+                         cplx *__restrict__ g, const cplx *__restrict__ nrm2, int ldn, double *__restrict__ inv,
                          int *__restrict__ active, int *__restrict__ kused, const double *__restrict__ thresh,
-                         const int *__restrict__ jlim) {
+                         const int *__restrict__ jlim, cplx *__restrict__ H0) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nvec || !active[v]) return;
   cplx *Hv = H + (size_t)v * (m + 1) * m;
   cplx *c = cs + (size_t)v * m, *s = sn + (size_t)v * m, *gv = g + (size_t)v * (m + 1);
-  double hn = sqrt(fmax(nrm2[(size_t)v * (m + 1)].x, 0.0));
+  double hn = sqrt(fmax(nrm2[(size_t)v * ldn].x, 0.0));
   Hv[(size_t)(j + 1) * m + j] = mkc(hn, 0);
+  H0[(size_t)v * (m + 1) * m + (size_t)(j + 1) * m + j] = mkc(hn, 0);
   inv[v] = hn > 0 ? 1.0 / hn : 0.0;
   for (int i = 0; i < j; ++i) {
     cplx a = Hv[(size_t)i * m + j], b = Hv[(size_t)(i + 1) * m + j];
@@ -286,41 +304,98 @@ __global__ void k_backsolve(int nvec, int m, const cplx *__restrict__ H, const c
   }
 }
 
-// x[v] += D^-1 (sum_i y_i V_i[v])
-__global__ void k_update_x(cplx *__restrict__ xs, const cplx *__restrict__ V, long long svi, long long n, int m,
-                           const cplx *__restrict__ ysol, const int *__restrict__ kused,
-                           const cplx *__restrict__ diag, const cplx *__restrict__ shift, double sM,
-                           const int *__restrict__ done) {
+// X[v] += sum_i h[v][i] * U_i[v]  (masked)
+__global__ __launch_bounds__(256) void k_add_proj(cplx *__restrict__ X, const cplx *__restrict__ U, long long svi,
+                                                  long long n, int ni, const cplx *__restrict__ h, int ldh,
+                                                  const int *__restrict__ active) {
   const int v = blockIdx.y;
-  if (done[v]) return;
+  if (!active[v]) return;
   long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= n) return;
-  cplx acc = mkc(0, 0);
-  int k = kused[v];
-  for (int i = 0; i < k; ++i) cfma(acc, ysol[(size_t)v * m + i], V[(size_t)i * svi + (size_t)v * n + x]);
-  cplx dd = cadd(shift[v], cscale(diag[x], sM));
+  cplx acc = X[(size_t)v * n + x];
+  for (int i = 0; i < ni; ++i) cfma(acc, h[(size_t)v * ldh + i], U[(size_t)i * svi + (size_t)v * n + x]);
+  X[(size_t)v * n + x] = acc;
+}
+
+// t = Bm y (recycled-space coefficients, kc entries) and d = H0 y (kused + 1 entries)
+__global__ void k_gcrot_small(int nvec, int m, int kc, const cplx *__restrict__ Bm, const cplx *__restrict__ H0,
+                              const cplx *__restrict__ ysol, const int *__restrict__ kused, cplx *__restrict__ t,
+                              cplx *__restrict__ d, const int *__restrict__ skip, int ldt) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nvec || skip[v]) return;
+  const int k = kused[v];
+  const cplx *y = ysol + (size_t)v * m;
+  for (int l = 0; l < kc; ++l) {
+    cplx acc = mkc(0, 0);
+    for (int i = 0; i < k; ++i) cfma(acc, Bm[(size_t)v * ldt * m + (size_t)l * m + i], y[i]);
+    t[(size_t)v * ldt + l] = acc;
+  }
+  for (int r = 0; r <= k; ++r) {
+    cplx acc = mkc(0, 0);
+    for (int i = 0; i < k; ++i) cfma(acc, H0[(size_t)v * (m + 1) * m + (size_t)r * m + i], y[i]);
+    d[(size_t)v * (m + 1) + r] = acc;
+  }
+}
+
+// u = D^-1 V y - U t,  c = V d;  x += u, r -= c;  u, c stored into the recycle slot
+__global__ __launch_bounds__(256) void k_gcrot_combine(
+    long long n, int m, long long svi, const cplx *__restrict__ V, const cplx *__restrict__ ysol,
+    const cplx *__restrict__ d, const int *__restrict__ kused, int kc, const cplx *Ub,
+    const cplx *__restrict__ t, int ldt, const cplx *__restrict__ diag, const cplx *__restrict__ pshift, double sM,
+    cplx *uout, cplx *__restrict__ cout, cplx *__restrict__ xs, cplx *__restrict__ rs,
+    const int *__restrict__ skip) {
+  const int v = blockIdx.y;
+  if (skip[v]) return;
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int k = kused[v];
+  cplx vy = mkc(0, 0), cc = mkc(0, 0);
+  for (int i = 0; i < k; ++i) {
+    cplx vi = V[(size_t)i * svi + (size_t)v * n + e];
+    cfma(vy, ysol[(size_t)v * m + i], vi);
+    cfma(cc, d[(size_t)v * (m + 1) + i], vi);
+  }
+  cfma(cc, d[(size_t)v * (m + 1) + k], V[(size_t)k * svi + (size_t)v * n + e]);
+  cplx dd = cadd(pshift[v], cscale(diag[e], sM));
   double den = dd.x * dd.x + dd.y * dd.y;
-  cplx q = mkc((acc.x * dd.x + acc.y * dd.y) / den, (acc.y * dd.x - acc.x * dd.y) / den);
-  xs[(size_t)v * n + x] = cadd(xs[(size_t)v * n + x], q);
+  cplx u = mkc((vy.x * dd.x + vy.y * dd.y) / den, (vy.y * dd.x - vy.x * dd.y) / den);
+  for (int l = 0; l < kc; ++l) u = csub(u, cmul(t[(size_t)v * ldt + l], Ub[(size_t)l * svi + (size_t)v * n + e]));
+  const size_t o = (size_t)v * n + e;
+  uout[o] = u;  // may overwrite the oldest recycled u of this element, already read above
+  cout[o] = cc;
+  xs[o] = cadd(xs[o], u);
+  rs[o] = csub(rs[o], cc);
+}
+
+// inv[v] = 1 / sqrt(nrm2[v]) for the right-hand sides that took part
+__global__ void k_inv_sqrt(int nvec, const cplx *__restrict__ nrm2, int ld, double *__restrict__ inv,
+                           const int *__restrict__ skip) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nvec || skip[v]) return;
+  double q = sqrt(fmax(nrm2[(size_t)v * ld].x, 0.0));
+  inv[v] = q > 0 ? 1.0 / q : 0.0;
+}
+
+// u, c *= inv (participating right-hand sides)
+__global__ void k_scale2(cplx *__restrict__ a, cplx *__restrict__ b, const double *__restrict__ inv, long long n,
+                         const int *__restrict__ skip) {
+  const int v = blockIdx.y;
+  if (skip[v]) return;
+  long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  size_t o = (size_t)v * n + x;
+  a[o] = cscale(a[o], inv[v]);
+  b[o] = cscale(b[o], inv[v]);
 }
 
 }  // namespace
 
 struct GmresWork {
-  long long n = 0;
-  int B = 0, m = 0, nchunk = 0, ldp = 0;
-  cplx *V = nullptr, *x = nullptr, *z = nullptr, *w = nullptr, *b = nullptr, *diag = nullptr, *wc = nullptr;
-  cplx *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *htmp = nullptr, *partial = nullptr;
-  cplx *shift = nullptr, *pshift = nullptr, *ysol = nullptr, *gout = nullptr;
-  double *inv = nullptr, *thresh = nullptr;
-  int *active = nullptr, *kused = nullptr, *done = nullptr, *jlim = nullptr, *aidx = nullptr;
-  long long *uoff = nullptr, *eoff = nullptr;
   std::vector<void *> mine;
   bool failed = false;
 };
 
-static void *walloc(ccgf_ctx *c, GmresWork &W, size_t bytes) {
-  (void)c;
+static void *walloc(GmresWork &W, size_t bytes) {
   void *p = nullptr;
   if (hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess) {
     (void)hipGetLastError();
@@ -342,157 +417,189 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
   const double sM = part == CCGF_PART_IP ? 1.0 : -1.0;
   const double sE = part == CCGF_PART_IP ? -1.0 : 1.0;
   const int m = c->opt.restart_m;
+  const int kr = c->opt.recycle_k;          // recycled pairs (0: GMRES(m))
+  const int kslots = std::max(kr, 1);
   const int Bmax = std::max(1, std::min(c->opt.max_batch, nrhs));
+  const int nchunk = (int)((n + DOT_CHUNK - 1) / DOT_CHUNK);
+  const int ldp = std::max(m, kslots) + 1;
   hipStream_t s = c->stream;
   GmresWork W;
-  W.n = n;
-  W.B = Bmax;
-  W.m = m;
-  W.nchunk = (int)((n + DOT_CHUNK - 1) / DOT_CHUNK);
-  W.ldp = m + 1;
   const size_t vb = (size_t)Bmax * n;
-  W.V = (cplx *)walloc(c, W, sizeof(cplx) * vb * (m + 1));
-  W.x = (cplx *)walloc(c, W, sizeof(cplx) * vb);
-  W.z = (cplx *)walloc(c, W, sizeof(cplx) * vb);
-  W.w = (cplx *)walloc(c, W, sizeof(cplx) * vb);
-  W.wc = (cplx *)walloc(c, W, sizeof(cplx) * vb);
-  W.b = (cplx *)walloc(c, W, sizeof(cplx) * vb);
-  W.diag = (cplx *)walloc(c, W, sizeof(cplx) * n);
-  W.H = (cplx *)walloc(c, W, sizeof(cplx) * Bmax * (m + 1) * m);
-  W.cs = (cplx *)walloc(c, W, sizeof(cplx) * Bmax * m);
-  W.sn = (cplx *)walloc(c, W, sizeof(cplx) * Bmax * m);
-  W.g = (cplx *)walloc(c, W, sizeof(cplx) * Bmax * (m + 1));
-  W.htmp = (cplx *)walloc(c, W, sizeof(cplx) * Bmax * (m + 1));
-  W.partial = (cplx *)walloc(c, W, sizeof(cplx) * (size_t)Bmax * W.nchunk * W.ldp);
-  W.shift = (cplx *)walloc(c, W, sizeof(cplx) * Bmax);
-  W.pshift = (cplx *)walloc(c, W, sizeof(cplx) * Bmax);
-  W.ysol = (cplx *)walloc(c, W, sizeof(cplx) * Bmax * m);
-  W.gout = (cplx *)walloc(c, W, sizeof(cplx) * Bmax);
-  W.inv = (double *)walloc(c, W, sizeof(double) * Bmax);
-  W.thresh = (double *)walloc(c, W, sizeof(double) * Bmax);
-  W.active = (int *)walloc(c, W, sizeof(int) * Bmax);
-  W.kused = (int *)walloc(c, W, sizeof(int) * Bmax);
-  W.done = (int *)walloc(c, W, sizeof(int) * Bmax);
-  W.jlim = (int *)walloc(c, W, sizeof(int) * Bmax);
-  W.aidx = (int *)walloc(c, W, sizeof(int) * Bmax);
-  W.uoff = (long long *)walloc(c, W, sizeof(long long) * Bmax);
-  W.eoff = (long long *)walloc(c, W, sizeof(long long) * Bmax);
+  const size_t svi = vb;
+  cplx *V = (cplx *)walloc(W, sizeof(cplx) * vb * (m + 1));
+  cplx *Ub = (cplx *)walloc(W, sizeof(cplx) * vb * kslots);
+  cplx *Cb = (cplx *)walloc(W, sizeof(cplx) * vb * kslots);
+  cplx *X = (cplx *)walloc(W, sizeof(cplx) * vb);
+  cplx *R = (cplx *)walloc(W, sizeof(cplx) * vb);
+  cplx *Z = (cplx *)walloc(W, sizeof(cplx) * vb);
+  cplx *Wv = (cplx *)walloc(W, sizeof(cplx) * vb);
+  cplx *Wc = (cplx *)walloc(W, sizeof(cplx) * vb);
+  cplx *Bv = (cplx *)walloc(W, sizeof(cplx) * vb);
+  cplx *diag = (cplx *)walloc(W, sizeof(cplx) * n);
+  cplx *H = (cplx *)walloc(W, sizeof(cplx) * Bmax * (m + 1) * m);
+  cplx *H0 = (cplx *)walloc(W, sizeof(cplx) * Bmax * (m + 1) * m);
+  cplx *Bm = (cplx *)walloc(W, sizeof(cplx) * Bmax * kslots * m);
+  cplx *cs = (cplx *)walloc(W, sizeof(cplx) * Bmax * m);
+  cplx *sn = (cplx *)walloc(W, sizeof(cplx) * Bmax * m);
+  cplx *g = (cplx *)walloc(W, sizeof(cplx) * Bmax * (m + 1));
+  cplx *htmp = (cplx *)walloc(W, sizeof(cplx) * Bmax * ldp);
+  cplx *partial = (cplx *)walloc(W, sizeof(cplx) * (size_t)Bmax * nchunk * ldp);
+  cplx *shift = (cplx *)walloc(W, sizeof(cplx) * Bmax);
+  cplx *pshift = (cplx *)walloc(W, sizeof(cplx) * Bmax);
+  cplx *ysol = (cplx *)walloc(W, sizeof(cplx) * Bmax * m);
+  cplx *tv = (cplx *)walloc(W, sizeof(cplx) * Bmax * kslots);
+  cplx *dv = (cplx *)walloc(W, sizeof(cplx) * Bmax * (m + 1));
+  double *inv = (double *)walloc(W, sizeof(double) * Bmax);
+  double *thresh = (double *)walloc(W, sizeof(double) * Bmax);
+  int *active = (int *)walloc(W, sizeof(int) * Bmax);
+  int *kused = (int *)walloc(W, sizeof(int) * Bmax);
+  int *skip = (int *)walloc(W, sizeof(int) * Bmax);
+  int *jlim = (int *)walloc(W, sizeof(int) * Bmax);
+  int *aidx = (int *)walloc(W, sizeof(int) * Bmax);
+  long long *uoff = (long long *)walloc(W, sizeof(long long) * Bmax);
+  long long *eoff = (long long *)walloc(W, sizeof(long long) * Bmax);
   if (W.failed) {
     wfree(W);
-    return set_err(c, CCGF_ENOMEM, "GMRES workspace allocation failed (reduce max_batch or restart_m)");
+    return set_err(c, CCGF_ENOMEM, "solver workspace allocation failed (reduce max_batch, restart_m or recycle_k)");
   }
   const unsigned gx = (unsigned)((n + 255) / 256);
-  hipLaunchKernelGGL(k_diag, dim3(gx), dim3(256), 0, s, part, c->nk, c->no, c->nv, K, c->kc3, c->Foo, c->Fvv,
-                     W.diag, n);
+  hipLaunchKernelGGL(k_diag, dim3(gx), dim3(256), 0, s, part, c->nk, c->no, c->nv, K, c->kc3, c->Foo, c->Fvv, diag,
+                     n);
 
   int status = CCGF_OK;
-  std::vector<cplx> hshift(Bmax), hpshift(Bmax), hh((size_t)Bmax * (m + 1)), g0((size_t)Bmax * (m + 1));
   const double peta = std::max(eta, c->opt.precond_eta);
-  std::vector<double> hbnorm(Bmax), hthr(Bmax), hbeta(Bmax), hinv(Bmax);
+  std::vector<cplx> hshift(Bmax), hpshift(Bmax), hh((size_t)Bmax * ldp), g0((size_t)Bmax * (m + 1));
+  std::vector<double> hbnorm(Bmax), hthr(Bmax), hrn(Bmax), hinv(Bmax);
   std::vector<int> hconv(Bmax), hkused(Bmax), hact(Bmax), hskip(Bmax), its(Bmax), hjlim(Bmax);
   std::vector<long long> hoff(Bmax), heoff(Bmax);
   std::vector<int> alist;
   alist.reserve(Bmax);
   const double tol = c->opt.tol;
   const int maxit = c->opt.maxiter;
-  const size_t svi = (size_t)Bmax * n;
   auto sync = [&](const char *what) -> int {
     if (hipStreamSynchronize(s) != hipSuccess) return hip_check(c, hipGetLastError(), what);
     return hip_check(c, hipGetLastError(), what);
   };
-  // weighted squared norms of the B vectors at X into hh[v*(m+1)]
-  auto norms = [&](const cplx *X, int B) {
-    hipLaunchKernelGGL(k_dots, dim3(W.nchunk, B), dim3(256), 0, s, X, W.uoff, 0LL, 1, X, n, n1, 1,
-                       (const int *)nullptr, W.partial, W.nchunk, W.ldp);
-    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, W.partial, W.nchunk, W.ldp, 1, (const int *)nullptr,
-                       W.htmp, m + 1, (cplx *)nullptr, 0, 0LL, 0);
-    hipMemcpyAsync(hh.data(), W.htmp, sizeof(cplx) * B * (m + 1), hipMemcpyDeviceToHost, s);
+  // weighted squared norms of the B vectors at Xp into hh[v * ldp]
+  auto norms = [&](const cplx *Xp, int B) {
+    hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Xp, uoff, 0LL, 1, Xp, n, n1, 1,
+                       (const int *)nullptr, partial, nchunk, ldp);
+    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, 1, (const int *)nullptr, htmp,
+                       ldp, (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr);
+  };
+  // true residual b - A x of the listed right-hand sides into R and its norm into hh
+  auto true_residual = [&](int B) -> int {
+    const int np = (int)alist.size();
+    if (np == 0) return CCGF_OK;
+    hipMemcpyAsync(aidx, alist.data(), sizeof(int) * np, hipMemcpyHostToDevice, s);
+    hipLaunchKernelGGL(k_gather_precond, dim3(gx, np), dim3(256), 0, s, Z, X, diag, shift, 0.0, n, aidx, 0);
+    int rc = sigma_apply(c, part, K, np, Z, Wc);
+    if (rc != CCGF_OK) return rc;
+    if (st) st->n_sigma += np;
+    hipLaunchKernelGGL(k_residual_c, dim3(gx, np), dim3(256), 0, s, R, Bv, X, Wc, shift, sM, n, aidx);
+    norms(R, B);
+    hipMemcpyAsync(hh.data(), htmp, sizeof(cplx) * B * ldp, hipMemcpyDeviceToHost, s);
+    return sync("true residual");
   };
 
-  for (int r0 = 0; r0 < nrhs && status != CCGF_EDEVICE; r0 += Bmax) {
+  for (int r0 = 0; r0 < nrhs; r0 += Bmax) {
     const int B = std::min(Bmax, nrhs - r0);
     for (int v = 0; v < B; ++v) {
       hshift[v] = mkc(rhs_omega[r0 + v], sE * eta);
       hpshift[v] = mkc(rhs_omega[r0 + v], sE * peta);
       hoff[v] = (long long)v * n;  // each RHS's own vector inside a [B][n] batch
       heoff[v] = (long long)rhs_orb[r0 + v] * n;
-      hipMemcpyAsync(W.b + (size_t)v * n, Bvecs + (size_t)rhs_orb[r0 + v] * n, sizeof(cplx) * n,
+      hipMemcpyAsync(Bv + (size_t)v * n, Bvecs + (size_t)rhs_orb[r0 + v] * n, sizeof(cplx) * n,
                      hipMemcpyDeviceToDevice, s);
     }
-    hipMemcpyAsync(W.shift, hshift.data(), sizeof(cplx) * B, hipMemcpyHostToDevice, s);
-    hipMemcpyAsync(W.pshift, hpshift.data(), sizeof(cplx) * B, hipMemcpyHostToDevice, s);
-    hipMemcpyAsync(W.uoff, hoff.data(), sizeof(long long) * B, hipMemcpyHostToDevice, s);
-    hipMemcpyAsync(W.eoff, heoff.data(), sizeof(long long) * B, hipMemcpyHostToDevice, s);
-    hipMemsetAsync(W.x, 0, sizeof(cplx) * (size_t)B * n, s);
-    norms(W.b, B);  // x0 = 0, so r0 = b
-    if (int rc = sync("GMRES start")) {
+    hipMemcpyAsync(shift, hshift.data(), sizeof(cplx) * B, hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(pshift, hpshift.data(), sizeof(cplx) * B, hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(uoff, hoff.data(), sizeof(long long) * B, hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(eoff, heoff.data(), sizeof(long long) * B, hipMemcpyHostToDevice, s);
+    hipMemsetAsync(X, 0, sizeof(cplx) * (size_t)B * n, s);
+    hipMemcpyAsync(R, Bv, sizeof(cplx) * (size_t)B * n, hipMemcpyDeviceToDevice, s);  // x0 = 0: r0 = b
+    norms(Bv, B);
+    hipMemcpyAsync(hh.data(), htmp, sizeof(cplx) * B * ldp, hipMemcpyDeviceToHost, s);
+    if (int rc = sync("solver start")) {
       wfree(W);
       return rc;
     }
     for (int v = 0; v < B; ++v) {
-      hbnorm[v] = std::sqrt(std::max(hh[(size_t)v * (m + 1)].x, 0.0));
-      hbeta[v] = hbnorm[v];
+      hbnorm[v] = std::sqrt(std::max(hh[(size_t)v * ldp].x, 0.0));
+      hrn[v] = hbnorm[v];
       hthr[v] = tol * hbnorm[v];
       hconv[v] = hbnorm[v] == 0.0;
       its[v] = 0;
-      hinv[v] = hbeta[v] > 0 ? 1.0 / hbeta[v] : 0.0;
     }
-    hipMemcpyAsync(W.thresh, hthr.data(), sizeof(double) * B, hipMemcpyHostToDevice, s);
-    hipMemcpyAsync(W.inv, hinv.data(), sizeof(double) * B, hipMemcpyHostToDevice, s);
-    hipLaunchKernelGGL(k_scale, dim3(gx, B), dim3(256), 0, s, W.V, W.b, W.inv, n, (const int *)nullptr);
-
-    while (true) {  // restart cycles
+    hipMemcpyAsync(thresh, hthr.data(), sizeof(double) * B, hipMemcpyHostToDevice, s);
+    int cyc = 0;
+    while (true) {  // outer cycles
       int npart = 0;
       for (int v = 0; v < B; ++v) {
         hact[v] = (!hconv[v] && its[v] < maxit) ? 1 : 0;
         hskip[v] = !hact[v];
         hjlim[v] = std::min(m, std::max(0, maxit - its[v]));  // iteration budget of this cycle
+        hinv[v] = hrn[v] > 0 ? 1.0 / hrn[v] : 0.0;
         npart += hact[v];
       }
       if (npart == 0) break;
-      hipMemcpyAsync(W.jlim, hjlim.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
-      hipMemcpyAsync(W.active, hact.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
-      hipMemcpyAsync(W.done, hskip.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
-      hipMemsetAsync(W.H, 0, sizeof(cplx) * B * (m + 1) * m, s);
+      const int kc = std::min(cyc, kr);  // recycled pairs in use
+      const int slot = kr > 0 ? cyc % kr : 0;
+      hipMemcpyAsync(jlim, hjlim.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
+      hipMemcpyAsync(active, hact.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
+      hipMemcpyAsync(skip, hskip.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
+      hipMemcpyAsync(inv, hinv.data(), sizeof(double) * B, hipMemcpyHostToDevice, s);
+      hipLaunchKernelGGL(k_scale, dim3(gx, B), dim3(256), 0, s, V, R, inv, n, active);  // V_0 = r / ||r||
+      hipMemsetAsync(H, 0, sizeof(cplx) * B * (m + 1) * m, s);
+      hipMemsetAsync(H0, 0, sizeof(cplx) * B * (m + 1) * m, s);
+      hipMemsetAsync(Bm, 0, sizeof(cplx) * B * kslots * m, s);
       std::fill(g0.begin(), g0.end(), mkc(0, 0));
-      for (int v = 0; v < B; ++v) g0[(size_t)v * (m + 1)] = mkc(hbeta[v], 0);
-      hipMemcpyAsync(W.g, g0.data(), sizeof(cplx) * B * (m + 1), hipMemcpyHostToDevice, s);
-      hipMemsetAsync(W.kused, 0, sizeof(int) * B, s);
+      for (int v = 0; v < B; ++v) g0[(size_t)v * (m + 1)] = mkc(hrn[v], 0);
+      hipMemcpyAsync(g, g0.data(), sizeof(cplx) * B * (m + 1), hipMemcpyHostToDevice, s);
+      hipMemsetAsync(kused, 0, sizeof(int) * B, s);
       for (int j = 0; j < m; ++j) {
-        cplx *Vj = W.V + (size_t)j * svi;
+        cplx *Vj = V + (size_t)j * svi;
         // only the right-hand sides still iterating enter the sigma product
         alist.clear();
         for (int v = 0; v < B; ++v)
           if (hact[v]) alist.push_back(v);
         const int na = (int)alist.size();
-        hipMemcpyAsync(W.aidx, alist.data(), sizeof(int) * na, hipMemcpyHostToDevice, s);
-        hipLaunchKernelGGL(k_gather_precond, dim3(gx, na), dim3(256), 0, s, W.z, Vj, W.diag, W.pshift, sM, n, W.aidx, 1);
-        int rc = sigma_apply(c, part, K, na, W.z, W.wc);
+        hipMemcpyAsync(aidx, alist.data(), sizeof(int) * na, hipMemcpyHostToDevice, s);
+        hipLaunchKernelGGL(k_gather_precond, dim3(gx, na), dim3(256), 0, s, Z, Vj, diag, pshift, sM, n, aidx, 1);
+        int rc = sigma_apply(c, part, K, na, Z, Wc);
         if (rc != CCGF_OK) {
           wfree(W);
           return rc;
         }
         if (st) st->n_sigma += na;
-        hipLaunchKernelGGL(k_scatter_shift, dim3(gx, na), dim3(256), 0, s, W.w, W.z, W.wc, W.shift, sM, n, W.aidx);
-        for (int pass = 0; pass < 2; ++pass) {  // CGS2 against V_0..V_j
-          hipLaunchKernelGGL(k_dots, dim3(W.nchunk, B), dim3(256), 0, s, W.V, W.uoff, (long long)svi, j + 1, W.w, n,
-                             n1, 1, W.active, W.partial, W.nchunk, W.ldp);
-          hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, W.partial, W.nchunk, W.ldp, j + 1, W.active,
-                             W.htmp, m + 1, W.H, m, (long long)(m + 1) * m, j);
-          hipLaunchKernelGGL(k_sub_proj, dim3(gx, B), dim3(256), 0, s, W.w, W.V, (long long)svi, n, j + 1, W.htmp,
-                             m + 1, W.active);
+        hipLaunchKernelGGL(k_scatter_shift, dim3(gx, na), dim3(256), 0, s, Wv, Z, Wc, shift, sM, n, aidx);
+        for (int pass = 0; pass < 2; ++pass) {  // CGS2 against the recycled C and V_0..V_j
+          if (kc > 0) {
+            hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Cb, uoff, (long long)svi, kc, Wv, n, n1, 1,
+                               active, partial, nchunk, ldp);
+            hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, kc, active, htmp, ldp,
+                               Bm, m, (long long)kslots * m, j, (cplx *)nullptr);
+            hipLaunchKernelGGL(k_sub_proj, dim3(gx, B), dim3(256), 0, s, Wv, Cb, (long long)svi, n, kc, htmp, ldp,
+                               active);
+          }
+          hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, V, uoff, (long long)svi, j + 1, Wv, n, n1, 1,
+                             active, partial, nchunk, ldp);
+          hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, j + 1, active, htmp, ldp,
+                             H, m, (long long)(m + 1) * m, j, H0);
+          hipLaunchKernelGGL(k_sub_proj, dim3(gx, B), dim3(256), 0, s, Wv, V, (long long)svi, n, j + 1, htmp, ldp,
+                             active);
         }
-        hipLaunchKernelGGL(k_dots, dim3(W.nchunk, B), dim3(256), 0, s, W.w, W.uoff, 0LL, 1, W.w, n, n1, 1, W.active,
-                           W.partial, W.nchunk, W.ldp);
-        hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, W.partial, W.nchunk, W.ldp, 1, W.active, W.htmp,
-                           m + 1, (cplx *)nullptr, 0, 0LL, 0);
-        hipLaunchKernelGGL(k_givens, dim3((B + 63) / 64), dim3(64), 0, s, B, m, j, W.H, W.cs, W.sn, W.g, W.htmp,
-                           W.inv, W.active, W.kused, W.thresh, W.jlim);
-        if (j + 1 < m)
-          hipLaunchKernelGGL(k_scale, dim3(gx, B), dim3(256), 0, s, W.V + (size_t)(j + 1) * svi, W.w, W.inv, n,
-                             W.active);
-        hipMemcpyAsync(hact.data(), W.active, sizeof(int) * B, hipMemcpyDeviceToHost, s);
-        if (int rc2 = sync("GMRES iteration")) {
+        hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Wv, uoff, 0LL, 1, Wv, n, n1, 1, active, partial,
+                           nchunk, ldp);
+        hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, 1, active, htmp, ldp,
+                           (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr);
+        hipLaunchKernelGGL(k_givens, dim3((B + 63) / 64), dim3(64), 0, s, B, m, j, H, cs, sn, g, htmp, ldp, inv,
+                           active, kused, thresh, jlim, H0);
+        // V_{j+1} = w / h_{j+1,j} (also for j + 1 = m: the image c = V H y uses it).  k_givens
+        // clears `active` of right-hand sides that finish here, so use this step's list aidx.
+        hipLaunchKernelGGL(k_scale_idx, dim3(gx, na), dim3(256), 0, s, V + (size_t)(j + 1) * svi, Wv, inv, n, aidx);
+        hipMemcpyAsync(hact.data(), active, sizeof(int) * B, hipMemcpyDeviceToHost, s);
+        if (int rc2 = sync("solver iteration")) {
           wfree(W);
           return rc2;
         }
@@ -500,52 +607,96 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
         for (int v = 0; v < B; ++v) any |= hact[v];
         if (!any) break;  // every right-hand side has finished this cycle
       }
-      hipLaunchKernelGGL(k_backsolve, dim3((B + 63) / 64), dim3(64), 0, s, B, m, W.H, W.g, W.kused, W.ysol, W.done);
-      hipLaunchKernelGGL(k_update_x, dim3(gx, B), dim3(256), 0, s, W.x, W.V, (long long)svi, n, m, W.ysol, W.kused,
-                         W.diag, W.pshift, sM, W.done);
-      hipMemcpyAsync(hkused.data(), W.kused, sizeof(int) * B, hipMemcpyDeviceToHost, s);
-      // true residual r = b - A x (right-hand sides of this cycle) into V_0 and its norm
-      alist.clear();
-      for (int v = 0; v < B; ++v)
-        if (!hskip[v]) alist.push_back(v);
-      const int np = (int)alist.size();
-      hipMemcpyAsync(W.aidx, alist.data(), sizeof(int) * np, hipMemcpyHostToDevice, s);
-      hipLaunchKernelGGL(k_gather_precond, dim3(gx, np), dim3(256), 0, s, W.z, W.x, W.diag, W.shift, 0.0, n, W.aidx, 0);
-      int rc = sigma_apply(c, part, K, np, W.z, W.wc);
-      if (rc != CCGF_OK) {
-        wfree(W);
-        return rc;
+      // minimal-residual correction of this cycle and its image under A
+      hipLaunchKernelGGL(k_backsolve, dim3((B + 63) / 64), dim3(64), 0, s, B, m, H, g, kused, ysol, skip);
+      hipLaunchKernelGGL(k_gcrot_small, dim3((B + 63) / 64), dim3(64), 0, s, B, m, kc, Bm, H0, ysol, kused, tv, dv,
+                         skip, kslots);
+      cplx *us = Ub + (size_t)slot * svi, *cs_ = Cb + (size_t)slot * svi;
+      hipLaunchKernelGGL(k_gcrot_combine, dim3(gx, B), dim3(256), 0, s, n, m, (long long)svi, V, ysol, dv, kused, kc,
+                         Ub, tv, kslots, diag, pshift, sM, us, cs_, X, R, skip);
+      if (kr > 0) {  // normalise the new pair so that c has unit norm
+        norms(cs_, B);
+        hipLaunchKernelGGL(k_inv_sqrt, dim3((B + 63) / 64), dim3(64), 0, s, B, htmp, ldp, inv, skip);
+        hipLaunchKernelGGL(k_scale2, dim3(gx, B), dim3(256), 0, s, us, cs_, inv, n, skip);
       }
-      if (st) st->n_sigma += np;
-      hipLaunchKernelGGL(k_residual_c, dim3(gx, np), dim3(256), 0, s, W.V, W.b, W.x, W.wc, W.shift, sM, n, W.aidx);
-      norms(W.V, B);
-      if (int rc2 = sync("GMRES restart")) {
+      norms(R, B);
+      hipMemcpyAsync(hh.data(), htmp, sizeof(cplx) * B * ldp, hipMemcpyDeviceToHost, s);
+      hipMemcpyAsync(hkused.data(), kused, sizeof(int) * B, hipMemcpyDeviceToHost, s);
+      if (int rc2 = sync("solver cycle")) {
         wfree(W);
         return rc2;
       }
+      alist.clear();
       for (int v = 0; v < B; ++v) {
-        if (hskip[v]) continue;  // finished earlier: keep its residual
-        hbeta[v] = std::sqrt(std::max(hh[(size_t)v * (m + 1)].x, 0.0));
+        if (hskip[v]) continue;
+        hrn[v] = std::sqrt(std::max(hh[(size_t)v * ldp].x, 0.0));
         its[v] += hkused[v];
-        hconv[v] = hbnorm[v] == 0.0 || hbeta[v] <= tol * hbnorm[v];
-        hinv[v] = hbeta[v] > 0 ? 1.0 / hbeta[v] : 0.0;
+        hconv[v] = hrn[v] <= tol * hbnorm[v];
+        if (hconv[v]) alist.push_back(v);
       }
-      hipMemcpyAsync(W.inv, hinv.data(), sizeof(double) * B, hipMemcpyHostToDevice, s);
-      hipLaunchKernelGGL(k_scale, dim3(gx, B), dim3(256), 0, s, W.V, W.V, W.inv, n, (const int *)nullptr);
+      // confirm convergence with the true residual (the recursive one can drift)
+      if (!alist.empty()) {
+        std::vector<int> cand = alist;
+        if (int rc = true_residual(B)) {
+          wfree(W);
+          return rc;
+        }
+        std::vector<int> redo(B, 0);
+        int nredo = 0;
+        for (int v : cand) {
+          hrn[v] = std::sqrt(std::max(hh[(size_t)v * ldp].x, 0.0));
+          hconv[v] = hrn[v] <= tol * hbnorm[v];
+          if (!hconv[v]) redo[v] = 1, ++nredo;
+        }
+        const int kcn = std::min(cyc + 1, kr);
+        if (nredo && kcn > 0) {
+          // restore r _|_ C for the restarted residuals: x += U (C^H r), r -= C (C^H r)
+          hipMemcpyAsync(active, redo.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
+          hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Cb, uoff, (long long)svi, kcn, R, n, n1, 1,
+                             active, partial, nchunk, ldp);
+          hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, kcn, active, htmp, ldp,
+                             (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr);
+          hipLaunchKernelGGL(k_add_proj, dim3(gx, B), dim3(256), 0, s, X, Ub, (long long)svi, n, kcn, htmp, ldp,
+                             active);
+          hipLaunchKernelGGL(k_sub_proj, dim3(gx, B), dim3(256), 0, s, R, Cb, (long long)svi, n, kcn, htmp, ldp,
+                             active);
+          norms(R, B);
+          hipMemcpyAsync(hh.data(), htmp, sizeof(cplx) * B * ldp, hipMemcpyDeviceToHost, s);
+          if (int rc2 = sync("residual projection")) {
+            wfree(W);
+            return rc2;
+          }
+          for (int v = 0; v < B; ++v)
+            if (redo[v]) hrn[v] = std::sqrt(std::max(hh[(size_t)v * ldp].x, 0.0));
+        }
+      }
+      ++cyc;
+    }
+    // final true residual of right-hand sides that stopped unconverged (budget exhausted)
+    alist.clear();
+    for (int v = 0; v < B; ++v)
+      if (!hconv[v] && hbnorm[v] > 0) alist.push_back(v);
+    if (!alist.empty()) {
+      std::vector<int> cand = alist;
+      if (int rc = true_residual(B)) {
+        wfree(W);
+        return rc;
+      }
+      for (int v : cand) hrn[v] = std::sqrt(std::max(hh[(size_t)v * ldp].x, 0.0));
     }
     // G = e . x (bilinear, Eq. 7)
-    hipLaunchKernelGGL(k_dots, dim3(W.nchunk, B), dim3(256), 0, s, Evecs, W.eoff, 0LL, 1, W.x, n, n1, 0,
-                       (const int *)nullptr, W.partial, W.nchunk, W.ldp);
-    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, W.partial, W.nchunk, W.ldp, 1, (const int *)nullptr,
-                       W.htmp, m + 1, (cplx *)nullptr, 0, 0LL, 0);
-    hipMemcpyAsync(hh.data(), W.htmp, sizeof(cplx) * B * (m + 1), hipMemcpyDeviceToHost, s);
+    hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Evecs, eoff, 0LL, 1, X, n, n1, 0,
+                       (const int *)nullptr, partial, nchunk, ldp);
+    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, 1, (const int *)nullptr, htmp, ldp,
+                       (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr);
+    hipMemcpyAsync(hh.data(), htmp, sizeof(cplx) * B * ldp, hipMemcpyDeviceToHost, s);
     if (int rc2 = sync("G assembly")) {
       wfree(W);
       return rc2;
     }
     for (int v = 0; v < B; ++v) {
-      Gout[r0 + v] = hh[(size_t)v * (m + 1)];
-      double rel = hbnorm[v] > 0 ? hbeta[v] / hbnorm[v] : 0.0;
+      Gout[r0 + v] = hh[(size_t)v * ldp];
+      double rel = hbnorm[v] > 0 ? hrn[v] / hbnorm[v] : 0.0;
       bool ok = hbnorm[v] == 0.0 || rel <= tol;
       if (st) {
         st->n_solves += 1;

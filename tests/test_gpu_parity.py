@@ -76,13 +76,24 @@ GCASES = [
 ]
 
 
+# The recycling solver (GCROT(m,k), experimental) has a true-residual floor near
+# 1e-11 on some small systems, so it is run at tol 1e-10 and G is compared at 1e-8;
+# the plain GMRES path carries the 1e-10 bar.
+SOLVERS = [dict(restart_m=30, recycle_k=0, tol=1e-13), dict(restart_m=8, recycle_k=6, precond_eta=0.2, tol=1e-10)]
+GTOL = [1e-10, 1e-8]
+
+
+@pytest.mark.parametrize("solver", range(len(SOLVERS)), ids=["gmres30", "gcrot8_6"])
 @pytest.mark.parametrize("gi", range(len(GCASES)))
-def test_green_function_matches_dense_oracle(gi):
+def test_green_function_matches_dense_oracle(gi, solver):
+    """G+, G- and G of every orbital and momentum against dense inversion, with
+    restarted GMRES and with GCROT(m,k) recycling (short cycles so that several
+    recycled pairs are in play)."""
     from paper_2208_07478_amd.ccgf import Context
     s = _system(GCASES[gi])
-    print("case", GCASES[gi], flush=True)
+    print("case", GCASES[gi], SOLVERS[solver], flush=True)
     E = eom.EOMSystem(s)
-    ctx = Context(s, tol=1e-13, max_batch=32)
+    ctx = Context(s, max_batch=32, maxiter=4000, **SOLVERS[solver])
     w = np.linspace(-1.0, 1.0, 7)
     eta = 0.02
     nmo = s.nocc + s.nvir
@@ -98,7 +109,7 @@ def test_green_function_matches_dense_oracle(gi):
                 if np.abs(ref).max() == 0:
                     assert np.abs(got).max() <= 1e-14
                 else:
-                    assert np.abs(got - ref).max() / scale <= 1e-10, (K, p)
+                    assert np.abs(got - ref).max() / scale <= GTOL[solver], (K, p)
     ctx.close()
 
 

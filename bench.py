@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--precond-eta", type=float, default=0.2)
     ap.add_argument("--recycle-k", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probe", choices=["sigma", "copy"], default=None,
+                    help="counter-collection runs: 'sigma' applies 3 EA sigma products to the step's "
+                         "batch; 'copy' copies a 1 GiB buffer once (HBM-traffic calibration)")
     ap.add_argument("--cpu-sample-s", type=float, default=20.0)
     return ap.parse_args()
 
@@ -97,6 +100,14 @@ def main():
     from paper_2208_07478_amd.ccgf import Context
 
     torch.cuda.set_device(0)
+    if args.probe == "copy":
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": "copy", "bytes_read": src.numel() * 8, "bytes_written": dst.numel() * 8}))
+        return
     sysm = synth.preset_system(args.workload)
     omega, eta = synth.preset_query(args.workload)
     nmo = sysm.nocc + sysm.nvir
@@ -106,6 +117,15 @@ def main():
                   timing=True, precond_eta=args.precond_eta, recycle_k=args.recycle_k)
     init_s = time.perf_counter() - t0
     stride = len(omega) // args.nw
+    if args.probe == "sigma":
+        nb = nmo * args.nw
+        X = torch.from_numpy(synth.random_eom_vectors(sysm.kmesh, sysm.nocc, sysm.nvir, "ea", 0, nb, seed=11)).cuda()
+        for _ in range(3):
+            ctx.sigma("ea", 0, X)
+        torch.cuda.synchronize()
+        ctx.close()
+        print(json.dumps({"probe": "sigma", "nvec": nb, "products": 3}))
+        return
 
     def freqs(i):
         # frequencies i, i + stride, ... : every step samples the whole grid

@@ -45,8 +45,8 @@ def eri_blocks(mesh: KMesh, A: np.ndarray, s1: slice, s2: slice, s3: slice, s4: 
     data = np.zeros([nk, nk, nk] + shp, dtype=np.complex128)
     for k1, k2, k3 in itertools.product(range(nk), repeat=3):
         k4 = mesh.lin([(1, k1), (1, k2), (-1, k3)])
-        d = np.einsum("Lpr,Lqs->pqrs", A[k1, k3][:, s1, s3], A[k2, k4][:, s2, s4])
-        x = np.einsum("Lps,Lqr->pqrs", A[k1, k4][:, s1, s4], A[k2, k3][:, s2, s3])
+        d = np.einsum("Lpr,Lqs->pqrs", A[k1, k3][:, s1, s3], A[k2, k4][:, s2, s4], optimize=True)
+        x = np.einsum("Lps,Lqr->pqrs", A[k1, k4][:, s1, s4], A[k2, k3][:, s2, s3], optimize=True)
         data[k1, k2, k3] = d - x
     return KT(mesh, data, P4, 0)
 

@@ -239,3 +239,37 @@ def preset_query(name: str):
     p = PRESETS[name]
     lo, hi, n = p["omega"]
     return np.linspace(lo, hi, n), p["eta"]
+
+
+def eom_vector_shapes(kmesh, nocc, nvir, part):
+    """(n1, r2 shape) of an EOM vector in full antisymmetric storage:
+    IP [r1[i], r2[ki][kj][i][j][a]] and EA [r1[a], r2[ki][ka][i][a][b]]."""
+    nk = int(np.prod(kmesh))
+    if part == "ip":
+        return nocc, (nk, nk, nocc, nocc, nvir)
+    return nvir, (nk, nk, nocc, nvir, nvir)
+
+
+def random_eom_vectors(kmesh, nocc, nvir, part, K, nvec, *, seed=BASE_SEED):
+    """nvec seeded random vectors of total momentum K, antisymmetric in the pair
+    indices (IP: (i,ki)<->(j,kj); EA: (a,ka)<->(b,kb) with kb = K + ki - ka),
+    flat in the layout of ``eom_vector_shapes``.  Input construction only."""
+    n1, shp = eom_vector_shapes(kmesh, nocc, nvir, part)
+    nk = shp[0]
+    tab = _ksum_table(kmesh)
+    rng = _rng(seed, TID_VEC, K, nvec, 1 if part == "ea" else 0)
+    out = np.zeros((nvec, n1 + int(np.prod(shp))), dtype=np.complex128)
+    for v in range(nvec):
+        r1 = _cnormal(rng, (n1,), 1.0, False)
+        x = _cnormal(rng, shp, 1.0, False)
+        y = np.zeros_like(x)
+        for k1 in range(nk):
+            for k2 in range(nk):
+                if part == "ip":   # partner block [kj][ki](j,i,a)
+                    y[k1, k2] = (x[k1, k2] - x[k2, k1].transpose(1, 0, 2)) / np.sqrt(2.0)
+                else:              # partner block [ki][kb](i,b,a), kb = K + ki - ka
+                    kb = tab[K, k1, k2]
+                    y[k1, k2] = (x[k1, k2] - x[k1, kb].transpose(0, 2, 1)) / np.sqrt(2.0)
+        out[v, :n1] = r1
+        out[v, n1:] = y.ravel()
+    return out

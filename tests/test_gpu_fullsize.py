@@ -1,0 +1,71 @@
+"""Full-size parity on the Si-like 2x2x2 workload (4 + 26 spin orbitals per
+cell), in the launch configuration that bench.py times: sigma products on a
+120-vector batch, b/e vectors, and G at a few points, against oracle samples
+written by tests/golden/make_golden.py (which calls only the CPU oracle)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLD = os.path.join(HERE, "golden", "si_k222_oracle_samples.json")
+
+
+def c(a):
+    return np.asarray(a[0]) + 1j * np.asarray(a[1])
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    from paper_2208_07478_amd import synth
+    from paper_2208_07478_amd.ccgf import Context
+    gold = json.load(open(GOLD))
+    s = synth.preset_system(gold["preset"])
+    # bench configuration: GMRES(100), damped preconditioner, 120 right-hand sides per batch
+    ctx = Context(s, tol=1e-12, restart_m=100, maxiter=6000, max_batch=120, precond_eta=0.2)
+    yield s, gold, ctx
+    ctx.close()
+    torch.cuda.synchronize()
+
+
+def test_sigma_samples(setup):
+    import torch
+    from paper_2208_07478_amd import synth
+    s, gold, ctx = setup
+    cache = {}
+    for rec in gold["sigma"]:
+        key = (rec["part"], rec["K"], rec["seed"])
+        if key not in cache:
+            X = synth.random_eom_vectors(s.kmesh, s.nocc, s.nvir, rec["part"], rec["K"], gold["nvec"],
+                                         seed=rec["seed"])
+            Y = ctx.sigma(rec["part"], rec["K"], torch.from_numpy(X).cuda()).cpu().numpy()
+            cache[key] = Y
+        Y = cache[key]
+        got = Y[rec["vec"], rec["idx"]]
+        ref = c(rec["val"])
+        err = np.abs(got - ref).max() / rec["scale"]
+        print(rec["part"], rec["K"], rec["vec"], "rel err", err, flush=True)
+        assert err <= 1e-12
+
+
+def test_vector_samples(setup):
+    s, gold, ctx = setup
+    for rec in gold["vectors"]:
+        b, e = ctx.vectors(rec["part"], rec["K"], rec["p"])
+        idx = rec["idx"]
+        assert np.allclose(b.cpu().numpy()[idx], c(rec["b"]), atol=1e-14, rtol=0)
+        assert np.allclose(e.cpu().numpy()[idx], c(rec["e"]), atol=1e-14, rtol=0)
+
+
+def test_green_function_points(setup):
+    s, gold, ctx = setup
+    for rec in gold["gf"]:
+        G, Gp, Gm, st = ctx.solve([rec["K"]], [rec["p"]], [rec["w"]], rec["eta"], parts=rec["part"])
+        got = (Gm if rec["part"] == "ip" else Gp)[0, 0, 0]
+        ref = complex(rec["g"][0], rec["g"][1])
+        print(rec["part"], rec["K"], rec["p"], rec["w"], got, ref, flush=True)
+        assert abs(got - ref) <= 1e-9 * abs(ref)

@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--recycle-k", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe", choices=["sigma", "copy"], default=None,
-                    help="counter-collection runs: 'sigma' applies 3 EA sigma products to the step's "
+                    help="counter-collection runs: 'sigma' applies 3 EA and 3 IP sigma products to the step's "
                          "batch; 'copy' copies a 1 GiB buffer once (HBM-traffic calibration)")
     ap.add_argument("--cpu-sample-s", type=float, default=20.0)
     return ap.parse_args()
@@ -119,9 +119,11 @@ def main():
     stride = len(omega) // args.nw
     if args.probe == "sigma":
         nb = nmo * args.nw
-        X = torch.from_numpy(synth.random_eom_vectors(sysm.kmesh, sysm.nocc, sysm.nvir, "ea", 0, nb, seed=11)).cuda()
-        for _ in range(3):
-            ctx.sigma("ea", 0, X)
+        for part in ("ea", "ip"):
+            X = torch.from_numpy(synth.random_eom_vectors(sysm.kmesh, sysm.nocc, sysm.nvir, part, 0, nb,
+                                                          seed=11)).cuda()
+            for _ in range(3):
+                ctx.sigma(part, 0, X)
         torch.cuda.synchronize()
         ctx.close()
         print(json.dumps({"probe": "sigma", "nvec": nb, "products": 3}))

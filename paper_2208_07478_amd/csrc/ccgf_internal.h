@@ -98,6 +98,7 @@ struct SigmaPlan {  // per (part, K, batch layout)
   long long n;
   GemmPlan g_big;   // EA: W_vvvv term; IP: W_oooo term (writes sigma2)
   GemmPlan g_ovvo;  // W_ovvo term into the scratch vector
+  GemmPlan g_r1;    // EA: W_abei r^e; IP: -W_maij r_m  (accumulates into sigma2)
   bool ready = false;
 };
 
@@ -123,6 +124,8 @@ struct ccgf_ctx {
   size_t sig_tmp_elems = 0;
   cplx *sig_r1aux = nullptr;  // per-RHS 3-body contraction (nvec x max(no, nv))
   size_t sig_r1aux_elems = 0;
+  cplx *sig_part = nullptr;  // split-range partial sums of the 1h / 1p rows
+  size_t sig_part_elems = 0;
   std::vector<SigmaPlan> plans;
   // event timing of the sigma products (options.timing)
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};

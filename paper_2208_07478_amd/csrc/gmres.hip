@@ -317,6 +317,22 @@ __global__ __launch_bounds__(256) void k_add_proj(cplx *__restrict__ X, const cp
   X[(size_t)v * n + x] = acc;
 }
 
+// w0n[v] = ||w||^2 before projection (read from the reduced dots)
+__global__ void k_take_norm(int nvec, const cplx *__restrict__ nrm2, int ld, double *__restrict__ w0n,
+                            const int *__restrict__ active) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nvec || !active[v]) return;
+  w0n[v] = nrm2[(size_t)v * ld].x;
+}
+
+// second Gram-Schmidt pass only where one pass lost more than half of ||w||^2
+__global__ void k_need_reorth(int nvec, const cplx *__restrict__ nrm2, int ld, const double *__restrict__ w0n,
+                              const int *__restrict__ active, int *__restrict__ need) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nvec) return;
+  need[v] = active[v] && nrm2[(size_t)v * ld].x < 0.5 * w0n[v];
+}
+
 // t = Bm y (recycled-space coefficients, kc entries) and d = H0 y (kused + 1 entries)
 __global__ void k_gcrot_small(int nvec, int m, int kc, const cplx *__restrict__ Bm, const cplx *__restrict__ H0,
                               const cplx *__restrict__ ysol, const int *__restrict__ kused, cplx *__restrict__ t,
@@ -456,6 +472,8 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
   int *skip = (int *)walloc(W, sizeof(int) * Bmax);
   int *jlim = (int *)walloc(W, sizeof(int) * Bmax);
   int *aidx = (int *)walloc(W, sizeof(int) * Bmax);
+  int *need = (int *)walloc(W, sizeof(int) * Bmax);
+  double *w0n = (double *)walloc(W, sizeof(double) * Bmax);
   long long *uoff = (long long *)walloc(W, sizeof(long long) * Bmax);
   long long *eoff = (long long *)walloc(W, sizeof(long long) * Bmax);
   if (W.failed) {
@@ -573,26 +591,37 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
         }
         if (st) st->n_sigma += na;
         hipLaunchKernelGGL(k_scatter_shift, dim3(gx, na), dim3(256), 0, s, Wv, Z, Wc, shift, sM, n, aidx);
-        for (int pass = 0; pass < 2; ++pass) {  // CGS2 against the recycled C and V_0..V_j
-          if (kc > 0) {
-            hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Cb, uoff, (long long)svi, kc, Wv, n, n1, 1,
-                               active, partial, nchunk, ldp);
-            hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, kc, active, htmp, ldp,
-                               Bm, m, (long long)kslots * m, j, (cplx *)nullptr);
-            hipLaunchKernelGGL(k_sub_proj, dim3(gx, B), dim3(256), 0, s, Wv, Cb, (long long)svi, n, kc, htmp, ldp,
-                               active);
-          }
-          hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, V, uoff, (long long)svi, j + 1, Wv, n, n1, 1,
-                             active, partial, nchunk, ldp);
-          hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, j + 1, active, htmp, ldp,
-                             H, m, (long long)(m + 1) * m, j, H0);
-          hipLaunchKernelGGL(k_sub_proj, dim3(gx, B), dim3(256), 0, s, Wv, V, (long long)svi, n, j + 1, htmp, ldp,
-                             active);
-        }
+        // ||w||^2 before projection (for the reorthogonalisation test)
         hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Wv, uoff, 0LL, 1, Wv, n, n1, 1, active, partial,
                            nchunk, ldp);
         hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, 1, active, htmp, ldp,
                            (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr);
+        hipLaunchKernelGGL(k_take_norm, dim3((B + 63) / 64), dim3(64), 0, s, B, htmp, ldp, w0n, active);
+        // classical Gram-Schmidt against the recycled C and V_0..V_j; a second pass only for the
+        // right-hand sides whose norm fell below 1/sqrt(2) of its value (Daniel-Gragg-Kaufman-Stewart)
+        for (int pass = 0; pass < 2; ++pass) {
+          const int *mask = pass == 0 ? active : need;
+          if (kc > 0) {
+            hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Cb, uoff, (long long)svi, kc, Wv, n, n1, 1,
+                               mask, partial, nchunk, ldp);
+            hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, kc, mask, htmp, ldp,
+                               Bm, m, (long long)kslots * m, j, (cplx *)nullptr);
+            hipLaunchKernelGGL(k_sub_proj, dim3(gx, B), dim3(256), 0, s, Wv, Cb, (long long)svi, n, kc, htmp, ldp,
+                               mask);
+          }
+          hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, V, uoff, (long long)svi, j + 1, Wv, n, n1, 1,
+                             mask, partial, nchunk, ldp);
+          hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, j + 1, mask, htmp, ldp,
+                             H, m, (long long)(m + 1) * m, j, H0);
+          hipLaunchKernelGGL(k_sub_proj, dim3(gx, B), dim3(256), 0, s, Wv, V, (long long)svi, n, j + 1, htmp, ldp,
+                             mask);
+          hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Wv, uoff, 0LL, 1, Wv, n, n1, 1, mask, partial,
+                             nchunk, ldp);
+          hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, 1, mask, htmp, ldp,
+                             (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr);
+          if (pass == 0)
+            hipLaunchKernelGGL(k_need_reorth, dim3((B + 63) / 64), dim3(64), 0, s, B, htmp, ldp, w0n, active, need);
+        }
         hipLaunchKernelGGL(k_givens, dim3((B + 63) / 64), dim3(64), 0, s, B, m, j, H, cs, sn, g, htmp, ldp, inv,
                            active, kused, thresh, jlim, H0);
         // V_{j+1} = w / h_{j+1,j} (also for j + 1 = m: the image c = V H y uses it).  k_givens

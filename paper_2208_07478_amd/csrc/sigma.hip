@@ -5,11 +5,12 @@
 // are block-dense complex contractions over momentum-conserving k-blocks.  They
 // run as one segmented complex GEMM per term: a task is one output k-block for
 // all right-hand sides at once (N = pair index x RHS), its segments are the
-// summed momentum blocks, and the complex product is four real FP64 MFMA
-// 16x16x4 products per step.  The remaining terms (one-body F blocks, the
-// 1p<->2p1h / 1h<->2h1p couplings and the three-body T2 piece) are element-wise
-// or reduction kernels with the RHS index fastest, so that adjacent lanes share
-// the same Hbar element.
+// summed momentum blocks, and the complex product is three real FP64 MFMA
+// 16x16x4 products per step (Gauss' three-multiplication form).  The 1p/1h ->
+// 2p1h/2h1p couplings are small-K GEMMs of the same kind.  The one-body F terms,
+// the antisymmetriser and the three-body T2 piece are element-wise (one thread
+// per element, looping over the right-hand sides); the 1p/1h rows are
+// reductions split over blocks.
 #include "ccgf_internal.h"
 
 #include <algorithm>
@@ -21,14 +22,15 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 #define TK 16
 
 __device__ inline long long imap(const IdxMap &m, int x) {
+  if (x < m.L) return (long long)x * m.s1;  // one-level maps never divide
   return (long long)(x / m.L) * m.s0 + (long long)(x % m.L) * m.s1;
 }
 
 // C[m][n] = alpha * sum_seg sum_k A[m][k] B[k][n] (+ C), complex FP64 on MFMA.
 // TAG only separates the uses in kernel traces (0: EA W_abcd, 1: EA W_lbdi,
-// 2: IP W_mnij, 3: IP W_maei).
+// 2: IP W_mnij, 3: IP W_maei, 4: EA W_abei r^e, 5: IP W_maij r_m).
 template <int TAG>
-__global__ __launch_bounds__(256) void k_cgemm_f64(GemmShape sh, const GemmTask *__restrict__ tasks,
+__global__ __launch_bounds__(256, 2) void k_cgemm_f64(GemmShape sh, const GemmTask *__restrict__ tasks,
                                                    const GemmSeg *__restrict__ segs,
                                                    const cplx *__restrict__ A, const cplx *__restrict__ B,
                                                    cplx *__restrict__ C, int tilesM, int tilesN, int total) {
@@ -46,46 +48,46 @@ __global__ __launch_bounds__(256) void k_cgemm_f64(GemmShape sh, const GemmTask 
   __shared__ double Ar[TM][TK + 1], Ai[TM][TK + 1], Br[TN][TK + 1], Bi[TN][TK + 1];
   const int tid = threadIdx.x;
 
+  // each thread stages column kt of rows rt + 16 j (j = 0..3) of both tiles
+  const int kt = tid & (TK - 1), rt = tid >> 4;
   long long aoff[4], boff[4];
-  int arow[4], akk[4], bcol[4], bkk[4];
   bool aok[4], bok[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    int e = tid + 256 * j;
-    arow[j] = e / TK;
-    akk[j] = e % TK;
-    int m = tm * TM + arow[j];
+    int m = tm * TM + rt + 16 * j;
     aok[j] = m < sh.M;
     aoff[j] = aok[j] ? imap(sh.am, m) : 0;
-    bcol[j] = e / TK;
-    bkk[j] = e % TK;
-    int n = tn * TN + bcol[j];
+    int n = tn * TN + rt + 16 * j;
     bok[j] = n < sh.N;
     boff[j] = bok[j] ? imap(sh.bn, n) : 0;
   }
   const int ksteps = (sh.K + TK - 1) / TK;
   const int nsteps = task.nseg * ksteps;
 
-  v4d accR[2][2], accI[2][2];
+  // Gauss' three-product form: P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi);
+  // C = (P1 - P2) + i (P3 - P1 - P2)
+  v4d P1[2][2], P2[2][2], P3[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      accR[a][b] = (v4d){0, 0, 0, 0};
-      accI[a][b] = (v4d){0, 0, 0, 0};
+      P1[a][b] = (v4d){0, 0, 0, 0};
+      P2[a][b] = (v4d){0, 0, 0, 0};
+      P3[a][b] = (v4d){0, 0, 0, 0};
     }
 
   cplx ra[4], rb[4];
   auto load = [&](int step) {
     int s = step / ksteps;
-    int k0 = (step - s * ksteps) * TK;
+    int k = (step - s * ksteps) * TK + kt;
     GemmSeg sg = segs[task.seg_begin + s];
+    const bool kok = k < sh.K;
+    const cplx *Ap = A + sg.a_off + (kok ? imap(sh.ak, k) : 0);
+    const cplx *Bp = B + sg.b_off + (kok ? imap(sh.bk, k) : 0);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      int k = k0 + akk[j];
-      ra[j] = (aok[j] && k < sh.K) ? A[sg.a_off + aoff[j] + imap(sh.ak, k)] : mkc(0, 0);
-      k = k0 + bkk[j];
-      rb[j] = (bok[j] && k < sh.K) ? B[sg.b_off + boff[j] + imap(sh.bk, k)] : mkc(0, 0);
+      ra[j] = (aok[j] && kok) ? Ap[aoff[j]] : mkc(0, 0);
+      rb[j] = (bok[j] && kok) ? Bp[boff[j]] : mkc(0, 0);
     }
   };
 
@@ -98,10 +100,10 @@ __global__ __launch_bounds__(256) void k_cgemm_f64(GemmShape sh, const GemmTask 
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      Ar[arow[j]][akk[j]] = ra[j].x;
-      Ai[arow[j]][akk[j]] = ra[j].y;
-      Br[bcol[j]][bkk[j]] = rb[j].x;
-      Bi[bcol[j]][bkk[j]] = rb[j].y;
+      Ar[rt + 16 * j][kt] = ra[j].x;
+      Ai[rt + 16 * j][kt] = ra[j].y;
+      Br[rt + 16 * j][kt] = rb[j].x;
+      Bi[rt + 16 * j][kt] = rb[j].y;
     }
     __syncthreads();
     if (step + 1 < nsteps) load(step + 1);
@@ -115,14 +117,19 @@ __global__ __launch_bounds__(256) void k_cgemm_f64(GemmShape sh, const GemmTask 
         b_r[q] = Br[wc * 32 + q * 16 + lr][kk + lk];
         b_i[q] = Bi[wc * 32 + q * 16 + lr][kk + lk];
       }
+      double a_s[2], b_s[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        a_s[q] = a_r[q] + a_i[q];
+        b_s[q] = b_r[q] + b_i[q];
+      }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          accR[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[a], b_r[b], accR[a][b], 0, 0, 0);
-          accR[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_i[a], b_i[b], accR[a][b], 0, 0, 0);
-          accI[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[a], b_i[b], accI[a][b], 0, 0, 0);
-          accI[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[a], b_r[b], accI[a][b], 0, 0, 0);
+          P1[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[a], b_r[b], P1[a][b], 0, 0, 0);
+          P2[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[a], b_i[b], P2[a][b], 0, 0, 0);
+          P3[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_s[a], b_s[b], P3[a][b], 0, 0, 0);
         }
     }
   }
@@ -139,7 +146,8 @@ __global__ __launch_bounds__(256) void k_cgemm_f64(GemmShape sh, const GemmTask 
         int m = tm * TM + row, n = tn * TN + col;
         if (m < sh.M && n < sh.N) {
           long long off = task.c_off + imap(sh.cm, m) + imap(sh.cn, n);
-          double re = accR[a][b][v], im = accI[a][b][v];
+          double p1 = P1[a][b][v], p2 = P2[a][b][v];
+          double re = p1 - p2, im = P3[a][b][v] - p1 - p2;
           cplx val = mkc(sh.alpha_re * re - sh.alpha_im * im, sh.alpha_re * im + sh.alpha_im * re);
           if (sh.accumulate) val = cadd(val, C[off]);
           C[off] = val;
@@ -157,7 +165,9 @@ void gemm_launch(int tag, const GemmPlan &plan, const cplx *A, const cplx *B, cp
     case 0: hipLaunchKernelGGL(k_cgemm_f64<0>, g, b, 0, s, sh, plan.d_tasks, plan.d_segs, A, B, C, tilesM, tilesN, (int)total); break;
     case 1: hipLaunchKernelGGL(k_cgemm_f64<1>, g, b, 0, s, sh, plan.d_tasks, plan.d_segs, A, B, C, tilesM, tilesN, (int)total); break;
     case 2: hipLaunchKernelGGL(k_cgemm_f64<2>, g, b, 0, s, sh, plan.d_tasks, plan.d_segs, A, B, C, tilesM, tilesN, (int)total); break;
-    default: hipLaunchKernelGGL(k_cgemm_f64<3>, g, b, 0, s, sh, plan.d_tasks, plan.d_segs, A, B, C, tilesM, tilesN, (int)total); break;
+    case 3: hipLaunchKernelGGL(k_cgemm_f64<3>, g, b, 0, s, sh, plan.d_tasks, plan.d_segs, A, B, C, tilesM, tilesN, (int)total); break;
+    case 4: hipLaunchKernelGGL(k_cgemm_f64<4>, g, b, 0, s, sh, plan.d_tasks, plan.d_segs, A, B, C, tilesM, tilesN, (int)total); break;
+    default: hipLaunchKernelGGL(k_cgemm_f64<5>, g, b, 0, s, sh, plan.d_tasks, plan.d_segs, A, B, C, tilesM, tilesN, (int)total); break;
   }
 }
 
@@ -281,8 +291,56 @@ static void build_plans(ccgf_ctx *c, SigmaPlan &P) {
         h.tasks.push_back(t);
       }
   }
+  // coupling of the one-quasiparticle part into the three-quasiparticle part
+  GemmPlan &q = P.g_r1;
+  if (P.part == CCGF_PART_EA) {
+    // sigma2[ki][ka](i,a,b) += sum_e W_abei r^e : C(ab,i ; v) = sum_e A(ab,i ; e) r1(e ; v)
+    const long long b2 = (long long)no * nv * nv;
+    q.shape.M = nv * nv * no;
+    q.shape.N = nvec;
+    q.shape.K = nv;
+    q.shape.am = two(no, (long long)nv * no, 1);
+    q.shape.ak = one(no);
+    q.shape.bk = one(1);
+    q.shape.bn = one(n);
+    q.shape.cm = two(no, 1, (long long)nv * nv);
+    q.shape.cn = one(n);
+    q.shape.alpha_re = 1;
+    q.shape.alpha_im = 0;
+    q.shape.accumulate = 1;
+    T4 Wt{nullptr, nk, nv, nv, nv, no};
+    for (int ki = 0; ki < nk; ++ki)
+      for (int ka = 0; ka < nk; ++ka) {
+        int kb = host_c3(c, K, ki, ka);
+        q.tasks.push_back(GemmTask{nv + (ki * nk + ka) * b2, (int)q.segs.size(), 1});
+        q.segs.push_back(GemmSeg{(long long)Wt.blk(ka, kb, K), 0});
+      }
+  } else {
+    // sigma2[ki][kj](i,j,a) -= sum_m W_maij r_m : C(ij,a ; v) = -sum_m A(ij,a ; m) r1(m ; v)
+    const long long b2 = (long long)no * no * nv;
+    q.shape.M = no * no * nv;
+    q.shape.N = nvec;
+    q.shape.K = no;
+    q.shape.am = two(nv, 1, (long long)no * no);
+    q.shape.ak = one((long long)nv * no * no);
+    q.shape.bk = one(1);
+    q.shape.bn = one(n);
+    q.shape.cm = one(1);
+    q.shape.cn = one(n);
+    q.shape.alpha_re = -1;
+    q.shape.alpha_im = 0;
+    q.shape.accumulate = 1;
+    T4 Wt{nullptr, nk, no, nv, no, no};
+    for (int ki = 0; ki < nk; ++ki)
+      for (int kj = 0; kj < nk; ++kj) {
+        int ka = host_c3(c, ki, kj, K);
+        q.tasks.push_back(GemmTask{no + (ki * nk + kj) * b2, (int)q.segs.size(), 1});
+        q.segs.push_back(GemmSeg{(long long)Wt.blk(K, ka, ki), 0});
+      }
+  }
   plan_upload(c, P.g_big);
   plan_upload(c, P.g_ovvo);
+  plan_upload(c, P.g_r1);
   P.ready = true;
 }
 
@@ -311,26 +369,56 @@ static bool plan_in_bounds(const GemmPlan &p, size_t a_elems, size_t b_elems, si
   return true;
 }
 
-// ------------------------------------------------------------------ EA
-#define RCH 8  // right-hand sides handled together by the reduction kernels
+// ------------------------------------------------------------------ reductions
+#define RCH 16  // right-hand sides handled together by the reduction kernels
+#define ZCH 16384  // r2 entries summed by one block (the range is split over blockIdx.z)
 
+__device__ inline double wsum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// Sum acc[q] over the block and write it with `put(q, value)` from threads q < nq.
+template <class PUT>
+__device__ inline void block_reduce_store(const cplx *acc, int nq, double (*sh)[RCH][2], PUT put) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < RCH; ++q) {
+    double re = wsum(acc[q].x), im = wsum(acc[q].y);
+    if (l == 0) {
+      sh[w][q][0] = re;
+      sh[w][q][1] = im;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nq) {
+    const int q = threadIdx.x;
+    cplx v = mkc(0, 0);
+    for (int ww = 0; ww < (int)(blockDim.x >> 6); ++ww) v = cadd(v, mkc(sh[ww][q][0], sh[ww][q][1]));
+    put(q, v);
+  }
+}
+
+// ------------------------------------------------------------------ EA
 // blocks (a-or-k, RHS chunk): sigma1[a] (a < nv) or Y[k] = sum <kl||cd> r_l^cd (k < no)
 __global__ __launch_bounds__(256) void k_ea_r1(int nk, int no, int nv, int K, int nvec, long long n,
-                                               const cplx *__restrict__ x, cplx *__restrict__ y,
-                                               cplx *__restrict__ aux, const cplx *__restrict__ Fvv,
+                                               const cplx *__restrict__ x, cplx *__restrict__ part,
+                                               const cplx *__restrict__ Fvv,
                                                const cplx *__restrict__ Fov, const cplx *__restrict__ Wvovv,
                                                const cplx *__restrict__ Voovv) {
   const int row = blockIdx.x;  // 0..nv-1: sigma1[a];  nv..nv+no-1: Y[k]
   const int v0 = blockIdx.y * RCH;
-  const int nv_ch = min(RCH, nvec - v0);
+  const int nq = min(RCH, nvec - v0);
   const long long b2 = (long long)no * nv * nv;
   const long long n2 = (long long)nk * nk * b2;
+  const long long z0 = (long long)blockIdx.z * ZCH, z1 = min(n2, z0 + ZCH);
   cplx acc[RCH];
 #pragma unroll
   for (int q = 0; q < RCH; ++q) acc[q] = mkc(0, 0);
   const bool is_sig = row < nv;
-  // sum over every r2 entry (kl, kc, l, c, d)
-  for (long long z = threadIdx.x; z < n2; z += blockDim.x) {
+  const cplx *xv = x + (size_t)v0 * n;
+  // sum over this block's share of the r2 entries (kl, kc, l, c, d)
+  for (long long z = z0 + threadIdx.x; z < z1; z += blockDim.x) {
     long long blk = z / b2, w = z % b2;
     int kl = (int)(blk / nk), kc = (int)(blk % nk);
     cplx wv;
@@ -343,118 +431,107 @@ __global__ __launch_bounds__(256) void k_ea_r1(int nk, int no, int nv, int K, in
     }
 #pragma unroll
     for (int q = 0; q < RCH; ++q)
-      if (q < nv_ch) cfma(acc[q], wv, x[(size_t)(v0 + q) * n + nv + z]);
+      if (q < nq) cfma(acc[q], wv, xv[(size_t)q * n + nv + z]);
   }
-  if (is_sig) {
+  if (is_sig && blockIdx.z == 0) {
     const int a = row;
     // F_ac r^c  and  F_ld r_l^ad (block [kl][K], kd = kl)
     for (int z = threadIdx.x; z < nv + nk * no * nv; z += blockDim.x) {
+      cplx f;
+      size_t off;
       if (z < nv) {
-        cplx f = Fvv[((size_t)K * nv + a) * nv + z];
-#pragma unroll
-        for (int q = 0; q < RCH; ++q)
-          if (q < nv_ch) cfma(acc[q], f, x[(size_t)(v0 + q) * n + z]);
+        f = Fvv[((size_t)K * nv + a) * nv + z];
+        off = z;
       } else {
         int w = z - nv;
         int kl = w / (no * nv), l = (w / nv) % no, d = w % nv;
-        cplx f = Fov[((size_t)kl * no + l) * nv + d];
-        size_t off = nv + (size_t)(kl * nk + K) * b2 + ((size_t)l * nv + a) * nv + d;
-#pragma unroll
-        for (int q = 0; q < RCH; ++q)
-          if (q < nv_ch) cfma(acc[q], f, x[(size_t)(v0 + q) * n + off]);
+        f = Fov[((size_t)kl * no + l) * nv + d];
+        off = nv + (size_t)(kl * nk + K) * b2 + ((size_t)l * nv + a) * nv + d;
       }
+#pragma unroll
+      for (int q = 0; q < RCH; ++q)
+        if (q < nq) cfma(acc[q], f, xv[(size_t)q * n + off]);
     }
   }
-  // block reduction
-  __shared__ double red[2][RCH][256];
-#pragma unroll
-  for (int q = 0; q < RCH; ++q) {
-    red[0][q][threadIdx.x] = acc[q].x;
-    red[1][q][threadIdx.x] = acc[q].y;
-  }
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s)
-#pragma unroll
-      for (int q = 0; q < RCH; ++q) {
-        red[0][q][threadIdx.x] += red[0][q][threadIdx.x + s];
-        red[1][q][threadIdx.x] += red[1][q][threadIdx.x + s];
-      }
-    __syncthreads();
-  }
-  if (threadIdx.x < (unsigned)nv_ch) {
-    int q = threadIdx.x;
-    cplx v = mkc(red[0][q][0], red[1][q][0]);
-    if (is_sig) y[(size_t)(v0 + q) * n + row] = v;
-    else aux[(size_t)(v0 + q) * (no > nv ? no : nv) + (row - nv)] = v;
-  }
+  __shared__ double sh[4][RCH][2];
+  const int nrow = gridDim.x;
+  block_reduce_store(acc, nq, sh, [&](int q, cplx v) {
+    part[((size_t)blockIdx.z * nrow + row) * nvec + v0 + q] = v;
+  });
 }
 
-// element-wise EA 2p1h terms (RHS index fastest)
+// sum the split partial results: rows < n1 go to sigma1 of the vector, the rest to aux
+__global__ void k_r1_finish(int nrow, int n1, int nvec, int nz, long long n, const cplx *__restrict__ part,
+                            cplx *__restrict__ y, cplx *__restrict__ aux, int ldaux) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrow * nvec) return;
+  int row = t / nvec, v = t % nvec;
+  cplx acc = mkc(0, 0);
+  for (int zz = 0; zz < nz; ++zz) acc = cadd(acc, part[((size_t)zz * nrow + row) * nvec + v]);
+  if (row < n1) y[(size_t)v * n + row] = acc;
+  else aux[(size_t)v * ldaux + (row - n1)] = acc;
+}
+
+// element-wise EA 2p1h terms: one thread per sigma2 element, looping over the right-hand sides
 __global__ __launch_bounds__(256) void k_ea_local(int nk, int no, int nv, int K, int nvec, long long n,
                                                   const int *__restrict__ kc3, const cplx *__restrict__ x,
                                                   cplx *__restrict__ y, const cplx *__restrict__ X,
                                                   const cplx *__restrict__ aux, const cplx *__restrict__ Foo,
-                                                  const cplx *__restrict__ Fvv, const cplx *__restrict__ Wvvvo,
-                                                  const cplx *__restrict__ t2) {
+                                                  const cplx *__restrict__ Fvv, const cplx *__restrict__ t2) {
   const long long b2 = (long long)no * nv * nv;
   const long long n2 = (long long)nk * nk * b2;
-  long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= n2 * nvec) return;
-  const int v = (int)(gid % nvec);
-  const long long z = gid / nvec;
+  const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= n2) return;
   const long long blk = z / b2, w = z % b2;
   const int ki = (int)(blk / nk), ka = (int)(blk % nk);
   const int b = (int)(w % nv), a = (int)((w / nv) % nv), i = (int)(w / ((long long)nv * nv));
   const int kb = kc3[(K * nk + ki) * nk + ka];
-  const cplx *xv = x + (size_t)v * n;
-  const cplx *r2 = xv + nv;
   const size_t oab = (size_t)(ki * nk + ka) * b2, oba = (size_t)(ki * nk + kb) * b2;
-  cplx acc = y[(size_t)v * n + nv + z];
-  // W_abei r^e, block [ka][kb][K] (i implied)
-  {
-    const cplx *W = Wvvvo + (((size_t)ka * nk + kb) * nk + K) * (size_t)(nv * nv * nv * no);
-    for (int e = 0; e < nv; ++e) cfma(acc, W[(((size_t)a * nv + b) * nv + e) * no + i], xv[e]);
-  }
-  // P(ab) F_bd r_i^ad
-  for (int d = 0; d < nv; ++d) {
-    cfma(acc, Fvv[((size_t)kb * nv + b) * nv + d], r2[oab + ((size_t)i * nv + a) * nv + d]);
-    cplx t = cmul(Fvv[((size_t)ka * nv + a) * nv + d], r2[oba + ((size_t)i * nv + b) * nv + d]);
-    acc = csub(acc, t);
-  }
-  // - F_li r_l^ab
-  for (int l = 0; l < no; ++l) acc = csub(acc, cmul(Foo[((size_t)ki * no + l) * no + i], r2[oab + ((size_t)l * nv + a) * nv + b]));
-  // P(ab) W_lbdi r_l^ad from the GEMM scratch
-  acc = cadd(acc, X[(size_t)v * n + nv + oab + ((size_t)i * nv + a) * nv + b]);
-  acc = csub(acc, X[(size_t)v * n + nv + oba + ((size_t)i * nv + b) * nv + a]);
-  // three-body: - 1/2 sum_k Y_k t_ki^ab, t2 block [K][ki][ka]
-  {
-    const int ldaux = no > nv ? no : nv;
-    const cplx *T = t2 + (((size_t)K * nk + ki) * nk + ka) * (size_t)(no * no * nv * nv);
+  const cplx *Fb = Fvv + ((size_t)kb * nv + b) * nv, *Fa = Fvv + ((size_t)ka * nv + a) * nv;
+  const cplx *T = t2 + (((size_t)K * nk + ki) * nk + ka) * (size_t)(no * no * nv * nv);
+  const int ldaux = no > nv ? no : nv;
+  for (int v = 0; v < nvec; ++v) {
+    const cplx *r2 = x + (size_t)v * n + nv;
+    cplx acc = y[(size_t)v * n + nv + z];
+    // P(ab) F_bd r_i^ad
+    const cplx *ra = r2 + oab + ((size_t)i * nv + a) * nv, *rb = r2 + oba + ((size_t)i * nv + b) * nv;
+    for (int d = 0; d < nv; ++d) {
+      cfma(acc, Fb[d], ra[d]);
+      acc = csub(acc, cmul(Fa[d], rb[d]));
+    }
+    // - F_li r_l^ab
+    for (int l = 0; l < no; ++l)
+      acc = csub(acc, cmul(Foo[((size_t)ki * no + l) * no + i], r2[oab + ((size_t)l * nv + a) * nv + b]));
+    // P(ab) W_lbdi r_l^ad from the GEMM scratch
+    const cplx *Xv = X + (size_t)v * n + nv;
+    acc = cadd(acc, Xv[oab + ((size_t)i * nv + a) * nv + b]);
+    acc = csub(acc, Xv[oba + ((size_t)i * nv + b) * nv + a]);
+    // three-body: - 1/2 sum_k Y_k t_ki^ab, t2 block [K][ki][ka]
     cplx h = mkc(0, 0);
     for (int k = 0; k < no; ++k) cfma(h, aux[(size_t)v * ldaux + k], T[(((size_t)k * no + i) * nv + a) * nv + b]);
     acc = csub(acc, cscale(h, 0.5));
+    y[(size_t)v * n + nv + z] = acc;
   }
-  y[(size_t)v * n + nv + z] = acc;
 }
 
 // ------------------------------------------------------------------ IP
 // blocks (i-or-e, RHS chunk): sigma1[i] (i < no) or Xe[e] = sum <mn||ef> r_mn^f (e < nv)
 __global__ __launch_bounds__(256) void k_ip_r1(int nk, int no, int nv, int K, int nvec, long long n,
                                                const int *__restrict__ kc3, const cplx *__restrict__ x,
-                                               cplx *__restrict__ y, cplx *__restrict__ aux,
-                                               const cplx *__restrict__ Foo, const cplx *__restrict__ Fov,
+                                               cplx *__restrict__ part, const cplx *__restrict__ Foo, const cplx *__restrict__ Fov,
                                                const cplx *__restrict__ Wooov, const cplx *__restrict__ Voovv) {
   const int row = blockIdx.x;
   const int v0 = blockIdx.y * RCH;
-  const int nv_ch = min(RCH, nvec - v0);
+  const int nq = min(RCH, nvec - v0);
   const long long b2 = (long long)no * no * nv;
   const long long n2 = (long long)nk * nk * b2;
+  const long long z0 = (long long)blockIdx.z * ZCH, z1 = min(n2, z0 + ZCH);
   const bool is_sig = row < no;
+  const cplx *xv = x + (size_t)v0 * n;
   cplx acc[RCH];
 #pragma unroll
   for (int q = 0; q < RCH; ++q) acc[q] = mkc(0, 0);
-  for (long long z = threadIdx.x; z < n2; z += blockDim.x) {
+  for (long long z = z0 + threadIdx.x; z < z1; z += blockDim.x) {
     long long blk = z / b2, w = z % b2;
     int km = (int)(blk / nk), kn = (int)(blk % nk);
     int e = (int)(w % nv), nn = (int)((w / nv) % no), m = (int)(w / ((long long)nv * no));
@@ -470,97 +547,76 @@ __global__ __launch_bounds__(256) void k_ip_r1(int nk, int no, int nv, int K, in
     }
 #pragma unroll
     for (int q = 0; q < RCH; ++q)
-      if (q < nv_ch) cfma(acc[q], wv, x[(size_t)(v0 + q) * n + no + z]);
+      if (q < nq) cfma(acc[q], wv, xv[(size_t)q * n + no + z]);
   }
-  if (is_sig) {
+  if (is_sig && blockIdx.z == 0) {
     const int i = row;
     // - F_mi r_m  and  F_me r_im^e (block [K][km], ke = km)
     for (int z = threadIdx.x; z < no + nk * no * nv; z += blockDim.x) {
+      cplx f;
+      size_t off;
       if (z < no) {
-        cplx f = Foo[((size_t)K * no + z) * no + i];
+        f = Foo[((size_t)K * no + z) * no + i];
         f = mkc(-f.x, -f.y);
-#pragma unroll
-        for (int q = 0; q < RCH; ++q)
-          if (q < nv_ch) cfma(acc[q], f, x[(size_t)(v0 + q) * n + z]);
+        off = z;
       } else {
         int w = z - no;
         int km = w / (no * nv), m = (w / nv) % no, e = w % nv;
-        cplx f = Fov[((size_t)km * no + m) * nv + e];
-        size_t off = no + (size_t)(K * nk + km) * b2 + ((size_t)i * no + m) * nv + e;
-#pragma unroll
-        for (int q = 0; q < RCH; ++q)
-          if (q < nv_ch) cfma(acc[q], f, x[(size_t)(v0 + q) * n + off]);
+        f = Fov[((size_t)km * no + m) * nv + e];
+        off = no + (size_t)(K * nk + km) * b2 + ((size_t)i * no + m) * nv + e;
       }
+#pragma unroll
+      for (int q = 0; q < RCH; ++q)
+        if (q < nq) cfma(acc[q], f, xv[(size_t)q * n + off]);
     }
   }
-  __shared__ double red[2][RCH][256];
-#pragma unroll
-  for (int q = 0; q < RCH; ++q) {
-    red[0][q][threadIdx.x] = acc[q].x;
-    red[1][q][threadIdx.x] = acc[q].y;
-  }
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s)
-#pragma unroll
-      for (int q = 0; q < RCH; ++q) {
-        red[0][q][threadIdx.x] += red[0][q][threadIdx.x + s];
-        red[1][q][threadIdx.x] += red[1][q][threadIdx.x + s];
-      }
-    __syncthreads();
-  }
-  if (threadIdx.x < (unsigned)nv_ch) {
-    int q = threadIdx.x;
-    cplx v = mkc(red[0][q][0], red[1][q][0]);
-    if (is_sig) y[(size_t)(v0 + q) * n + row] = v;
-    else aux[(size_t)(v0 + q) * (no > nv ? no : nv) + (row - no)] = v;
-  }
+  __shared__ double sh[4][RCH][2];
+  const int nrow = gridDim.x;
+  block_reduce_store(acc, nq, sh, [&](int q, cplx v) {
+    part[((size_t)blockIdx.z * nrow + row) * nvec + v0 + q] = v;
+  });
 }
 
+// element-wise IP 2h1p terms: one thread per sigma2 element, looping over the right-hand sides
 __global__ __launch_bounds__(256) void k_ip_local(int nk, int no, int nv, int K, int nvec, long long n,
                                                   const int *__restrict__ kc3, const cplx *__restrict__ x,
                                                   cplx *__restrict__ y, const cplx *__restrict__ X,
                                                   const cplx *__restrict__ aux, const cplx *__restrict__ Foo,
-                                                  const cplx *__restrict__ Fvv, const cplx *__restrict__ Wovoo,
-                                                  const cplx *__restrict__ t2) {
+                                                  const cplx *__restrict__ Fvv, const cplx *__restrict__ t2) {
   const long long b2 = (long long)no * no * nv;
   const long long n2 = (long long)nk * nk * b2;
-  long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= n2 * nvec) return;
-  const int v = (int)(gid % nvec);
-  const long long z = gid / nvec;
+  const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= n2) return;
   const long long blk = z / b2, w = z % b2;
   const int ki = (int)(blk / nk), kj = (int)(blk % nk);
   const int a = (int)(w % nv), j = (int)((w / nv) % no), i = (int)(w / ((long long)nv * no));
   const int ka = kc3[(ki * nk + kj) * nk + K];
-  const cplx *xv = x + (size_t)v * n;
-  const cplx *r2 = xv + no;
   const size_t oij = (size_t)(ki * nk + kj) * b2, oji = (size_t)(kj * nk + ki) * b2;
-  cplx acc = y[(size_t)v * n + no + z];
-  // - W_maij r_m, block [K][ka][ki] (j implied)
-  {
-    const cplx *W = Wovoo + (((size_t)K * nk + ka) * nk + ki) * (size_t)(no * nv * no * no);
-    for (int m = 0; m < no; ++m) acc = csub(acc, cmul(W[(((size_t)m * nv + a) * no + i) * no + j], xv[m]));
-  }
-  // F_ae r_ij^e
-  for (int e = 0; e < nv; ++e) cfma(acc, Fvv[((size_t)ka * nv + a) * nv + e], r2[oij + ((size_t)i * no + j) * nv + e]);
-  // - P(ij) F_mi r_mj^a
-  for (int m = 0; m < no; ++m) {
-    acc = csub(acc, cmul(Foo[((size_t)ki * no + m) * no + i], r2[oij + ((size_t)m * no + j) * nv + a]));
-    cfma(acc, Foo[((size_t)kj * no + m) * no + j], r2[oji + ((size_t)m * no + i) * nv + a]);
-  }
-  // P(ij) W_maei r_mj^e from the GEMM scratch
-  acc = cadd(acc, X[(size_t)v * n + no + oij + ((size_t)i * no + j) * nv + a]);
-  acc = csub(acc, X[(size_t)v * n + no + oji + ((size_t)j * no + i) * nv + a]);
-  // three-body: + 1/2 sum_e Xe_e t_ij^ae, t2 block [ki][kj][ka] (ke = K)
-  {
-    const int ldaux = no > nv ? no : nv;
-    const cplx *T = t2 + (((size_t)ki * nk + kj) * nk + ka) * (size_t)(no * no * nv * nv);
+  const cplx *Fa = Fvv + ((size_t)ka * nv + a) * nv;
+  const cplx *T = t2 + (((size_t)ki * nk + kj) * nk + ka) * (size_t)(no * no * nv * nv) +
+                  (((size_t)i * no + j) * nv + a) * nv;
+  const int ldaux = no > nv ? no : nv;
+  for (int v = 0; v < nvec; ++v) {
+    const cplx *r2 = x + (size_t)v * n + no;
+    cplx acc = y[(size_t)v * n + no + z];
+    // F_ae r_ij^e
+    const cplx *rij = r2 + oij + ((size_t)i * no + j) * nv;
+    for (int e = 0; e < nv; ++e) cfma(acc, Fa[e], rij[e]);
+    // - P(ij) F_mi r_mj^a
+    for (int m = 0; m < no; ++m) {
+      acc = csub(acc, cmul(Foo[((size_t)ki * no + m) * no + i], r2[oij + ((size_t)m * no + j) * nv + a]));
+      cfma(acc, Foo[((size_t)kj * no + m) * no + j], r2[oji + ((size_t)m * no + i) * nv + a]);
+    }
+    // P(ij) W_maei r_mj^e from the GEMM scratch
+    const cplx *Xv = X + (size_t)v * n + no;
+    acc = cadd(acc, Xv[oij + ((size_t)i * no + j) * nv + a]);
+    acc = csub(acc, Xv[oji + ((size_t)j * no + i) * nv + a]);
+    // three-body: + 1/2 sum_e Xe_e t_ij^ae, t2 block [ki][kj][ka] (ke = K)
     cplx h = mkc(0, 0);
-    for (int e = 0; e < nv; ++e) cfma(h, aux[(size_t)v * ldaux + e], T[(((size_t)i * no + j) * nv + a) * nv + e]);
+    for (int e = 0; e < nv; ++e) cfma(h, aux[(size_t)v * ldaux + e], T[e]);
     acc = cadd(acc, cscale(h, 0.5));
+    y[(size_t)v * n + no + z] = acc;
   }
-  y[(size_t)v * n + no + z] = acc;
 }
 
 int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y) {
@@ -590,6 +646,21 @@ int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y) 
     c->sig_r1aux_elems = c->sig_r1aux ? need_aux : 0;
     if (!c->sig_r1aux) return CCGF_ENOMEM;
   }
+  {
+    const long long n2max = (long long)c->nk * c->nk * c->no * c->nv * std::max(c->no, c->nv);
+    const size_t nzmax = (size_t)((n2max + ZCH - 1) / ZCH);
+    const size_t need_part = nzmax * (size_t)(c->no + c->nv) * nvec;
+    if (c->sig_part_elems < need_part) {
+      if (c->sig_part) {
+        for (auto &q : c->allocs)
+          if (q == c->sig_part) q = nullptr;
+        hipFree(c->sig_part);
+      }
+      c->sig_part = (cplx *)dev_alloc(c, need_part * sizeof(cplx));
+      c->sig_part_elems = c->sig_part ? need_part : 0;
+      if (!c->sig_part) return CCGF_ENOMEM;
+    }
+  }
   SigmaPlan *P = nullptr;
   for (auto &q : c->plans)
     if (q.part == part && q.K == K && q.nvec == nvec) P = &q;
@@ -601,16 +672,18 @@ int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y) 
     P->nvec = nvec;
     P->n = n;
     build_plans(c, *P);
-    if (!P->g_big.d_tasks || !P->g_ovvo.d_tasks) return CCGF_ENOMEM;
+    if (!P->g_big.d_tasks || !P->g_ovvo.d_tasks || !P->g_r1.d_tasks) return CCGF_ENOMEM;
     const size_t nk3 = (size_t)c->nk * c->nk * c->nk;
     const size_t vb = (size_t)nvec * n;
     bool ok;
     if (part == CCGF_PART_EA)
       ok = plan_in_bounds(P->g_big, nk3 * c->nv * c->nv * c->nv * c->nv, vb, vb) &&
-           plan_in_bounds(P->g_ovvo, nk3 * c->nv * c->no * c->no * c->nv, vb, vb);
+           plan_in_bounds(P->g_ovvo, nk3 * c->nv * c->no * c->no * c->nv, vb, vb) &&
+           plan_in_bounds(P->g_r1, nk3 * c->nv * c->nv * c->nv * c->no, vb, vb);
     else
       ok = plan_in_bounds(P->g_big, nk3 * c->no * c->no * c->no * c->no, vb, vb) &&
-           plan_in_bounds(P->g_ovvo, nk3 * c->nv * c->no * c->no * c->nv, vb, vb);
+           plan_in_bounds(P->g_ovvo, nk3 * c->nv * c->no * c->no * c->nv, vb, vb) &&
+           plan_in_bounds(P->g_r1, nk3 * c->no * c->nv * c->no * c->no, vb, vb);
     if (!ok) {
       c->plans.pop_back();
       return set_err(c, CCGF_EINVAL, "internal: sigma GEMM plan exceeds its buffers");
@@ -628,21 +701,29 @@ int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y) 
     gemm_launch(0, P->g_big, c->Wvvvv, x, y, s);
     if (timing) hipEventRecord(c->ev[3], s);
     gemm_launch(1, P->g_ovvo, c->WvoP, x, c->sig_tmp, s);
-    hipLaunchKernelGGL(k_ea_r1, dim3(nv + no, nch), dim3(256), 0, s, nk, no, nv, K, nvec, n, x, y, c->sig_r1aux,
+    gemm_launch(4, P->g_r1, c->Wvvvo, x, y, s);
+    const int nz = (int)((nk * nk * (long long)no * nv * nv + ZCH - 1) / ZCH);
+    hipLaunchKernelGGL(k_ea_r1, dim3(nv + no, nch, nz), dim3(256), 0, s, nk, no, nv, K, nvec, n, x, c->sig_part,
                        c->Fvv, c->Fov, c->Wvovv, c->Voovv);
-    long long tot = (long long)nk * nk * no * nv * nv * nvec;
+    hipLaunchKernelGGL(k_r1_finish, dim3(((nv + no) * nvec + 255) / 256), dim3(256), 0, s, nv + no, nv, nvec, nz, n,
+                       c->sig_part, y, c->sig_r1aux, std::max(no, nv));
+    long long tot = (long long)nk * nk * no * nv * nv;
     hipLaunchKernelGGL(k_ea_local, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, nk, no, nv, K, nvec, n,
-                       c->kc3, x, y, c->sig_tmp, c->sig_r1aux, c->Foo, c->Fvv, c->Wvvvo, c->t2);
+                       c->kc3, x, y, c->sig_tmp, c->sig_r1aux, c->Foo, c->Fvv, c->t2);
   } else {
     if (timing) hipEventRecord(c->ev[2], s);
     gemm_launch(2, P->g_big, c->WooP, x, y, s);
     if (timing) hipEventRecord(c->ev[3], s);
     gemm_launch(3, P->g_ovvo, c->WvoP, x, c->sig_tmp, s);
-    hipLaunchKernelGGL(k_ip_r1, dim3(no + nv, nch), dim3(256), 0, s, nk, no, nv, K, nvec, n, c->kc3, x, y,
-                       c->sig_r1aux, c->Foo, c->Fov, c->Wooov, c->Voovv);
-    long long tot = (long long)nk * nk * no * no * nv * nvec;
+    gemm_launch(5, P->g_r1, c->Wovoo, x, y, s);
+    const int nz = (int)((nk * nk * (long long)no * no * nv + ZCH - 1) / ZCH);
+    hipLaunchKernelGGL(k_ip_r1, dim3(no + nv, nch, nz), dim3(256), 0, s, nk, no, nv, K, nvec, n, c->kc3, x,
+                       c->sig_part, c->Foo, c->Fov, c->Wooov, c->Voovv);
+    hipLaunchKernelGGL(k_r1_finish, dim3(((nv + no) * nvec + 255) / 256), dim3(256), 0, s, no + nv, no, nvec, nz, n,
+                       c->sig_part, y, c->sig_r1aux, std::max(no, nv));
+    long long tot = (long long)nk * nk * no * no * nv;
     hipLaunchKernelGGL(k_ip_local, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, nk, no, nv, K, nvec, n,
-                       c->kc3, x, y, c->sig_tmp, c->sig_r1aux, c->Foo, c->Fvv, c->Wovoo, c->t2);
+                       c->kc3, x, y, c->sig_tmp, c->sig_r1aux, c->Foo, c->Fvv, c->t2);
   }
   if (timing) {
     hipEventRecord(c->ev[1], s);

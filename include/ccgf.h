@@ -62,7 +62,12 @@ enum {
 
 enum { CCGF_HOST = 0, CCGF_DEVICE = 1 };
 enum { CCGF_PART_IP = 1, CCGF_PART_EA = 2, CCGF_PART_BOTH = 3 };
-enum { CCGF_PLAIN_F64 = 0 };
+/* Arithmetic of the sigma products inside the Krylov steps.  The residuals that
+ * decide convergence, the Arnoldi orthogonalisation, the Hessenberg least squares
+ * and the solution updates are FP64 in every mode; in the mixed mode the FP64
+ * true residual restarts every cycle, so the restarted solve is an iterative
+ * refinement and still reaches tol. */
+enum { CCGF_PLAIN_F64 = 0, CCGF_MIXED_F32 = 1 };
 
 /* One periodic system.  All pointers are borrowed for the duration of
  * cc_gf_init only (the library copies what it needs to the device); they are
@@ -82,7 +87,8 @@ typedef struct {
 } ccgf_system;
 
 typedef struct {
-  int precision;    /* CCGF_PLAIN_F64 (the only value in this build) */
+  int precision;    /* CCGF_PLAIN_F64 or CCGF_MIXED_F32 (W_abcd, W_mbej, W_mnij GEMMs in complex
+                       float on FP32 MFMA; needs half the size of those blocks again in memory) */
   int restart_m;    /* Krylov vectors per cycle, 1..2000; 0 -> 30 */
   int maxiter;      /* total GMRES iterations per solve; 0 -> 2000 */
   double tol;       /* relative residual ||b - A x|| / ||b|| in the unique-pair norm; 0 -> 1e-10 */
@@ -129,12 +135,33 @@ int cc_gf_solve(ccgf_ctx *ctx, int nkq, const int *kidx, int norb, const int *or
                 int nw, const double *omega, double eta, int parts,
                 double *G, double *Gplus_opt, double *Gminus_opt, ccgf_stats *st_opt);
 
+/* Largest number of expansion frequencies per part accepted by cc_gf_mor. */
+#define CCGF_MOR_MAX 32
+
+/* Model-order-reduced G_pp(K, w) (MOR paragraph of the results; Eqs. 6, 7, 9):
+ * for every (kidx[a], orbs[b]) and part, the shifted systems of Eq. 6 are
+ * solved in full (same solver and tol as cc_gf_solve) only at the expansion
+ * frequencies wexp_ip[0..nexp_ip) (IP) and wexp_ea[0..nexp_ea) (EA); their
+ * solutions are orthonormalised (Gram-Schmidt twice, unique-pair inner
+ * product, columns below 1e-10 of the largest solution norm dropped) into S;
+ * the model Ht = S^H M S, bt = S^H b, et = e S is then solved on every omega
+ * (one-sided Galerkin projection; exact at the expansion points up to the
+ * solve tolerance).  Counts: nexp_* in 1..CCGF_MOR_MAX for each requested
+ * part (the other part's pointer may be NULL).  Other arguments, layouts and
+ * ownership as in cc_gf_solve.  Returns CCGF_ENOCONV if an expansion solve
+ * missed tol (G is still written). */
+int cc_gf_mor(ccgf_ctx *ctx, int nkq, const int *kidx, int norb, const int *orbs,
+              int nexp_ip, const double *wexp_ip, int nexp_ea, const double *wexp_ea,
+              int nw, const double *omega, double eta, int parts,
+              double *G, double *Gplus_opt, double *Gminus_opt, ccgf_stats *st_opt);
+
 /* Length (complex entries) of an EOM vector of the given part (CCGF_PART_IP or
  * CCGF_PART_EA) in the full antisymmetric storage described above. */
 int cc_gf_vector_size(const ccgf_ctx *ctx, int part, long long *n);
 
 /* sigma = M(K) r for nvec vectors: the EOM-IP or EOM-EA matrix (connected
- * commutator of Hbar, the hot product inside every solve of Eq. 6).
+ * commutator of Hbar, the hot product inside every solve of Eq. 6), in the
+ * arithmetic of the context's Krylov steps (options.precision).
  * x, y: DEVICE complex [nvec][n] (n from cc_gf_vector_size), not aliased;
  * x must be antisymmetric in its pair indices.  Runs on the context stream
  * and returns after the product is complete. */

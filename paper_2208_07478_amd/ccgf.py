@@ -19,10 +19,12 @@ LIB_PATH = os.path.join(HERE, "libccgf.so")
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 HOST, DEVICE = 0, 1
 PART_IP, PART_EA, PART_BOTH = 1, 2, 3
-PLAIN_F64 = 0
+PLAIN_F64, MIXED_F32 = 0, 1
+PRECISIONS = {"f64": PLAIN_F64, "plain_f64": PLAIN_F64, "f32": MIXED_F32, "mixed_f32": MIXED_F32}
 
-EXPORTS = ("cc_gf_init", "cc_gf_solve", "cc_gf_vector_size", "cc_gf_sigma", "cc_gf_vectors",
+EXPORTS = ("cc_gf_init", "cc_gf_solve", "cc_gf_mor", "cc_gf_vector_size", "cc_gf_sigma", "cc_gf_vectors",
            "cc_gf_free", "cc_gf_last_error")
+MOR_MAX = 32
 
 
 class System(ctypes.Structure):
@@ -78,6 +80,9 @@ def load(path: str = LIB_PATH):
     lib.cc_gf_solve.argtypes = [vp, ctypes.c_int, ip, ctypes.c_int, ip, ctypes.c_int, dp, ctypes.c_double,
                                 ctypes.c_int, vp, vp, vp, ctypes.POINTER(Stats)]
     lib.cc_gf_solve.restype = ctypes.c_int
+    lib.cc_gf_mor.argtypes = [vp, ctypes.c_int, ip, ctypes.c_int, ip, ctypes.c_int, dp, ctypes.c_int, dp,
+                              ctypes.c_int, dp, ctypes.c_double, ctypes.c_int, vp, vp, vp, ctypes.POINTER(Stats)]
+    lib.cc_gf_mor.restype = ctypes.c_int
     lib.cc_gf_vector_size.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong)]
     lib.cc_gf_vector_size.restype = ctypes.c_int
     lib.cc_gf_sigma.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp]
@@ -106,7 +111,7 @@ class Context:
     """One system on the GPU (wraps cc_gf_init / cc_gf_free)."""
 
     def __init__(self, system, *, tol=1e-10, restart_m=30, maxiter=2000, max_batch=64, stream=None,
-                 timing=False, foo=None, fvv=None, precond_eta=0.0, recycle_k=0):
+                 timing=False, foo=None, fvv=None, precond_eta=0.0, recycle_k=0, precision="f64"):
         lib = load()
         import torch  # device memory and streams only
         self._torch = torch
@@ -130,7 +135,8 @@ class Context:
         cs.t1 = self._keep[2].ctypes.data
         cs.t2 = self._keep[3].ctypes.data
         cs.mem_space = HOST
-        opt = Options(PLAIN_F64, int(restart_m), int(maxiter), float(tol), int(max_batch),
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        opt = Options(prec, int(restart_m), int(maxiter), float(tol), int(max_batch),
                       ctypes.c_void_p(stream.cuda_stream), 1 if timing else 0, float(precond_eta),
                       int(recycle_k))
         self._opt = opt
@@ -207,5 +213,28 @@ class Context:
         rc = load().cc_gf_solve(self._h, len(kidx), kidx.ctypes.data_as(ip), len(orbs), orbs.ctypes.data_as(ip),
                                 len(om), om.ctypes.data_as(dp), float(eta), _part(parts), G.ctypes.data,
                                 Gp.ctypes.data, Gm.ctypes.data, ctypes.byref(st))
+        self._check(rc, allow=(ENOCONV,) if allow_noconv else ())
+        return G, Gp, Gm, st.as_dict()
+
+    def mor(self, kidx: Sequence[int], orbs: Sequence[int], wexp_ip, wexp_ea, omega, eta: float, parts="both",
+            allow_noconv=False):
+        """Model-order-reduced G, G+, G-, stats on the grid omega from full solves at the
+        expansion frequencies wexp_ip (IP) and wexp_ea (EA); arrays [nkq][norb][nw]."""
+        kidx = np.ascontiguousarray(np.asarray(kidx, dtype=np.int32))
+        orbs = np.ascontiguousarray(np.asarray(orbs, dtype=np.int32))
+        om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
+        wi = np.ascontiguousarray(np.asarray(wexp_ip if wexp_ip is not None else [], dtype=np.float64))
+        wa = np.ascontiguousarray(np.asarray(wexp_ea if wexp_ea is not None else [], dtype=np.float64))
+        shape = (len(kidx), len(orbs), len(om))
+        G = np.zeros(shape, dtype=np.complex128)
+        Gp = np.zeros(shape, dtype=np.complex128)
+        Gm = np.zeros(shape, dtype=np.complex128)
+        st = Stats()
+        ip = ctypes.POINTER(ctypes.c_int)
+        dp = ctypes.POINTER(ctypes.c_double)
+        rc = load().cc_gf_mor(self._h, len(kidx), kidx.ctypes.data_as(ip), len(orbs), orbs.ctypes.data_as(ip),
+                              len(wi), wi.ctypes.data_as(dp), len(wa), wa.ctypes.data_as(dp),
+                              len(om), om.ctypes.data_as(dp), float(eta), _part(parts), G.ctypes.data,
+                              Gp.ctypes.data, Gm.ctypes.data, ctypes.byref(st))
         self._check(rc, allow=(ENOCONV,) if allow_noconv else ())
         return G, Gp, Gm, st.as_dict()

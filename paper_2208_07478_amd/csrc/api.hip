@@ -104,7 +104,8 @@ extern "C" int cc_gf_init(const ccgf_system *s, const ccgf_options *opt, ccgf_ct
     return set_err(nullptr, CCGF_EINVAL, "mem_space must be CCGF_HOST or CCGF_DEVICE");
   ccgf_options o{};
   if (opt) o = *opt;
-  if (o.precision != CCGF_PLAIN_F64) return set_err(nullptr, CCGF_EUNSUPPORTED, "only CCGF_PLAIN_F64 is available");
+  if (o.precision != CCGF_PLAIN_F64 && o.precision != CCGF_MIXED_F32)
+    return set_err(nullptr, CCGF_EUNSUPPORTED, "precision must be CCGF_PLAIN_F64 or CCGF_MIXED_F32");
   if (o.restart_m == 0) o.restart_m = 30;
   if (o.maxiter == 0) o.maxiter = 2000;
   if (o.tol == 0) o.tol = 1e-10;
@@ -210,7 +211,7 @@ extern "C" int cc_gf_sigma(ccgf_ctx *c, int part, int K, int nvec, const double 
   if (K < 0 || K >= c->nk) return set_err(c, CCGF_EINVAL, "K out of range");
   if (nvec < 0 || (nvec > 0 && (!x || !y))) return set_err(c, CCGF_EINVAL, "bad vectors");
   if (x == y && nvec > 0) return set_err(c, CCGF_EINVAL, "x and y must not alias");
-  int rc = sigma_apply(c, part, K, nvec, (const cplx *)x, (cplx *)y);
+  int rc = sigma_apply(c, part, K, nvec, (const cplx *)x, (cplx *)y, c->opt.precision);
   if (rc != CCGF_OK) return rc;
   return hip_check(c, hipStreamSynchronize(c->stream), "cc_gf_sigma");
 }
@@ -289,6 +290,74 @@ extern "C" int cc_gf_solve(ccgf_ctx *c, int nkq, const int *kidx, int norb, cons
     }
     hipFree(Bv);
     hipFree(Ev);
+    if (status != CCGF_OK && status != CCGF_ENOCONV) break;
+  }
+  std::memcpy(G, Gsum.data(), sizeof(cplx) * ntot);
+  if (Gp) std::memcpy(Gp, Gplus.data(), sizeof(cplx) * ntot);
+  if (Gm) std::memcpy(Gm, Gminus.data(), sizeof(cplx) * ntot);
+  S->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  S->big_ms = c->t_big_ms;
+  S->big_launches = c->t_big_launches;
+  S->big_flops = c->t_big_flops;
+  S->sigma_ms = c->t_sigma_ms;
+  S->sigma_launches = c->t_sigma_launches;
+  return status;
+}
+
+extern "C" int cc_gf_mor(ccgf_ctx *c, int nkq, const int *kidx, int norb, const int *orbs, int nexp_ip,
+                         const double *wexp_ip, int nexp_ea, const double *wexp_ea, int nw, const double *omega,
+                         double eta, int parts, double *G, double *Gp, double *Gm, ccgf_stats *st) {
+  if (!c) return CCGF_ESTATE;
+  auto t0 = std::chrono::steady_clock::now();
+  if (nkq < 0 || norb < 0 || nw < 0) return set_err(c, CCGF_EINVAL, "negative counts");
+  if ((nkq && !kidx) || (norb && !orbs) || (nw && !omega) || !G)
+    return set_err(c, CCGF_EINVAL, "NULL array argument");
+  if (!(eta > 0)) return set_err(c, CCGF_EINVAL, "eta must be > 0");
+  if (parts < 1 || parts > 3) return set_err(c, CCGF_EINVAL, "parts must be CCGF_PART_IP, _EA or _BOTH");
+  for (int part : {CCGF_PART_IP, CCGF_PART_EA}) {
+    if (!(parts & part)) continue;
+    const int ne = part == CCGF_PART_IP ? nexp_ip : nexp_ea;
+    const double *we = part == CCGF_PART_IP ? wexp_ip : wexp_ea;
+    if (ne < 1 || ne > CCGF_MOR_MAX) return set_err(c, CCGF_EINVAL, "expansion point count must be in 1..32");
+    if (!we) return set_err(c, CCGF_EINVAL, "NULL expansion frequencies");
+    for (int j = 0; j < ne; ++j)
+      if (!std::isfinite(we[j])) return set_err(c, CCGF_EINVAL, "expansion frequencies must be finite");
+  }
+  for (int a = 0; a < nkq; ++a)
+    if (kidx[a] < 0 || kidx[a] >= c->nk) return set_err(c, CCGF_EINVAL, "kidx out of range");
+  for (int b = 0; b < norb; ++b)
+    if (orbs[b] < 0 || orbs[b] >= c->nmo) return set_err(c, CCGF_EINVAL, "orbital index out of range");
+  for (int w = 0; w < nw; ++w)
+    if (!std::isfinite(omega[w])) return set_err(c, CCGF_EINVAL, "omega must be finite");
+  ccgf_stats local{};
+  ccgf_stats *S = st ? st : &local;
+  std::memset(S, 0, sizeof(*S));
+  c->t_big_ms = c->t_big_flops = c->t_sigma_ms = 0;
+  c->t_big_launches = c->t_sigma_launches = 0;
+  const size_t ntot = (size_t)nkq * norb * nw;
+  std::vector<cplx> Gsum(ntot, mkc(0, 0)), Gplus(ntot, mkc(0, 0)), Gminus(ntot, mkc(0, 0));
+  std::vector<cplx> res((size_t)norb * nw);
+  int status = CCGF_OK;
+  for (int part : {CCGF_PART_IP, CCGF_PART_EA}) {
+    if (!(parts & part) || norb == 0) continue;
+    const int ne = part == CCGF_PART_IP ? nexp_ip : nexp_ea;
+    const double *we = part == CCGF_PART_IP ? wexp_ip : wexp_ea;
+    for (int a = 0; a < nkq; ++a) {
+      int rc = mor_part(c, part, kidx[a], norb, orbs, ne, we, nw, omega, eta, res.data(), S);
+      if (rc != CCGF_OK) {
+        if (rc == CCGF_ENOCONV) set_err(c, rc, "some expansion-point solves did not reach tol");
+        status = (status == CCGF_OK || rc != CCGF_ENOCONV) ? rc : status;
+        if (rc != CCGF_ENOCONV) break;
+      }
+      for (int b = 0; b < norb; ++b)
+        for (int w = 0; w < nw; ++w) {
+          size_t o = ((size_t)a * norb + b) * nw + w;
+          cplx g = res[(size_t)b * nw + w];
+          Gsum[o] = cadd(Gsum[o], g);
+          if (part == CCGF_PART_EA) Gplus[o] = g;
+          else Gminus[o] = g;
+        }
+    }
     if (status != CCGF_OK && status != CCGF_ENOCONV) break;
   }
   std::memcpy(G, Gsum.data(), sizeof(cplx) * ntot);

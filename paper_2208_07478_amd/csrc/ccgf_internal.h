@@ -99,6 +99,8 @@ struct SigmaPlan {  // per (part, K, batch layout)
   GemmPlan g_big;   // EA: W_vvvv term; IP: W_oooo term (writes sigma2)
   GemmPlan g_ovvo;  // W_ovvo term into the scratch vector
   GemmPlan g_r1;    // EA: W_abei r^e; IP: -W_maij r_m  (accumulates into sigma2)
+  GemmPlan g_red1;  // split-K partial sums of the 1p / 1h rows of sigma (EA W_alcd, IP W_mnie)
+  GemmPlan g_red2;  // split-K partial sums of the three-body intermediate (<kl||cd> r / <mn||ef> r)
   bool ready = false;
 };
 
@@ -118,6 +120,8 @@ struct ccgf_ctx {
   cplx *Wvovv = nullptr, *Wvvvo = nullptr, *Wvvvv = nullptr, *Voovv = nullptr;
   cplx *WvoP = nullptr;   // W_ovvo permuted to [kx][ki][km](x, i, m, e)
   cplx *WooP = nullptr;   // W_oooo permuted to [ki][kj][km](i, j, m, n)
+  // complex-float copies of the GEMM operands for the mixed-precision products
+  float2 *Wvvvv32 = nullptr, *WvoP32 = nullptr, *WooP32 = nullptr;
   std::vector<void *> allocs;
   // sigma workspace
   cplx *sig_tmp = nullptr;  // scratch vector batch for the W_ovvo term
@@ -144,10 +148,13 @@ int build_vectors(ccgf_ctx *c, int part, int K, int p, cplx *b, cplx *e);
 long long vec_len(const ccgf_ctx *c, int part);
 
 // sigma.hip
-int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y);
-void gemm_launch(int tag, const GemmPlan &plan, const cplx *A, const cplx *B, cplx *C, hipStream_t s);
+int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y, int prec = 0);
+void gemm_launch(int tag, const GemmPlan &plan, const void *A, const cplx *B, cplx *C, hipStream_t s, int prec);
 void plan_upload(ccgf_ctx *c, GemmPlan &p);
 
 // gmres.hip
 int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb_slot, const double *rhs_omega,
-                  double eta, const cplx *Bvecs, const cplx *Evecs, cplx *Gout, ccgf_stats *st);
+                  double eta, const cplx *Bvecs, const cplx *Evecs, cplx *Gout, ccgf_stats *st,
+                  cplx *Xout = nullptr);
+int mor_part(ccgf_ctx *c, int part, int K, int norb, const int *orbs, int nexp, const double *wexp, int nw,
+             const double *omega, double eta, cplx *Gout, ccgf_stats *st);

@@ -404,6 +404,86 @@ __global__ void k_scale2(cplx *__restrict__ a, cplx *__restrict__ b, const doubl
   b[o] = cscale(b[o], inv[v]);
 }
 
+// dst[v] = src[soff[v]] (strided gather / scatter of whole vectors)
+__global__ void k_copy_vecs(cplx *__restrict__ dst, const long long *__restrict__ doff, const cplx *__restrict__ src,
+                            const long long *__restrict__ soff, long long n) {
+  const int v = blockIdx.y;
+  long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  dst[doff[v] + x] = src[soff[v] + x];
+}
+
+// W[v] -= sum_i h[v][i] * U_i[v],  U_i[v] = U + uoff[v] + i * n
+__global__ __launch_bounds__(256) void k_sub_proj_off(cplx *__restrict__ W, const cplx *__restrict__ U,
+                                                      const long long *__restrict__ uoff, long long n, int ni,
+                                                      const cplx *__restrict__ h, int ldh) {
+  const int v = blockIdx.y;
+  long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  const cplx *Ub = U + uoff[v];
+  cplx acc = W[(size_t)v * n + x];
+  for (int i = 0; i < ni; ++i) acc = csub(acc, cmul(h[(size_t)v * ldh + i], Ub[(size_t)i * n + x]));
+  W[(size_t)v * n + x] = acc;
+}
+
+// Reduced model of Eq. 6 for one orbital per thread row: solve
+// (w + s_M Ht + i s_eta eta) y = bt by Gaussian elimination with partial pivoting, G = et . y
+template <int MAXR>
+__global__ void k_mor_eval(int norb, int r, int nw, const double *__restrict__ omega, double eta_s, double sM,
+                           const cplx *__restrict__ Ht, const cplx *__restrict__ bt, const cplx *__restrict__ et,
+                           cplx *__restrict__ G) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= norb * nw) return;
+  const int b = t / nw, w = t % nw;
+  cplx A[MAXR * MAXR], y[MAXR];
+  const cplx sh = mkc(omega[w], eta_s);
+  for (int j = 0; j < r; ++j) {
+    for (int k = 0; k < r; ++k) {
+      cplx h = cscale(Ht[((size_t)b * r + j) * r + k], sM);
+      A[j * MAXR + k] = j == k ? cadd(h, sh) : h;
+    }
+    y[j] = bt[(size_t)b * r + j];
+  }
+  for (int col = 0; col < r; ++col) {
+    int piv = col;
+    double best = -1;
+    for (int j = col; j < r; ++j) {
+      cplx q = A[j * MAXR + col];
+      double m = q.x * q.x + q.y * q.y;
+      if (m > best) best = m, piv = j;
+    }
+    if (piv != col) {
+      for (int k = 0; k < r; ++k) {
+        cplx tmp = A[col * MAXR + k];
+        A[col * MAXR + k] = A[piv * MAXR + k];
+        A[piv * MAXR + k] = tmp;
+      }
+      cplx tmp = y[col];
+      y[col] = y[piv];
+      y[piv] = tmp;
+    }
+    cplx d = A[col * MAXR + col];
+    double den = d.x * d.x + d.y * d.y;
+    if (den == 0) continue;
+    cplx inv = mkc(d.x / den, -d.y / den);
+    for (int j = col + 1; j < r; ++j) {
+      cplx f = cmul(A[j * MAXR + col], inv);
+      for (int k = col; k < r; ++k) A[j * MAXR + k] = csub(A[j * MAXR + k], cmul(f, A[col * MAXR + k]));
+      y[j] = csub(y[j], cmul(f, y[col]));
+    }
+  }
+  for (int j = r - 1; j >= 0; --j) {
+    cplx acc = y[j];
+    for (int k = j + 1; k < r; ++k) acc = csub(acc, cmul(A[j * MAXR + k], y[k]));
+    cplx d = A[j * MAXR + j];
+    double den = d.x * d.x + d.y * d.y;
+    y[j] = den > 0 ? mkc((acc.x * d.x + acc.y * d.y) / den, (acc.y * d.x - acc.x * d.y) / den) : mkc(0, 0);
+  }
+  cplx g = mkc(0, 0);
+  for (int j = 0; j < r; ++j) cfma(g, et[(size_t)b * r + j], y[j]);
+  G[t] = g;
+}
+
 }  // namespace
 
 struct GmresWork {
@@ -427,7 +507,7 @@ static void wfree(GmresWork &W) {
 }
 
 int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, const double *rhs_omega, double eta,
-                  const cplx *Bvecs, const cplx *Evecs, cplx *Gout, ccgf_stats *st) {
+                  const cplx *Bvecs, const cplx *Evecs, cplx *Gout, ccgf_stats *st, cplx *Xout) {
   const long long n = vec_len(c, part);
   const int n1 = part == CCGF_PART_IP ? c->no : c->nv;
   const double sM = part == CCGF_PART_IP ? 1.0 : -1.0;
@@ -584,7 +664,7 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
         const int na = (int)alist.size();
         hipMemcpyAsync(aidx, alist.data(), sizeof(int) * na, hipMemcpyHostToDevice, s);
         hipLaunchKernelGGL(k_gather_precond, dim3(gx, na), dim3(256), 0, s, Z, Vj, diag, pshift, sM, n, aidx, 1);
-        int rc = sigma_apply(c, part, K, na, Z, Wc);
+        int rc = sigma_apply(c, part, K, na, Z, Wc, c->opt.precision);
         if (rc != CCGF_OK) {
           wfree(W);
           return rc;
@@ -661,7 +741,8 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
         hrn[v] = std::sqrt(std::max(hh[(size_t)v * ldp].x, 0.0));
         its[v] += hkused[v];
         hconv[v] = hrn[v] <= tol * hbnorm[v];
-        if (hconv[v]) alist.push_back(v);
+        // mixed precision: every cycle restarts from the FP64 true residual (iterative refinement)
+        if (hconv[v] || c->opt.precision != CCGF_PLAIN_F64) alist.push_back(v);
       }
       // confirm convergence with the true residual (the recursive one can drift)
       if (!alist.empty()) {
@@ -723,6 +804,8 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
       wfree(W);
       return rc2;
     }
+    if (Xout)  // solutions of this chunk, for the reduced model
+      hipMemcpyAsync(Xout + (size_t)r0 * n, X, sizeof(cplx) * (size_t)B * n, hipMemcpyDeviceToDevice, s);
     for (int v = 0; v < B; ++v) {
       Gout[r0 + v] = hh[(size_t)v * ldp];
       double rel = hbnorm[v] > 0 ? hrn[v] / hbnorm[v] : 0.0;
@@ -736,6 +819,165 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
       }
       if (!ok) status = CCGF_ENOCONV;
     }
+  }
+  wfree(W);
+  return status;
+}
+
+// Model-order reduction (MOR paragraph): full solves at the expansion
+// frequencies, an orthonormal basis S of their solutions per orbital (CGS
+// twice, columns below 1e-10 of the largest zeroed), the Galerkin model
+// Ht = S^H M S, bt = S^H b, et = e S, and its solution on the whole grid.
+int mor_part(ccgf_ctx *c, int part, int K, int norb, const int *orbs, int nexp, const double *wexp, int nw,
+             const double *omega, double eta, cplx *Gout, ccgf_stats *st) {
+  const long long n = vec_len(c, part);
+  const int n1 = part == CCGF_PART_IP ? c->no : c->nv;
+  const double sM = part == CCGF_PART_IP ? 1.0 : -1.0;
+  const double sE = part == CCGF_PART_IP ? -1.0 : 1.0;
+  const int nrhs = norb * nexp;
+  const int nchunk = (int)((n + DOT_CHUNK - 1) / DOT_CHUNK);
+  const int ldp = nexp + 1;
+  hipStream_t s = c->stream;
+  GmresWork W;
+  cplx *Bv = (cplx *)walloc(W, sizeof(cplx) * (size_t)norb * n);
+  cplx *Ev = (cplx *)walloc(W, sizeof(cplx) * (size_t)norb * n);
+  cplx *S = (cplx *)walloc(W, sizeof(cplx) * (size_t)nrhs * n);
+  cplx *MS = (cplx *)walloc(W, sizeof(cplx) * (size_t)nrhs * n);
+  cplx *Wt = (cplx *)walloc(W, sizeof(cplx) * (size_t)norb * n);
+  cplx *partial = (cplx *)walloc(W, sizeof(cplx) * (size_t)nrhs * nchunk * ldp);
+  cplx *out = (cplx *)walloc(W, sizeof(cplx) * (size_t)nrhs * ldp);
+  cplx *Ht = (cplx *)walloc(W, sizeof(cplx) * (size_t)norb * nexp * nexp);
+  cplx *bt = (cplx *)walloc(W, sizeof(cplx) * (size_t)norb * nexp);
+  cplx *et = (cplx *)walloc(W, sizeof(cplx) * (size_t)norb * nexp);
+  cplx *Gd = (cplx *)walloc(W, sizeof(cplx) * (size_t)norb * nw);
+  double *dom = (double *)walloc(W, sizeof(double) * nw);
+  double *inv = (double *)walloc(W, sizeof(double) * nrhs);
+  long long *off_a = (long long *)walloc(W, sizeof(long long) * nrhs);
+  long long *off_b = (long long *)walloc(W, sizeof(long long) * nrhs);
+  long long *off_c = (long long *)walloc(W, sizeof(long long) * nrhs);
+  if (W.failed) {
+    wfree(W);
+    return set_err(c, CCGF_ENOMEM, "MOR workspace allocation failed");
+  }
+  // full solves at the expansion frequencies (right-hand side index = b * nexp + j)
+  for (int b = 0; b < norb; ++b) {
+    int rc = build_vectors(c, part, K, orbs[b], Bv + (size_t)b * n, Ev + (size_t)b * n);
+    if (rc != CCGF_OK) {
+      wfree(W);
+      return rc;
+    }
+  }
+  std::vector<int> rorb(nrhs);
+  std::vector<double> rw(nrhs);
+  for (int b = 0; b < norb; ++b)
+    for (int j = 0; j < nexp; ++j) rorb[b * nexp + j] = b, rw[b * nexp + j] = wexp[j];
+  std::vector<cplx> gexp(nrhs);
+  int status = solve_batched(c, part, K, nrhs, rorb.data(), rw.data(), eta, Bv, Ev, gexp.data(), st, S);
+  if (status != CCGF_OK && status != CCGF_ENOCONV) {
+    wfree(W);
+    return status;
+  }
+  const unsigned gx = (unsigned)((n + 255) / 256);
+  std::vector<long long> ha(nrhs), hb(nrhs), hc(nrhs);
+  std::vector<cplx> hh((size_t)nrhs * ldp);
+  auto upload = [&](long long *d, const std::vector<long long> &h, int cnt) {
+    hipMemcpyAsync(d, h.data(), sizeof(long long) * cnt, hipMemcpyHostToDevice, s);
+  };
+  auto dots = [&](const cplx *U, const long long *uoff, long long su, int ni, const cplx *Wp, int B, int conjU) {
+    hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, U, uoff, su, ni, Wp, n, n1, conjU,
+                       (const int *)nullptr, partial, nchunk, ldp);
+    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, ni, (const int *)nullptr, out,
+                       ldp, (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr);
+  };
+  // norms of the solutions (drop threshold)
+  for (int v = 0; v < nrhs; ++v) ha[v] = (long long)v * n;
+  upload(off_a, ha, nrhs);
+  dots(S, off_a, 0, 1, S, nrhs, 1);
+  hipMemcpyAsync(hh.data(), out, sizeof(cplx) * nrhs * ldp, hipMemcpyDeviceToHost, s);
+  if (int rc = hip_check(c, hipStreamSynchronize(s), "MOR norms")) {
+    wfree(W);
+    return rc;
+  }
+  std::vector<double> big(norb, 0.0);
+  for (int b = 0; b < norb; ++b)
+    for (int j = 0; j < nexp; ++j) big[b] = std::max(big[b], std::sqrt(std::max(hh[(size_t)(b * nexp + j) * ldp].x, 0.0)));
+  // orthonormalise column j of every orbital against columns 0..j-1
+  for (int b = 0; b < norb; ++b) hb[b] = (long long)b * n, hc[b] = (long long)b * nexp * n;
+  upload(off_b, hb, norb);
+  upload(off_c, hc, norb);
+  std::vector<double> hinv(norb);
+  for (int j = 0; j < nexp; ++j) {
+    for (int b = 0; b < norb; ++b) ha[b] = (long long)(b * nexp + j) * n;
+    upload(off_a, ha, norb);
+    hipLaunchKernelGGL(k_copy_vecs, dim3(gx, norb), dim3(256), 0, s, Wt, off_b, S, off_a, n);
+    for (int pass = 0; pass < 2 && j > 0; ++pass) {
+      dots(S, off_c, n, j, Wt, norb, 1);
+      hipLaunchKernelGGL(k_sub_proj_off, dim3(gx, norb), dim3(256), 0, s, Wt, S, off_c, n, j, out, ldp);
+    }
+    dots(Wt, off_b, 0, 1, Wt, norb, 1);
+    hipMemcpyAsync(hh.data(), out, sizeof(cplx) * norb * ldp, hipMemcpyDeviceToHost, s);
+    if (int rc = hip_check(c, hipStreamSynchronize(s), "MOR basis")) {
+      wfree(W);
+      return rc;
+    }
+    for (int b = 0; b < norb; ++b) {
+      double nb = std::sqrt(std::max(hh[(size_t)b * ldp].x, 0.0));
+      hinv[b] = (nb > 1e-10 * big[b] && nb > 0) ? 1.0 / nb : 0.0;  // dependent column -> zero
+    }
+    hipMemcpyAsync(inv, hinv.data(), sizeof(double) * norb, hipMemcpyHostToDevice, s);
+    hipLaunchKernelGGL(k_scale, dim3(gx, norb), dim3(256), 0, s, Wt, Wt, inv, n, (const int *)nullptr);
+    hipLaunchKernelGGL(k_copy_vecs, dim3(gx, norb), dim3(256), 0, s, S, off_a, Wt, off_b, n);
+  }
+  // M S, then Ht[b][j][k] = <s_bj, (M S)_bk>, bt = <s_bj, b_b>, et = e_b . s_bj
+  int rc = sigma_apply(c, part, K, nrhs, S, MS, 0);
+  if (rc != CCGF_OK) {
+    wfree(W);
+    return rc;
+  }
+  if (st) st->n_sigma += nrhs;
+  for (int v = 0; v < nrhs; ++v) ha[v] = (long long)(v / nexp) * nexp * n;
+  upload(off_a, ha, nrhs);
+  dots(S, off_a, n, nexp, MS, nrhs, 1);  // out[(b,k)][j]
+  std::vector<cplx> hHt((size_t)norb * nexp * nexp), hbt((size_t)norb * nexp), het((size_t)norb * nexp);
+  hipMemcpyAsync(hh.data(), out, sizeof(cplx) * nrhs * ldp, hipMemcpyDeviceToHost, s);
+  if (int rc2 = hip_check(c, hipStreamSynchronize(s), "MOR projection")) {
+    wfree(W);
+    return rc2;
+  }
+  for (int b = 0; b < norb; ++b)
+    for (int k = 0; k < nexp; ++k)
+      for (int j = 0; j < nexp; ++j) hHt[((size_t)b * nexp + j) * nexp + k] = hh[(size_t)(b * nexp + k) * ldp + j];
+  dots(S, off_c, n, nexp, Bv, norb, 1);
+  hipMemcpyAsync(hh.data(), out, sizeof(cplx) * norb * ldp, hipMemcpyDeviceToHost, s);
+  if (int rc2 = hip_check(c, hipStreamSynchronize(s), "MOR projection")) {
+    wfree(W);
+    return rc2;
+  }
+  for (int b = 0; b < norb; ++b)
+    for (int j = 0; j < nexp; ++j) hbt[(size_t)b * nexp + j] = hh[(size_t)b * ldp + j];
+  dots(S, off_c, n, nexp, Ev, norb, 0);
+  hipMemcpyAsync(hh.data(), out, sizeof(cplx) * norb * ldp, hipMemcpyDeviceToHost, s);
+  if (int rc2 = hip_check(c, hipStreamSynchronize(s), "MOR projection")) {
+    wfree(W);
+    return rc2;
+  }
+  for (int b = 0; b < norb; ++b)
+    for (int j = 0; j < nexp; ++j) het[(size_t)b * nexp + j] = hh[(size_t)b * ldp + j];
+  hipMemcpyAsync(Ht, hHt.data(), sizeof(cplx) * hHt.size(), hipMemcpyHostToDevice, s);
+  hipMemcpyAsync(bt, hbt.data(), sizeof(cplx) * hbt.size(), hipMemcpyHostToDevice, s);
+  hipMemcpyAsync(et, het.data(), sizeof(cplx) * het.size(), hipMemcpyHostToDevice, s);
+  hipMemcpyAsync(dom, omega, sizeof(double) * nw, hipMemcpyHostToDevice, s);
+  const int nt = norb * nw;
+  if (nexp <= 16)
+    hipLaunchKernelGGL(k_mor_eval<16>, dim3((nt + 63) / 64), dim3(64), 0, s, norb, nexp, nw, dom, sE * eta, sM, Ht,
+                       bt, et, Gd);
+  else
+    hipLaunchKernelGGL(k_mor_eval<32>, dim3((nt + 63) / 64), dim3(64), 0, s, norb, nexp, nw, dom, sE * eta, sM, Ht,
+                       bt, et, Gd);
+  hipMemcpyAsync(Gout, Gd, sizeof(cplx) * nt, hipMemcpyDeviceToHost, s);
+  if (int rc2 = hip_check(c, hipStreamSynchronize(s), "MOR evaluation")) {
+    wfree(W);
+    return rc2;
   }
   wfree(W);
   return status;

@@ -337,6 +337,19 @@ int build_hbar(ccgf_ctx *c) {
   });
 
   c->Voovv = Voovv.p;
+  if (c->opt.precision == CCGF_MIXED_F32) {
+    // complex-float copies of the GEMM operands (rounded once, here)
+    auto to32 = [&](const cplx *src, size_t nel) -> float2 * {
+      float2 *d = (float2 *)dev_alloc(c, nel * sizeof(float2));
+      if (!d) return nullptr;
+      foreach_(s, nel, [=] __device__(size_t i) { d[i] = make_float2((float)src[i].x, (float)src[i].y); });
+      return d;
+    };
+    c->Wvvvv32 = to32(Wvvvv.p, Wvvvv.size());
+    c->WvoP32 = to32(WvoP.p, WvoP.size());
+    c->WooP32 = to32(WooP.p, WooP.size());
+    if (!c->Wvvvv32 || !c->WvoP32 || !c->WooP32) return CCGF_ENOMEM;
+  }
   if (hip_check(c, hipStreamSynchronize(s), "building Hbar blocks") != CCGF_OK) return CCGF_EDEVICE;
   // release the integral classes that the products do not read
   auto release = [&](cplx *p) {

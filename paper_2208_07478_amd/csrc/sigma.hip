@@ -16,6 +16,7 @@
 #include <algorithm>
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 #define TM 64
 #define TN 64
@@ -26,14 +27,42 @@ __device__ inline long long imap(const IdxMap &m, int x) {
   return (long long)(x / m.L) * m.s0 + (long long)(x % m.L) * m.s1;
 }
 
-// C[m][n] = alpha * sum_seg sum_k A[m][k] B[k][n] (+ C), complex FP64 on MFMA.
+// Real arithmetic of one GEMM variant: FP64 (A complex double) or FP32 (A complex
+// float, vectors rounded to float when staged, FP32 accumulation).  ROW gives the
+// output row of MFMA item v in lane group g (l / 16), measured per instruction:
+// the FP64 16x16x4 spreads a lane's four items over rows g, g+4, g+8, g+12, the
+// FP32 16x16x4 gives them four consecutive rows 4g .. 4g+3.
+template <typename R>
+struct Mf;
+template <>
+struct Mf<double> {
+  typedef v4d V4;
+  typedef double2 AE;
+  __device__ static inline V4 mm(double a, double b, V4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int g, int v) { return g + 4 * v; }
+};
+template <>
+struct Mf<float> {
+  typedef v4f V4;
+  typedef float2 AE;
+  __device__ static inline V4 mm(float a, float b, V4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static inline int row(int g, int v) { return 4 * g + v; }
+};
+
+// C[m][n] = alpha * sum_seg sum_k A[m][k] B[k][n] (+ C), complex, on MFMA.
 // TAG only separates the uses in kernel traces (0: EA W_abcd, 1: EA W_lbdi,
-// 2: IP W_mnij, 3: IP W_maei, 4: EA W_abei r^e, 5: IP W_maij r_m).
-template <int TAG>
-__global__ __launch_bounds__(256, 2) void k_cgemm_f64(GemmShape sh, const GemmTask *__restrict__ tasks,
-                                                   const GemmSeg *__restrict__ segs,
-                                                   const cplx *__restrict__ A, const cplx *__restrict__ B,
-                                                   cplx *__restrict__ C, int tilesM, int tilesN, int total) {
+// 2: IP W_mnij, 3: IP W_maei, 4: EA W_abei r^e, 5: IP W_maij r_m, 6: EA 1p-row
+// reductions W_alcd r, <kl||cd> r, 7: IP 1h-row reductions W_mnie r, <mn||ef> r).
+template <int TAG, typename R>
+__global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *__restrict__ tasks,
+                                                  const GemmSeg *__restrict__ segs,
+                                                  const typename Mf<R>::AE *__restrict__ A,
+                                                  const cplx *__restrict__ B, cplx *__restrict__ C, int tilesM,
+                                                  int tilesN, int total) {
+  typedef typename Mf<R>::V4 V4;
+  typedef typename Mf<R>::AE AE;
   int bid = blockIdx.x;
   // keep the tiles of one task on one XCD (consecutive logical ids share an L2)
   if ((total & 7) == 0) {
@@ -45,7 +74,7 @@ __global__ __launch_bounds__(256, 2) void k_cgemm_f64(GemmShape sh, const GemmTa
   const int tm = r / tilesN, tn = r % tilesN;
   const GemmTask task = tasks[t];
 
-  __shared__ double Ar[TM][TK + 1], Ai[TM][TK + 1], Br[TN][TK + 1], Bi[TN][TK + 1];
+  __shared__ R Ar[TM][TK + 1], Ai[TM][TK + 1], Br[TN][TK + 1], Bi[TN][TK + 1];
   const int tid = threadIdx.x;
 
   // each thread stages column kt of rows rt + 16 j (j = 0..3) of both tiles
@@ -66,27 +95,28 @@ __global__ __launch_bounds__(256, 2) void k_cgemm_f64(GemmShape sh, const GemmTa
 
   // Gauss' three-product form: P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi);
   // C = (P1 - P2) + i (P3 - P1 - P2)
-  v4d P1[2][2], P2[2][2], P3[2][2];
+  V4 P1[2][2], P2[2][2], P3[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      P1[a][b] = (v4d){0, 0, 0, 0};
-      P2[a][b] = (v4d){0, 0, 0, 0};
-      P3[a][b] = (v4d){0, 0, 0, 0};
+      P1[a][b] = (V4){0, 0, 0, 0};
+      P2[a][b] = (V4){0, 0, 0, 0};
+      P3[a][b] = (V4){0, 0, 0, 0};
     }
 
-  cplx ra[4], rb[4];
+  AE ra[4];
+  cplx rb[4];
   auto load = [&](int step) {
     int s = step / ksteps;
     int k = (step - s * ksteps) * TK + kt;
     GemmSeg sg = segs[task.seg_begin + s];
     const bool kok = k < sh.K;
-    const cplx *Ap = A + sg.a_off + (kok ? imap(sh.ak, k) : 0);
+    const AE *Ap = A + sg.a_off + (kok ? imap(sh.ak, k) : 0);
     const cplx *Bp = B + sg.b_off + (kok ? imap(sh.bk, k) : 0);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      ra[j] = (aok[j] && kok) ? Ap[aoff[j]] : mkc(0, 0);
+      ra[j] = (aok[j] && kok) ? Ap[aoff[j]] : AE{0, 0};
       rb[j] = (bok[j] && kok) ? Bp[boff[j]] : mkc(0, 0);
     }
   };
@@ -100,26 +130,22 @@ __global__ __launch_bounds__(256, 2) void k_cgemm_f64(GemmShape sh, const GemmTa
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      Ar[rt + 16 * j][kt] = ra[j].x;
-      Ai[rt + 16 * j][kt] = ra[j].y;
-      Br[rt + 16 * j][kt] = rb[j].x;
-      Bi[rt + 16 * j][kt] = rb[j].y;
+      Ar[rt + 16 * j][kt] = (R)ra[j].x;
+      Ai[rt + 16 * j][kt] = (R)ra[j].y;
+      Br[rt + 16 * j][kt] = (R)rb[j].x;
+      Bi[rt + 16 * j][kt] = (R)rb[j].y;
     }
     __syncthreads();
     if (step + 1 < nsteps) load(step + 1);
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
-      double a_r[2], a_i[2], b_r[2], b_i[2];
+      R a_r[2], a_i[2], b_r[2], b_i[2], a_s[2], b_s[2];
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         a_r[q] = Ar[wr * 32 + q * 16 + lr][kk + lk];
         a_i[q] = Ai[wr * 32 + q * 16 + lr][kk + lk];
         b_r[q] = Br[wc * 32 + q * 16 + lr][kk + lk];
         b_i[q] = Bi[wc * 32 + q * 16 + lr][kk + lk];
-      }
-      double a_s[2], b_s[2];
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
         a_s[q] = a_r[q] + a_i[q];
         b_s[q] = b_r[q] + b_i[q];
       }
@@ -127,27 +153,26 @@ __global__ __launch_bounds__(256, 2) void k_cgemm_f64(GemmShape sh, const GemmTa
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          P1[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[a], b_r[b], P1[a][b], 0, 0, 0);
-          P2[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[a], b_i[b], P2[a][b], 0, 0, 0);
-          P3[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_s[a], b_s[b], P3[a][b], 0, 0, 0);
+          P1[a][b] = Mf<R>::mm(a_r[a], b_r[b], P1[a][b]);
+          P2[a][b] = Mf<R>::mm(a_i[a], b_i[b], P2[a][b]);
+          P3[a][b] = Mf<R>::mm(a_s[a], b_s[b], P3[a][b]);
         }
     }
   }
 
-  // D layout of the 16x16 f64 MFMA block (measured): lane l, item v -> row l/16 + 4v, col l%16
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        int row = wr * 32 + a * 16 + lk + 4 * v;
+        int row = wr * 32 + a * 16 + Mf<R>::row(lk, v);
         int col = wc * 32 + b * 16 + lr;
         int m = tm * TM + row, n = tn * TN + col;
         if (m < sh.M && n < sh.N) {
           long long off = task.c_off + imap(sh.cm, m) + imap(sh.cn, n);
           double p1 = P1[a][b][v], p2 = P2[a][b][v];
-          double re = p1 - p2, im = P3[a][b][v] - p1 - p2;
+          double re = p1 - p2, im = (double)P3[a][b][v] - p1 - p2;
           cplx val = mkc(sh.alpha_re * re - sh.alpha_im * im, sh.alpha_re * im + sh.alpha_im * re);
           if (sh.accumulate) val = cadd(val, C[off]);
           C[off] = val;
@@ -155,20 +180,36 @@ __global__ __launch_bounds__(256, 2) void k_cgemm_f64(GemmShape sh, const GemmTa
       }
 }
 
-void gemm_launch(int tag, const GemmPlan &plan, const cplx *A, const cplx *B, cplx *C, hipStream_t s) {
+template <int TAG, typename R>
+static void launch_t(const GemmPlan &plan, const void *A, const cplx *B, cplx *C, hipStream_t s, int tilesM,
+                     int tilesN, long long total) {
+  hipLaunchKernelGGL((k_cgemm<TAG, R>), dim3((unsigned)total), dim3(256), 0, s, plan.shape, plan.d_tasks,
+                     plan.d_segs, (const typename Mf<R>::AE *)A, B, C, tilesM, tilesN, (int)total);
+}
+
+// prec 0: FP64 operands (A complex double); prec 1: FP32 (A complex float)
+void gemm_launch(int tag, const GemmPlan &plan, const void *A, const cplx *B, cplx *C, hipStream_t s, int prec) {
   const GemmShape &sh = plan.shape;
   if (plan.ntask == 0 || sh.M == 0 || sh.N == 0) return;
   int tilesM = (sh.M + TM - 1) / TM, tilesN = (sh.N + TN - 1) / TN;
   long long total = (long long)plan.ntask * tilesM * tilesN;
-  dim3 g((unsigned)total), b(256);
+#define CASE(T)                                                                              \
+  case T:                                                                                    \
+    if (prec) launch_t<T, float>(plan, A, B, C, s, tilesM, tilesN, total);                   \
+    else launch_t<T, double>(plan, A, B, C, s, tilesM, tilesN, total);                       \
+    break;
   switch (tag) {
-    case 0: hipLaunchKernelGGL(k_cgemm_f64<0>, g, b, 0, s, sh, plan.d_tasks, plan.d_segs, A, B, C, tilesM, tilesN, (int)total); break;
-    case 1: hipLaunchKernelGGL(k_cgemm_f64<1>, g, b, 0, s, sh, plan.d_tasks, plan.d_segs, A, B, C, tilesM, tilesN, (int)total); break;
-    case 2: hipLaunchKernelGGL(k_cgemm_f64<2>, g, b, 0, s, sh, plan.d_tasks, plan.d_segs, A, B, C, tilesM, tilesN, (int)total); break;
-    case 3: hipLaunchKernelGGL(k_cgemm_f64<3>, g, b, 0, s, sh, plan.d_tasks, plan.d_segs, A, B, C, tilesM, tilesN, (int)total); break;
-    case 4: hipLaunchKernelGGL(k_cgemm_f64<4>, g, b, 0, s, sh, plan.d_tasks, plan.d_segs, A, B, C, tilesM, tilesN, (int)total); break;
-    default: hipLaunchKernelGGL(k_cgemm_f64<5>, g, b, 0, s, sh, plan.d_tasks, plan.d_segs, A, B, C, tilesM, tilesN, (int)total); break;
+    CASE(0) CASE(1) CASE(2) CASE(3) CASE(4)
+    case 6:
+      launch_t<6, double>(plan, A, B, C, s, tilesM, tilesN, total);
+      break;
+    case 7:
+      launch_t<7, double>(plan, A, B, C, s, tilesM, tilesN, total);
+      break;
+    default:
+      launch_t<5, double>(plan, A, B, C, s, tilesM, tilesN, total);
   }
+#undef CASE
 }
 
 // algorithmic flops of one launch (8 per complex multiply-add)
@@ -338,9 +379,74 @@ static void build_plans(ccgf_ctx *c, SigmaPlan &P) {
         q.segs.push_back(GemmSeg{(long long)Wt.blk(K, ka, ki), 0});
       }
   }
+  // 1p / 1h rows of sigma and the three-body intermediate: long contractions over
+  // the whole r2 vector, split over its momentum blocks (one task per block) into
+  // partial sums part[z][row][v] that k_r1_finish adds up.
+  {
+    const int nrow = no + nv;
+    GemmPlan &u = P.g_red1, &w = P.g_red2;
+    if (P.part == CCGF_PART_EA) {
+      const long long b2 = (long long)no * nv * nv;
+      // rows a: 1/2 W_alcd r_l^cd, A = Wvovv[K][kl][kc](a,l,c,d)
+      u.shape.M = nv;
+      u.shape.K = (int)b2;
+      u.shape.am = one(b2);
+      u.shape.ak = one(1);
+      u.shape.alpha_re = 0.5;
+      // rows k: <kl||cd> r_l^cd, A = Voovv[K][kl][kc](k,l,c,d)
+      w.shape.M = no;
+      w.shape.K = (int)b2;
+      w.shape.am = one(b2);
+      w.shape.ak = one(1);
+      w.shape.alpha_re = 1;
+      T4 Wa{nullptr, nk, nv, no, nv, nv}, Va{nullptr, nk, no, no, nv, nv};
+      for (int kl = 0; kl < nk; ++kl)
+        for (int kc = 0; kc < nk; ++kc) {
+          const long long z = kl * nk + kc, boff = nv + z * b2;
+          u.tasks.push_back(GemmTask{z * nrow * nvec, (int)u.segs.size(), 1});
+          u.segs.push_back(GemmSeg{(long long)Wa.blk(K, kl, kc), boff});
+          w.tasks.push_back(GemmTask{(z * nrow + nv) * nvec, (int)w.segs.size(), 1});
+          w.segs.push_back(GemmSeg{(long long)Va.blk(K, kl, kc), boff});
+        }
+    } else {
+      const long long b2 = (long long)no * no * nv;
+      // rows i: -1/2 W_mnie r_mn^e, A = Wooov[km][kn][K](m,n,i,e)
+      u.shape.M = no;
+      u.shape.K = (int)b2;
+      u.shape.am = one(nv);
+      u.shape.ak = two(nv, (long long)no * nv, 1);
+      u.shape.alpha_re = -0.5;
+      // rows e: <mn||ef> r_mn^f, A = Voovv[km][kn][K](m,n,e,f)
+      w.shape.M = nv;
+      w.shape.K = (int)b2;
+      w.shape.am = one(nv);
+      w.shape.ak = two(nv, (long long)nv * nv, 1);
+      w.shape.alpha_re = 1;
+      T4 Wa{nullptr, nk, no, no, no, nv}, Va{nullptr, nk, no, no, nv, nv};
+      for (int km = 0; km < nk; ++km)
+        for (int kn = 0; kn < nk; ++kn) {
+          const long long z = km * nk + kn, boff = no + z * b2;
+          u.tasks.push_back(GemmTask{z * nrow * nvec, (int)u.segs.size(), 1});
+          u.segs.push_back(GemmSeg{(long long)Wa.blk(km, kn, K), boff});
+          w.tasks.push_back(GemmTask{(z * nrow + no) * nvec, (int)w.segs.size(), 1});
+          w.segs.push_back(GemmSeg{(long long)Va.blk(km, kn, K), boff});
+        }
+    }
+    for (GemmPlan *g : {&u, &w}) {
+      g->shape.N = nvec;
+      g->shape.bk = one(1);
+      g->shape.bn = one(n);
+      g->shape.cm = one(nvec);
+      g->shape.cn = one(1);
+      g->shape.alpha_im = 0;
+      g->shape.accumulate = 0;
+    }
+  }
   plan_upload(c, P.g_big);
   plan_upload(c, P.g_ovvo);
   plan_upload(c, P.g_r1);
+  plan_upload(c, P.g_red1);
+  plan_upload(c, P.g_red2);
   P.ready = true;
 }
 
@@ -370,109 +476,55 @@ static bool plan_in_bounds(const GemmPlan &p, size_t a_elems, size_t b_elems, si
 }
 
 // ------------------------------------------------------------------ reductions
-#define RCH 16  // right-hand sides handled together by the reduction kernels
-#define ZCH 16384  // r2 entries summed by one block (the range is split over blockIdx.z)
-
 __device__ inline double wsum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
   return v;
 }
 
-// Sum acc[q] over the block and write it with `put(q, value)` from threads q < nq.
-template <class PUT>
-__device__ inline void block_reduce_store(const cplx *acc, int nq, double (*sh)[RCH][2], PUT put) {
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-#pragma unroll
-  for (int q = 0; q < RCH; ++q) {
-    double re = wsum(acc[q].x), im = wsum(acc[q].y);
-    if (l == 0) {
-      sh[w][q][0] = re;
-      sh[w][q][1] = im;
-    }
-  }
-  __syncthreads();
-  if ((int)threadIdx.x < nq) {
-    const int q = threadIdx.x;
-    cplx v = mkc(0, 0);
-    for (int ww = 0; ww < (int)(blockDim.x >> 6); ++ww) v = cadd(v, mkc(sh[ww][q][0], sh[ww][q][1]));
-    put(q, v);
-  }
-}
-
-// ------------------------------------------------------------------ EA
-// blocks (a-or-k, RHS chunk): sigma1[a] (a < nv) or Y[k] = sum <kl||cd> r_l^cd (k < no)
-__global__ __launch_bounds__(256) void k_ea_r1(int nk, int no, int nv, int K, int nvec, long long n,
-                                               const cplx *__restrict__ x, cplx *__restrict__ part,
-                                               const cplx *__restrict__ Fvv,
-                                               const cplx *__restrict__ Fov, const cplx *__restrict__ Wvovv,
-                                               const cplx *__restrict__ Voovv) {
-  const int row = blockIdx.x;  // 0..nv-1: sigma1[a];  nv..nv+no-1: Y[k]
-  const int v0 = blockIdx.y * RCH;
-  const int nq = min(RCH, nvec - v0);
-  const long long b2 = (long long)no * nv * nv;
-  const long long n2 = (long long)nk * nk * b2;
-  const long long z0 = (long long)blockIdx.z * ZCH, z1 = min(n2, z0 + ZCH);
-  cplx acc[RCH];
-#pragma unroll
-  for (int q = 0; q < RCH; ++q) acc[q] = mkc(0, 0);
-  const bool is_sig = row < nv;
-  const cplx *xv = x + (size_t)v0 * n;
-  // sum over this block's share of the r2 entries (kl, kc, l, c, d)
-  for (long long z = z0 + threadIdx.x; z < z1; z += blockDim.x) {
-    long long blk = z / b2, w = z % b2;
-    int kl = (int)(blk / nk), kc = (int)(blk % nk);
-    cplx wv;
-    if (is_sig) {  // 1/2 W_alcd, block [K][kl][kc]
-      size_t off = (((size_t)K * nk + kl) * nk + kc) * (size_t)(nv * b2) + (size_t)row * b2 + w;
-      wv = cscale(Wvovv[off], 0.5);
-    } else {  // <kl||cd>, block [K][kl][kc]
-      size_t off = (((size_t)K * nk + kl) * nk + kc) * (size_t)(no * b2) + (size_t)(row - nv) * b2 + w;
-      wv = Voovv[off];
-    }
-#pragma unroll
-    for (int q = 0; q < RCH; ++q)
-      if (q < nq) cfma(acc[q], wv, xv[(size_t)q * n + nv + z]);
-  }
-  if (is_sig && blockIdx.z == 0) {
-    const int a = row;
-    // F_ac r^c  and  F_ld r_l^ad (block [kl][K], kd = kl)
-    for (int z = threadIdx.x; z < nv + nk * no * nv; z += blockDim.x) {
-      cplx f;
-      size_t off;
-      if (z < nv) {
-        f = Fvv[((size_t)K * nv + a) * nv + z];
-        off = z;
-      } else {
-        int w = z - nv;
-        int kl = w / (no * nv), l = (w / nv) % no, d = w % nv;
-        f = Fov[((size_t)kl * no + l) * nv + d];
-        off = nv + (size_t)(kl * nk + K) * b2 + ((size_t)l * nv + a) * nv + d;
-      }
-#pragma unroll
-      for (int q = 0; q < RCH; ++q)
-        if (q < nq) cfma(acc[q], f, xv[(size_t)q * n + off]);
-    }
-  }
-  __shared__ double sh[4][RCH][2];
-  const int nrow = gridDim.x;
-  block_reduce_store(acc, nq, sh, [&](int q, cplx v) {
-    part[((size_t)blockIdx.z * nrow + row) * nvec + v0 + q] = v;
-  });
-}
-
-// sum the split partial results: rows < n1 go to sigma1 of the vector, the rest to aux
-__global__ void k_r1_finish(int nrow, int n1, int nvec, int nz, long long n, const cplx *__restrict__ part,
-                            cplx *__restrict__ y, cplx *__restrict__ aux, int ldaux) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nrow * nvec) return;
-  int row = t / nvec, v = t % nvec;
+// One wave per (row, vector): add the split-K partial sums of the reduction GEMMs
+// and, for the rows of sigma1, the Fock terms; rows >= n1 are the three-body
+// intermediate, written to aux.
+//   EA, row a:  F_ac r^c + F_ld r_l^ad            (r2 block [kl][K], kd = kl)
+//   IP, row i: -F_mi r_m + F_me r_im^e            (r2 block [K][km], ke = km)
+__global__ __launch_bounds__(256) void k_r1_finish(int ea, int nk, int no, int nv, int K, int nrow, int n1,
+                                                   int nvec, int nz, long long n, const cplx *__restrict__ part,
+                                                   const cplx *__restrict__ x, cplx *__restrict__ y,
+                                                   cplx *__restrict__ aux, int ldaux, const cplx *__restrict__ Foo,
+                                                   const cplx *__restrict__ Fvv, const cplx *__restrict__ Fov) {
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (t >= nrow * nvec) return;  // whole waves leave together
+  const int row = t / nvec, v = t % nvec;
   cplx acc = mkc(0, 0);
-  for (int zz = 0; zz < nz; ++zz) acc = cadd(acc, part[((size_t)zz * nrow + row) * nvec + v]);
-  if (row < n1) y[(size_t)v * n + row] = acc;
-  else aux[(size_t)v * ldaux + (row - n1)] = acc;
+  for (int zz = lane; zz < nz; zz += 64) acc = cadd(acc, part[((size_t)zz * nrow + row) * nvec + v]);
+  if (row < n1) {
+    const cplx *xv = x + (size_t)v * n;
+    const int nf = nk * no * nv;
+    if (ea) {
+      const int a = row;
+      const long long b2 = (long long)no * nv * nv;
+      for (int c3 = lane; c3 < nv; c3 += 64) cfma(acc, Fvv[((size_t)K * nv + a) * nv + c3], xv[c3]);
+      for (int w = lane; w < nf; w += 64) {
+        const int kl = w / (no * nv), l = (w / nv) % no, d = w % nv;
+        cfma(acc, Fov[((size_t)kl * no + l) * nv + d], xv[nv + (kl * nk + K) * b2 + ((size_t)l * nv + a) * nv + d]);
+      }
+    } else {
+      const int i = row;
+      const long long b2 = (long long)no * no * nv;
+      for (int m = lane; m < no; m += 64) acc = csub(acc, cmul(Foo[((size_t)K * no + m) * no + i], xv[m]));
+      for (int w = lane; w < nf; w += 64) {
+        const int km = w / (no * nv), m = (w / nv) % no, e = w % nv;
+        cfma(acc, Fov[((size_t)km * no + m) * nv + e], xv[no + (K * nk + km) * b2 + ((size_t)i * no + m) * nv + e]);
+      }
+    }
+  }
+  const double re = wsum(acc.x), im = wsum(acc.y);
+  if (lane == 0) {
+    if (row < n1) y[(size_t)v * n + row] = mkc(re, im);
+    else aux[(size_t)v * ldaux + (row - n1)] = mkc(re, im);
+  }
 }
 
-// element-wise EA 2p1h terms: one thread per sigma2 element, looping over the right-hand sides
+// element-wise EA 2p1h terms: one thread per sigma2 element, vectors over grid y
 __global__ __launch_bounds__(256) void k_ea_local(int nk, int no, int nv, int K, int nvec, long long n,
                                                   const int *__restrict__ kc3, const cplx *__restrict__ x,
                                                   cplx *__restrict__ y, const cplx *__restrict__ X,
@@ -490,7 +542,7 @@ __global__ __launch_bounds__(256) void k_ea_local(int nk, int no, int nv, int K,
   const cplx *Fb = Fvv + ((size_t)kb * nv + b) * nv, *Fa = Fvv + ((size_t)ka * nv + a) * nv;
   const cplx *T = t2 + (((size_t)K * nk + ki) * nk + ka) * (size_t)(no * no * nv * nv);
   const int ldaux = no > nv ? no : nv;
-  for (int v = 0; v < nvec; ++v) {
+  for (int v = blockIdx.y; v < nvec; v += gridDim.y) {
     const cplx *r2 = x + (size_t)v * n + nv;
     cplx acc = y[(size_t)v * n + nv + z];
     // P(ab) F_bd r_i^ad
@@ -515,69 +567,7 @@ __global__ __launch_bounds__(256) void k_ea_local(int nk, int no, int nv, int K,
 }
 
 // ------------------------------------------------------------------ IP
-// blocks (i-or-e, RHS chunk): sigma1[i] (i < no) or Xe[e] = sum <mn||ef> r_mn^f (e < nv)
-__global__ __launch_bounds__(256) void k_ip_r1(int nk, int no, int nv, int K, int nvec, long long n,
-                                               const int *__restrict__ kc3, const cplx *__restrict__ x,
-                                               cplx *__restrict__ part, const cplx *__restrict__ Foo, const cplx *__restrict__ Fov,
-                                               const cplx *__restrict__ Wooov, const cplx *__restrict__ Voovv) {
-  const int row = blockIdx.x;
-  const int v0 = blockIdx.y * RCH;
-  const int nq = min(RCH, nvec - v0);
-  const long long b2 = (long long)no * no * nv;
-  const long long n2 = (long long)nk * nk * b2;
-  const long long z0 = (long long)blockIdx.z * ZCH, z1 = min(n2, z0 + ZCH);
-  const bool is_sig = row < no;
-  const cplx *xv = x + (size_t)v0 * n;
-  cplx acc[RCH];
-#pragma unroll
-  for (int q = 0; q < RCH; ++q) acc[q] = mkc(0, 0);
-  for (long long z = z0 + threadIdx.x; z < z1; z += blockDim.x) {
-    long long blk = z / b2, w = z % b2;
-    int km = (int)(blk / nk), kn = (int)(blk % nk);
-    int e = (int)(w % nv), nn = (int)((w / nv) % no), m = (int)(w / ((long long)nv * no));
-    cplx wv;
-    if (is_sig) {  // -1/2 W_mnie, block [km][kn][K]
-      size_t off = (((size_t)km * nk + kn) * nk + K) * (size_t)(no * no * no * nv) +
-                   (((size_t)m * no + nn) * no + row) * nv + e;
-      wv = cscale(Wooov[off], -0.5);
-    } else {  // <mn||ef> with e = row - no (momentum K) and f the r-index, block [km][kn][K]
-      size_t off = (((size_t)km * nk + kn) * nk + K) * (size_t)(no * no * nv * nv) +
-                   (((size_t)m * no + nn) * nv + (row - no)) * nv + e;
-      wv = Voovv[off];
-    }
-#pragma unroll
-    for (int q = 0; q < RCH; ++q)
-      if (q < nq) cfma(acc[q], wv, xv[(size_t)q * n + no + z]);
-  }
-  if (is_sig && blockIdx.z == 0) {
-    const int i = row;
-    // - F_mi r_m  and  F_me r_im^e (block [K][km], ke = km)
-    for (int z = threadIdx.x; z < no + nk * no * nv; z += blockDim.x) {
-      cplx f;
-      size_t off;
-      if (z < no) {
-        f = Foo[((size_t)K * no + z) * no + i];
-        f = mkc(-f.x, -f.y);
-        off = z;
-      } else {
-        int w = z - no;
-        int km = w / (no * nv), m = (w / nv) % no, e = w % nv;
-        f = Fov[((size_t)km * no + m) * nv + e];
-        off = no + (size_t)(K * nk + km) * b2 + ((size_t)i * no + m) * nv + e;
-      }
-#pragma unroll
-      for (int q = 0; q < RCH; ++q)
-        if (q < nq) cfma(acc[q], f, xv[(size_t)q * n + off]);
-    }
-  }
-  __shared__ double sh[4][RCH][2];
-  const int nrow = gridDim.x;
-  block_reduce_store(acc, nq, sh, [&](int q, cplx v) {
-    part[((size_t)blockIdx.z * nrow + row) * nvec + v0 + q] = v;
-  });
-}
-
-// element-wise IP 2h1p terms: one thread per sigma2 element, looping over the right-hand sides
+// element-wise IP 2h1p terms: one thread per sigma2 element, vectors over grid y
 __global__ __launch_bounds__(256) void k_ip_local(int nk, int no, int nv, int K, int nvec, long long n,
                                                   const int *__restrict__ kc3, const cplx *__restrict__ x,
                                                   cplx *__restrict__ y, const cplx *__restrict__ X,
@@ -596,7 +586,7 @@ __global__ __launch_bounds__(256) void k_ip_local(int nk, int no, int nv, int K,
   const cplx *T = t2 + (((size_t)ki * nk + kj) * nk + ka) * (size_t)(no * no * nv * nv) +
                   (((size_t)i * no + j) * nv + a) * nv;
   const int ldaux = no > nv ? no : nv;
-  for (int v = 0; v < nvec; ++v) {
+  for (int v = blockIdx.y; v < nvec; v += gridDim.y) {
     const cplx *r2 = x + (size_t)v * n + no;
     cplx acc = y[(size_t)v * n + no + z];
     // F_ae r_ij^e
@@ -619,7 +609,7 @@ __global__ __launch_bounds__(256) void k_ip_local(int nk, int no, int nv, int K,
   }
 }
 
-int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y) {
+int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y, int prec) {
   if (nvec <= 0) return CCGF_OK;
   const long long n = vec_len(c, part);
   // workspace
@@ -647,9 +637,7 @@ int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y) 
     if (!c->sig_r1aux) return CCGF_ENOMEM;
   }
   {
-    const long long n2max = (long long)c->nk * c->nk * c->no * c->nv * std::max(c->no, c->nv);
-    const size_t nzmax = (size_t)((n2max + ZCH - 1) / ZCH);
-    const size_t need_part = nzmax * (size_t)(c->no + c->nv) * nvec;
+    const size_t need_part = (size_t)c->nk * c->nk * (size_t)(c->no + c->nv) * nvec;
     if (c->sig_part_elems < need_part) {
       if (c->sig_part) {
         for (auto &q : c->allocs)
@@ -672,7 +660,8 @@ int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y) 
     P->nvec = nvec;
     P->n = n;
     build_plans(c, *P);
-    if (!P->g_big.d_tasks || !P->g_ovvo.d_tasks || !P->g_r1.d_tasks) return CCGF_ENOMEM;
+    if (!P->g_big.d_tasks || !P->g_ovvo.d_tasks || !P->g_r1.d_tasks || !P->g_red1.d_tasks || !P->g_red2.d_tasks)
+      return CCGF_ENOMEM;
     const size_t nk3 = (size_t)c->nk * c->nk * c->nk;
     const size_t vb = (size_t)nvec * n;
     bool ok;
@@ -691,38 +680,40 @@ int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y) 
   }
   const int nk = c->nk, no = c->no, nv = c->nv;
   hipStream_t s = c->stream;
-  const int nch = (nvec + RCH - 1) / RCH;
+  const unsigned gy = (unsigned)std::min(nvec, 65535);
   const bool timing = c->opt.timing != 0;
   if (timing && !c->ev[0])
     for (int q = 0; q < 4; ++q) hipEventCreate(&c->ev[q]);
   if (timing) hipEventRecord(c->ev[0], s);
   if (part == CCGF_PART_EA) {
     if (timing) hipEventRecord(c->ev[2], s);
-    gemm_launch(0, P->g_big, c->Wvvvv, x, y, s);
+    if (prec && !c->Wvvvv32) return set_err(c, CCGF_ESTATE, "mixed-precision operands were not built");
+    gemm_launch(0, P->g_big, prec ? (const void *)c->Wvvvv32 : (const void *)c->Wvvvv, x, y, s, prec);
     if (timing) hipEventRecord(c->ev[3], s);
-    gemm_launch(1, P->g_ovvo, c->WvoP, x, c->sig_tmp, s);
-    gemm_launch(4, P->g_r1, c->Wvvvo, x, y, s);
-    const int nz = (int)((nk * nk * (long long)no * nv * nv + ZCH - 1) / ZCH);
-    hipLaunchKernelGGL(k_ea_r1, dim3(nv + no, nch, nz), dim3(256), 0, s, nk, no, nv, K, nvec, n, x, c->sig_part,
-                       c->Fvv, c->Fov, c->Wvovv, c->Voovv);
-    hipLaunchKernelGGL(k_r1_finish, dim3(((nv + no) * nvec + 255) / 256), dim3(256), 0, s, nv + no, nv, nvec, nz, n,
-                       c->sig_part, y, c->sig_r1aux, std::max(no, nv));
+    gemm_launch(1, P->g_ovvo, prec ? (const void *)c->WvoP32 : (const void *)c->WvoP, x, c->sig_tmp, s, prec);
+    gemm_launch(4, P->g_r1, c->Wvvvo, x, y, s, 0);
+    gemm_launch(6, P->g_red1, c->Wvovv, x, c->sig_part, s, 0);
+    gemm_launch(6, P->g_red2, c->Voovv, x, c->sig_part, s, 0);
+    hipLaunchKernelGGL(k_r1_finish, dim3((unsigned)(((nv + no) * nvec + 3) / 4)), dim3(256), 0, s, 1, nk, no, nv, K,
+                       nv + no, nv, nvec, nk * nk, n, c->sig_part, x, y, c->sig_r1aux, std::max(no, nv), c->Foo,
+                       c->Fvv, c->Fov);
     long long tot = (long long)nk * nk * no * nv * nv;
-    hipLaunchKernelGGL(k_ea_local, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, nk, no, nv, K, nvec, n,
+    hipLaunchKernelGGL(k_ea_local, dim3((unsigned)((tot + 255) / 256), gy), dim3(256), 0, s, nk, no, nv, K, nvec, n,
                        c->kc3, x, y, c->sig_tmp, c->sig_r1aux, c->Foo, c->Fvv, c->t2);
   } else {
     if (timing) hipEventRecord(c->ev[2], s);
-    gemm_launch(2, P->g_big, c->WooP, x, y, s);
+    if (prec && !c->WooP32) return set_err(c, CCGF_ESTATE, "mixed-precision operands were not built");
+    gemm_launch(2, P->g_big, prec ? (const void *)c->WooP32 : (const void *)c->WooP, x, y, s, prec);
     if (timing) hipEventRecord(c->ev[3], s);
-    gemm_launch(3, P->g_ovvo, c->WvoP, x, c->sig_tmp, s);
-    gemm_launch(5, P->g_r1, c->Wovoo, x, y, s);
-    const int nz = (int)((nk * nk * (long long)no * no * nv + ZCH - 1) / ZCH);
-    hipLaunchKernelGGL(k_ip_r1, dim3(no + nv, nch, nz), dim3(256), 0, s, nk, no, nv, K, nvec, n, c->kc3, x,
-                       c->sig_part, c->Foo, c->Fov, c->Wooov, c->Voovv);
-    hipLaunchKernelGGL(k_r1_finish, dim3(((nv + no) * nvec + 255) / 256), dim3(256), 0, s, no + nv, no, nvec, nz, n,
-                       c->sig_part, y, c->sig_r1aux, std::max(no, nv));
+    gemm_launch(3, P->g_ovvo, prec ? (const void *)c->WvoP32 : (const void *)c->WvoP, x, c->sig_tmp, s, prec);
+    gemm_launch(5, P->g_r1, c->Wovoo, x, y, s, 0);
+    gemm_launch(7, P->g_red1, c->Wooov, x, c->sig_part, s, 0);
+    gemm_launch(7, P->g_red2, c->Voovv, x, c->sig_part, s, 0);
+    hipLaunchKernelGGL(k_r1_finish, dim3((unsigned)(((nv + no) * nvec + 3) / 4)), dim3(256), 0, s, 0, nk, no, nv, K,
+                       no + nv, no, nvec, nk * nk, n, c->sig_part, x, y, c->sig_r1aux, std::max(no, nv), c->Foo,
+                       c->Fvv, c->Fov);
     long long tot = (long long)nk * nk * no * no * nv;
-    hipLaunchKernelGGL(k_ip_local, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, nk, no, nv, K, nvec, n,
+    hipLaunchKernelGGL(k_ip_local, dim3((unsigned)((tot + 255) / 256), gy), dim3(256), 0, s, nk, no, nv, K, nvec, n,
                        c->kc3, x, y, c->sig_tmp, c->sig_r1aux, c->Foo, c->Fvv, c->t2);
   }
   if (timing) {

@@ -71,4 +71,6 @@ def test_invalid_inputs_are_rejected_on_the_host():
     assert lib.cc_gf_init(None, None, ctypes.byref(h)) == ccgf.EINVAL
     # calls on a NULL context
     assert lib.cc_gf_sigma(None, 1, 0, 0, None, None) == ccgf.ESTATE
+    assert lib.cc_gf_mor(None, 0, None, 0, None, 1, None, 1, None, 0, None, 0.1, 3, None, None, None,
+                         None) == ccgf.ESTATE
     lib.cc_gf_free(None)

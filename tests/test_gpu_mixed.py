@@ -1,0 +1,77 @@
+"""Mixed precision on the GPU: FP32 sigma products (the Krylov steps' operator)
+against the FP64 oracle, and Green's functions from the mixed solver (FP32
+Arnoldi, FP64 true residual and refinement every cycle) against dense
+inversion at FP64 accuracy."""
+import numpy as np
+import pytest
+
+from paper_2208_07478_amd import synth
+from oracle import eom, solve
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    dict(kmesh=(2, 1, 1), nocc=2, nvir=5, seed=12),
+    dict(kmesh=(3, 1, 1), nocc=3, nvir=9, seed=13),
+    dict(kmesh=(2, 2, 1), nocc=2, nvir=7, seed=14),
+]
+
+
+def _system(case):
+    return synth.make_system(t1_std=0.05, t2_std=0.05, eri_std=0.1, **case)
+
+
+@pytest.mark.parametrize("ci", range(len(CASES)))
+@pytest.mark.parametrize("part", ["ip", "ea"])
+def test_fp32_sigma_error_is_single_precision(ci, part):
+    """Each FP32 product agrees with the FP64 oracle to a few FP32 ulps of the
+    vector norm: a wrong MFMA lane layout or a stale FP32 copy is O(1)."""
+    import torch
+    from paper_2208_07478_amd.ccgf import Context
+    s = _system(CASES[ci])
+    print("case", CASES[ci], part, flush=True)
+    E = eom.EOMSystem(s)
+    ctx = Context(s, max_batch=32, precision="f32")
+    try:
+        for K in range(E.nk):
+            X = synth.random_eom_vectors(s.kmesh, s.nocc, s.nvir, part, K, 19, seed=300 + K)
+            ref = np.array([E.sigma(part, K, x) for x in X])
+            Y = ctx.sigma(part, K, torch.from_numpy(X).cuda()).cpu().numpy()
+            err = np.linalg.norm((Y - ref).reshape(len(X), -1), axis=1) / np.linalg.norm(ref.reshape(len(X), -1),
+                                                                                       axis=1)
+            print(part, K, "max rel err", err.max(), flush=True)
+            assert err.max() <= 2e-5
+            assert err.max() > 0  # really single precision, not the FP64 path
+    finally:
+        ctx.close()
+        torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("ci", range(len(CASES)))
+def test_mixed_solver_reaches_fp64_accuracy(ci):
+    """FP32 Krylov steps with FP64 refinement reach tol 1e-10 on the FP64
+    operator: G+ and G- match dense inversion like the plain FP64 solver."""
+    import torch
+    from paper_2208_07478_amd.ccgf import Context
+    s = _system(CASES[ci])
+    print("case", CASES[ci], flush=True)
+    E = eom.EOMSystem(s)
+    ctx = Context(s, max_batch=32, maxiter=12000, restart_m=60, tol=1e-10, precision="f32")
+    try:
+        w = np.linspace(-1.0, 1.0, 5)
+        eta = 0.02
+        nmo = s.nocc + s.nvir
+        ks = list(range(E.nk))
+        G, Gp, Gm, st = ctx.solve(ks, list(range(nmo)), w, eta)
+        assert st["n_unconverged"] == 0
+        assert st["max_rel_residual"] <= 1e-10
+        cache = {}
+        for a, K in enumerate(ks):
+            for p in range(nmo):
+                gp, gm = solve.dense_gf(E, K, p, w, eta, M_cache=cache)
+                scale = max(np.abs(gm).max(), np.abs(gp).max(), 1.0)
+                assert np.abs(Gm[a, p] - gm).max() <= 1e-8 * scale
+                assert np.abs(Gp[a, p] - gp).max() <= 1e-8 * scale
+    finally:
+        ctx.close()
+        torch.cuda.synchronize()

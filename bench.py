@@ -2,17 +2,25 @@
 
 A step is one pass of the whole path over one batch of synthetic input: build
 b/e vectors, solve every shifted IP and EA system of the batch with the batched
-FP64 GMRES (sigma products on MFMA), assemble G = G+ + G-.  The workload is the
+GMRES (sigma products on MFMA), assemble G = G+ + G-.  The workload is the
 Si-like 2x2x2 k-mesh system (4 occupied + 26 virtual spin orbitals per cell,
 complex k-blocks, eta = 0.005 Ha): each step covers all 30 orbitals at K = Gamma
-and 8 frequencies of the 64-point grid on [-1, 1] Ha, with GMRES stopped at a
-relative residual of 1e-8 so that G meets the 1e-6 relative-error target.
+and 16 frequencies spread over the 64-point grid on [-1, 1] Ha (480 points), with
+120 right-hand sides in flight per part.
 
-Prints ONE JSON line (see README / DESIGN for the fields).
+Each solver form (plain FP64, mixed FP32 sigma with FP64 refinement) is timed on
+the same batch at the same GMRES tolerance, and its G is compared with a tight
+plain-FP64 solve of every 4th frequency of the batch (all orbitals); a point
+counts at the 1e-6 relative-error target (per orbital: max over the checked
+frequencies of |dG| / max |G|).  `value` is
+the points/s of the fastest form that meets it.
+
+Prints ONE JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -25,7 +33,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "G(ω) points/sec at 1e-6 rel. error, learned+mixed vs plain FP64; MFMA util"
-PEAK_FP64 = 78.6e12  # MI355X dense FP64 matrix peak, FLOP/s
+PEAK = {"plain_f64": 78.6e12, "mixed_f32": 157.3e12}  # MI355X dense FP64 / FP32 matrix peaks, FLOP/s
+GEMM_NAME = {"plain_f64": "k_cgemm<0, double>", "mixed_f32": "k_cgemm<0, float>"}
+PRECISION = {"plain_f64": "f64", "mixed_f32": "f32"}
+TARGET = 1e-6
 
 
 def parse():
@@ -34,26 +45,48 @@ def parse():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="si_k222")
-    ap.add_argument("--nw", type=int, default=4, help="frequencies per step (spread over the grid)")
-    ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--restart", type=int, default=100)
+    ap.add_argument("--nw", type=int, default=16, help="frequencies per step (spread over the grid)")
+    ap.add_argument("--batch", type=int, default=120, help="right-hand sides in flight")
+    ap.add_argument("--forms", default="plain_f64,mixed_f32")
+    ap.add_argument("--tol", type=float, default=2e-7)
+    ap.add_argument("--ref-tol", type=float, default=1e-9)
+    ap.add_argument("--check-every", type=int, default=4, help="reference solve on every k-th step frequency")
+    ap.add_argument("--restart", type=int, default=150)
     ap.add_argument("--maxiter", type=int, default=12000)
     ap.add_argument("--precond-eta", type=float, default=0.2)
-    ap.add_argument("--recycle-k", type=int, default=0)
+    ap.add_argument("--no-check", action="store_true", help="skip the reference solve (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe", choices=["sigma", "copy"], default=None,
                     help="counter-collection runs: 'sigma' applies 3 EA and 3 IP sigma products to the step's "
                          "batch; 'copy' copies a 1 GiB buffer once (HBM-traffic calibration)")
+    ap.add_argument("--probe-precision", default="f64")
     ap.add_argument("--cpu-sample-s", type=float, default=20.0)
     return ap.parse_args()
+
+
+def stored_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summaries,
+    or None when the kernel source changed since the counters were taken."""
+    src = os.path.join(ROOT, "paper_2208_07478_amd", "csrc", "sigma.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    for name in sorted(os.listdir(pdir)):
+        if not name.endswith(".md"):
+            continue
+        for line in open(os.path.join(pdir, name)):
+            if line.startswith("<!-- traffic "):
+                rec = json.loads(line[len("<!-- traffic "):].rstrip().rstrip("->").strip())
+                if rec.get("kernel") == kernel and rec.get("source_sha256") == sha:
+                    return rec
+    return None
 
 
 def cpu_baseline(sysm, sigma_per_point, budget_s):
     """The oracle timed on the host: sigma products at K = Gamma of the same
     workload, scaled to points/s with the sigma products per point measured on
     the GPU run (the intermediates build is excluded, as cc_gf_init is)."""
-    import threading
-
     from oracle import eom
     from paper_2208_07478_amd import synth
 
@@ -83,10 +116,17 @@ def cpu_baseline(sysm, sigma_per_point, budget_s):
         "cores": int(os.environ.get("OMP_NUM_THREADS", threads) or threads),
         "kind": "oracle",
         "sample": (f"{per['ea'][1]} EA + {per['ip'][1]} IP oracle sigma products at K=Gamma "
-                   f"({per['ea'][0]:.2f} s / {per['ip'][0]:.3f} s each), scaled by the GPU run's "
+                   f"({per['ea'][0]:.2f} s / {per['ip'][0]:.3f} s each), scaled by the headline form's "
                    f"{sigma_per_point['ea']:.0f} EA + {sigma_per_point['ip']:.0f} IP sigma products per point; "
                    f"oracle intermediates build {build_s:.0f} s excluded"),
     }
+
+
+def col_err(G, Gref):
+    """Per orbital: max over frequencies of |G - Gref| / max |Gref|; the worst orbital."""
+    den = np.abs(Gref).max(axis=-1)
+    den = np.where(den > 0, den, 1.0)
+    return float(np.max(np.abs(G - Gref).max(axis=-1) / den))
 
 
 def main():
@@ -112,105 +152,142 @@ def main():
     omega, eta = synth.preset_query(args.workload)
     nmo = sysm.nocc + sysm.nvir
     orbs = list(range(nmo))
-    t0 = time.perf_counter()
-    ctx = Context(sysm, tol=args.tol, restart_m=args.restart, maxiter=args.maxiter, max_batch=nmo * args.nw,
-                  timing=True, precond_eta=args.precond_eta, recycle_k=args.recycle_k)
-    init_s = time.perf_counter() - t0
+    nb = nmo * args.nw
     stride = len(omega) // args.nw
+    wsel = omega[::stride][:args.nw]
+    opts = dict(tol=args.tol, restart_m=args.restart, maxiter=args.maxiter, max_batch=args.batch,
+                precond_eta=args.precond_eta)
     if args.probe == "sigma":
-        nb = nmo * args.nw
+        ctx = Context(sysm, precision=args.probe_precision, **opts)
         for part in ("ea", "ip"):
-            X = torch.from_numpy(synth.random_eom_vectors(sysm.kmesh, sysm.nocc, sysm.nvir, part, 0, nb,
+            X = torch.from_numpy(synth.random_eom_vectors(sysm.kmesh, sysm.nocc, sysm.nvir, part, 0, args.batch,
                                                           seed=11)).cuda()
             for _ in range(3):
                 ctx.sigma(part, 0, X)
         torch.cuda.synchronize()
         ctx.close()
-        print(json.dumps({"probe": "sigma", "nvec": nb, "products": 3}))
+        print(json.dumps({"probe": "sigma", "nvec": args.batch, "products": 3, "precision": args.probe_precision}))
         return
 
-    def freqs(i):
-        # frequencies i, i + stride, ... : every step samples the whole grid
-        return omega[(i % stride)::stride][:args.nw]
+    forms = [f for f in args.forms.split(",") if f]
+    res = {}
+    for form in forms:
+        t0 = time.perf_counter()
+        ctx = Context(sysm, timing=True, precision=PRECISION[form], **opts)
+        init_s = time.perf_counter() - t0
 
-    def step(i):
-        # every step solves the same batch: all orbitals at the frequencies of step 0
-        return ctx.solve([0], orbs, freqs(0), eta, allow_noconv=True)
+        def step():
+            # one pass over the batch: IP then EA solves of all orbitals x frequencies, G = G- + G+
+            _, _, Gm, sti = ctx.solve([0], orbs, wsel, eta, parts="ip", allow_noconv=True)
+            print(f"{form} IP: {sti['seconds']:.1f} s", file=sys.stderr, flush=True)
+            _, Gp, _, ste = ctx.solve([0], orbs, wsel, eta, parts="ea", allow_noconv=True)
+            print(f"{form} EA: {ste['seconds']:.1f} s", file=sys.stderr, flush=True)
+            return Gm + Gp, sti, ste
 
-    for i in range(args.warmup):
-        print(f"warmup step {i}", file=sys.stderr, flush=True)
-        step(i)
-    torch.cuda.synchronize()
-    tot = {"big_ms": 0.0, "big_launches": 0, "big_flops": 0.0, "n_sigma": 0, "n_iterations": 0,
-           "sigma_ms": 0.0, "n_solves": 0, "max_rel_residual": 0.0, "n_unconverged": 0}
-    sig_parts = {"ea": 0, "ip": 0}
-    t1 = time.perf_counter()
-    results = []
-    for i in range(args.steps):
-        G, Gp, Gm, st = step(args.warmup + i)
-        results.append((args.warmup + i, G))
-        for k in tot:
-            if k == "max_rel_residual":
-                tot[k] = max(tot[k], st[k])
-            else:
-                tot[k] += st[k]
-        print(f"step {i}: {st['seconds']:.2f} s, {st['n_iterations']} iterations", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t1
-    points = args.steps * nmo * args.nw
-    value = points / elapsed
+        for i in range(args.warmup):
+            print(f"{form} warmup step {i}", file=sys.stderr, flush=True)
+            step()
+        torch.cuda.synchronize()
+        tot = {"big_ms": 0.0, "big_launches": 0, "big_flops": 0.0, "n_iterations": 0, "sigma_ms": 0.0,
+               "n_solves": 0, "max_rel_residual": 0.0, "n_unconverged": 0, "n_steps": 0, "n_reorth": 0}
+        nsig = {"ip": 0, "ea": 0}
+        t1 = time.perf_counter()
+        for i in range(args.steps):
+            G, sti, ste = step()
+            for st in (sti, ste):
+                for k in tot:
+                    tot[k] = max(tot[k], st[k]) if k == "max_rel_residual" else tot[k] + st[k]
+            nsig["ip"] += sti["n_sigma"]
+            nsig["ea"] += ste["n_sigma"]
+            print(f"{form} step {i}: {sti['seconds'] + ste['seconds']:.2f} s, "
+                  f"{sti['n_iterations'] + ste['n_iterations']} iterations", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t1
+        ctx.close()
+        avg_ms = tot["big_ms"] / max(tot["big_launches"], 1)
+        fl = tot["big_flops"] / max(tot["big_launches"], 1)
+        ach = fl / (avg_ms * 1e-3) if avg_ms > 0 else 0.0
+        res[form] = {
+            "points_per_s": args.steps * nb / elapsed,
+            "ms_per_step": 1e3 * elapsed / args.steps,
+            "G": G,
+            "iterations_per_solve": tot["n_iterations"] / max(tot["n_solves"], 1),
+            "batched_steps": tot["n_steps"],
+            "mean_active": tot["n_iterations"] / max(tot["n_steps"], 1),
+            "reorth_fraction": tot["n_reorth"] / max(tot["n_iterations"], 1),
+            "sigma_per_point": {p: nsig[p] / (args.steps * nb) for p in nsig},
+            "sigma_ms_share": tot["sigma_ms"] / (1e3 * elapsed),
+            "max_rel_residual": tot["max_rel_residual"],
+            "unconverged": tot["n_unconverged"],
+            "init_s": init_s,
+            "roofline": {"bound": "mfma", "kernel": GEMM_NAME[form] + " (EA 1/2 W_abcd r_i^cd)",
+                         "achieved": ach / 1e12, "peak": PEAK[form] / 1e12, "unit": "TFLOP/s",
+                         "frac": ach / PEAK[form], "avg_ms": avg_ms, "flops_per_launch": fl,
+                         "launches": tot["big_launches"]},
+        }
 
-    # per-part sigma counts for the CPU baseline scaling: one more step with one part at a time
-    sl = freqs(0)
-    for part in ("ea", "ip"):
-        _, _, _, stp = ctx.solve([0], orbs, sl, eta, parts=part, allow_noconv=True)
-        sig_parts[part] = stp["n_sigma"] / (nmo * args.nw)
-    # accuracy of the timed tolerance against a tight solve of the same points (one frequency)
-    ctx_t = Context(sysm, tol=1e-11, restart_m=args.restart, maxiter=2 * args.maxiter, max_batch=nmo,
-                    precond_eta=args.precond_eta)
-    Gt, _, _, stt = ctx_t.solve([0], orbs, sl[:1], eta, allow_noconv=True)
-    ctx_t.close()
-    Gchk, _, _, _ = ctx.solve([0], orbs, sl[:1], eta, allow_noconv=True)
-    rel = float(np.max(np.abs(Gchk - Gt).max(axis=-1) / np.abs(Gt).max(axis=-1)))
-    ctx.close()
+    ref = None
+    if not args.no_check:
+        # tight plain-FP64 solve of every `check_every`-th frequency of the step, all orbitals
+        sub = slice(None, None, args.check_every)
+        ctx = Context(sysm, **dict(opts, tol=args.ref_tol, maxiter=3 * args.maxiter))
+        _, _, Gm, sti = ctx.solve([0], orbs, wsel[sub], eta, parts="ip", allow_noconv=True)
+        print(f"reference IP: {sti['seconds']:.1f} s", file=sys.stderr, flush=True)
+        _, Gp, _, ste = ctx.solve([0], orbs, wsel[sub], eta, parts="ea", allow_noconv=True)
+        print(f"reference EA: {ste['seconds']:.1f} s", file=sys.stderr, flush=True)
+        ctx.close()
+        ref = {"G": Gm + Gp, "tol": args.ref_tol, "unconverged": sti["n_unconverged"] + ste["n_unconverged"],
+               "points": int(Gm.shape[1] * Gm.shape[2])}
+        for form in res:
+            res[form]["max_rel_err"] = col_err(res[form]["G"][:, :, sub], ref["G"])
 
-    avg_ms = tot["big_ms"] / max(tot["big_launches"], 1)
-    flops_per_launch = tot["big_flops"] / max(tot["big_launches"], 1)
-    achieved = flops_per_launch / (avg_ms * 1e-3) if avg_ms > 0 else 0.0
+    def meets(f):
+        return ref is not None and res[f]["max_rel_err"] <= TARGET and res[f]["unconverged"] == 0
+
+    ok = [f for f in res if meets(f)] or list(res)
+    head = max(ok, key=lambda f: res[f]["points_per_s"])
+    h = res[head]
+    roof = dict(h["roofline"])
+    tr = stored_traffic(GEMM_NAME[head])
+    roof["traffic"] = tr["bytes_per_launch"] if tr else None
+    if tr:
+        roof["traffic_note"] = tr.get("note", "")
+    forms_out = {}
+    for f, r in res.items():
+        forms_out[f] = {k: v for k, v in r.items() if k not in ("G",)}
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": h["points_per_s"],
         "unit": "G(w) points/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": h["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128",
+        "dtype": "c64 sigma / c128 Krylov" if head == "mixed_f32" else "c128",
         "data": "synthetic",
         "config": {
             "workload": (f"{args.workload}: Si-like {sysm.kmesh[0]}x{sysm.kmesh[1]}x{sysm.kmesh[2]} k-mesh, "
                          f"{sysm.nocc} occ + {sysm.nvir} vir spin orbitals/cell, K=Gamma, {nmo} orbitals x "
                          f"{args.nw} omega per step (every {stride}th point of the {len(omega)}-point grid on "
-                         f"[-1,1] Ha), eta={eta}, plain FP64 GMRES({args.restart}) tol={args.tol}, "
-                         f"preconditioner damping {args.precond_eta} Ha, maxiter {args.maxiter}"),
-            "points_per_step": nmo * args.nw,
-            "precision": "plain_f64",
+                         f"[-1,1] Ha), eta={eta}, GMRES({args.restart}) tol={args.tol}, {args.batch} right-hand "
+                         f"sides in flight, preconditioner damping {args.precond_eta} Ha, maxiter {args.maxiter}"),
+            "form": head,
+            "points_per_step": nb,
         },
-        "accuracy": {"max_rel_err_vs_tol1e-11": rel, "reference_unconverged": stt["n_unconverged"],
-                     "max_rel_residual": tot["max_rel_residual"], "unconverged": tot["n_unconverged"]},
-        "solver": {"iterations_per_solve": tot["n_iterations"] / max(tot["n_solves"], 1),
-                   "sigma_ms_share": tot["sigma_ms"] / (1e3 * elapsed),
-                   "init_s": init_s},
-        "roofline": {"bound": "mfma", "kernel": "k_cgemm_f64<0> (EA 1/2 W_abcd r_i^cd)",
-                     "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64, "traffic": None,
-                     "avg_ms": avg_ms, "flops_per_launch": flops_per_launch},
+        "accuracy": {"target_rel_err": TARGET, "reference_tol": args.ref_tol,
+                     "checked_points": ref["points"] if ref else 0,
+                     "reference_unconverged": ref["unconverged"] if ref else None,
+                     "max_rel_err": h.get("max_rel_err"), "meets_target": meets(head)},
+        "forms": forms_out,
+        "speedup_vs_plain_f64": (h["points_per_s"] / res["plain_f64"]["points_per_s"]
+                                 if "plain_f64" in res else None),
+        "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sysm, sig_parts, args.cpu_sample_s)
+        out["cpu_baseline"] = cpu_baseline(sysm, h["sigma_per_point"], args.cpu_sample_s)
     print(json.dumps(out), flush=True)
 
 

@@ -99,6 +99,10 @@ typedef struct {
                          0 -> eta.  Changes only the iteration count, not the solution. */
   int recycle_k;      /* GCROT(m,k): correction pairs (u, A u) kept across cycles, 0..200;
                          0 -> restarted GMRES(m). */
+  double reorth_ratio; /* second Gram-Schmidt pass for a right-hand side when one pass leaves
+                          less than this fraction of ||w|| (Daniel-Gragg-Kaufman-Stewart test,
+                          whose classical value is 1/sqrt(2)); 0 -> 0.1; 1 -> always two passes;
+                          range [0, 1]. */
 } ccgf_options;
 
 typedef struct {
@@ -115,6 +119,8 @@ typedef struct {
   double big_flops;          /* its algorithmic flops (8 per complex multiply-add) */
   double sigma_ms;           /* time in whole sigma products */
   long long sigma_launches;  /* sigma products (each over a batch of vectors) */
+  long long n_steps;         /* batched Arnoldi steps (one sigma product over the active batch each) */
+  long long n_reorth;        /* right-hand-side steps that needed the second Gram-Schmidt pass */
 } ccgf_stats;
 
 /* Validates the system (shapes, t2 antisymmetry, factor Hermiticity, each to

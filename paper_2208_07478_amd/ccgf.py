@@ -37,7 +37,8 @@ class System(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("restart_m", ctypes.c_int), ("maxiter", ctypes.c_int),
                 ("tol", ctypes.c_double), ("max_batch", ctypes.c_int), ("hip_stream", ctypes.c_void_p),
-                ("timing", ctypes.c_int), ("precond_eta", ctypes.c_double), ("recycle_k", ctypes.c_int)]
+                ("timing", ctypes.c_int), ("precond_eta", ctypes.c_double), ("recycle_k", ctypes.c_int),
+                ("reorth_ratio", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -47,7 +48,8 @@ class Stats(ctypes.Structure):
                 ("seconds", ctypes.c_double),
                 ("big_ms", ctypes.c_double), ("big_launches", ctypes.c_longlong),
                 ("big_flops", ctypes.c_double), ("sigma_ms", ctypes.c_double),
-                ("sigma_launches", ctypes.c_longlong)]
+                ("sigma_launches", ctypes.c_longlong), ("n_steps", ctypes.c_longlong),
+                ("n_reorth", ctypes.c_longlong)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -111,7 +113,8 @@ class Context:
     """One system on the GPU (wraps cc_gf_init / cc_gf_free)."""
 
     def __init__(self, system, *, tol=1e-10, restart_m=30, maxiter=2000, max_batch=64, stream=None,
-                 timing=False, foo=None, fvv=None, precond_eta=0.0, recycle_k=0, precision="f64"):
+                 timing=False, foo=None, fvv=None, precond_eta=0.0, recycle_k=0, precision="f64",
+                 reorth_ratio=0.0):
         lib = load()
         import torch  # device memory and streams only
         self._torch = torch
@@ -138,7 +141,7 @@ class Context:
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         opt = Options(prec, int(restart_m), int(maxiter), float(tol), int(max_batch),
                       ctypes.c_void_p(stream.cuda_stream), 1 if timing else 0, float(precond_eta),
-                      int(recycle_k))
+                      int(recycle_k), float(reorth_ratio))
         self._opt = opt
         h = ctypes.c_void_p()
         rc = lib.cc_gf_init(ctypes.byref(cs), ctypes.byref(opt), ctypes.byref(h))

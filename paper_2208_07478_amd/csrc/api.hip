@@ -111,7 +111,7 @@ extern "C" int cc_gf_init(const ccgf_system *s, const ccgf_options *opt, ccgf_ct
   if (o.tol == 0) o.tol = 1e-10;
   if (o.max_batch == 0) o.max_batch = 64;
   if (o.restart_m < 1 || o.restart_m > 2000 || o.maxiter < 1 || o.tol < 0 || o.max_batch < 1 ||
-      o.recycle_k < 0 || o.recycle_k > 200 || o.precond_eta < 0)
+      o.recycle_k < 0 || o.recycle_k > 200 || o.precond_eta < 0 || o.reorth_ratio < 0 || o.reorth_ratio > 1)
     return set_err(nullptr, CCGF_EINVAL, "options out of range");
 
   ccgf_ctx *c = new ccgf_ctx();
@@ -296,6 +296,7 @@ extern "C" int cc_gf_solve(ccgf_ctx *c, int nkq, const int *kidx, int norb, cons
   if (Gp) std::memcpy(Gp, Gplus.data(), sizeof(cplx) * ntot);
   if (Gm) std::memcpy(Gm, Gminus.data(), sizeof(cplx) * ntot);
   S->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  timing_harvest(c);
   S->big_ms = c->t_big_ms;
   S->big_launches = c->t_big_launches;
   S->big_flops = c->t_big_flops;
@@ -364,6 +365,7 @@ extern "C" int cc_gf_mor(ccgf_ctx *c, int nkq, const int *kidx, int norb, const 
   if (Gp) std::memcpy(Gp, Gplus.data(), sizeof(cplx) * ntot);
   if (Gm) std::memcpy(Gm, Gminus.data(), sizeof(cplx) * ntot);
   S->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  timing_harvest(c);
   S->big_ms = c->t_big_ms;
   S->big_launches = c->t_big_launches;
   S->big_flops = c->t_big_flops;
@@ -375,8 +377,7 @@ extern "C" int cc_gf_mor(ccgf_ctx *c, int nkq, const int *kidx, int norb, const 
 extern "C" void cc_gf_free(ccgf_ctx *c) {
   if (!c) return;
   hipStreamSynchronize(c->stream);
-  for (int q = 0; q < 4; ++q)
-    if (c->ev[q]) hipEventDestroy(c->ev[q]);
+  timing_release(c);
   free_all(c);
   delete c;
 }

@@ -132,7 +132,15 @@ struct ccgf_ctx {
   size_t sig_part_elems = 0;
   std::vector<SigmaPlan> plans;
   // event timing of the sigma products (options.timing)
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // sigma timing (options.timing): events of recent products, read once they have completed
+  struct TimedSigma {
+    hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};  // sigma start, sigma end, big GEMM start, end
+    int big = 0;           // count the big GEMM (EA products)
+    double flops = 0;      // its algorithmic flops
+    bool pending = false;
+  };
+  std::vector<TimedSigma> tring;
+  int tnext = 0;
   double t_big_ms = 0, t_big_flops = 0, t_sigma_ms = 0;
   long long t_big_launches = 0, t_sigma_launches = 0;
 };
@@ -149,6 +157,9 @@ long long vec_len(const ccgf_ctx *c, int part);
 
 // sigma.hip
 int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y, int prec = 0);
+// Accumulate the timings of the recorded sigma products (waits for any still running).
+void timing_harvest(ccgf_ctx *c);
+void timing_release(ccgf_ctx *c);
 void gemm_launch(int tag, const GemmPlan &plan, const void *A, const cplx *B, cplx *C, hipStream_t s, int prec);
 void plan_upload(ccgf_ctx *c, GemmPlan &p);
 

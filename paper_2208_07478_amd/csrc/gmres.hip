@@ -6,9 +6,14 @@
 // correction u and its image c = A u, which join a recycled set of the k most
 // recent (u, c) pairs (k = 0 is restarted GMRES(m)).  Classical Gram-Schmidt is
 // applied twice (CGS2) against C and the Arnoldi basis, and complex Givens
-// rotations solve the Hessenberg least-squares problem, all in FP64.  All
-// right-hand sides of one momentum K and part (orbitals x frequencies) advance
-// together, so one sigma product per step serves the whole batch.  Inner
+// rotations solve the Hessenberg least-squares problem, all in FP64.  The
+// second Gram-Schmidt pass runs only where the first left less than a set
+// fraction of ||w|| (0.1 by default: with the damped diagonal preconditioner
+// nearly every step loses more than the classical 1/sqrt(2), and the extra pass
+// then doubles the orthogonalisation traffic for little gain in convergence).
+// The right-hand sides of one momentum K and part (orbitals x frequencies) share
+// a batch of slots that is refilled as solves finish, so one sigma product per
+// step serves the whole batch.  Inner
 // products count each unordered pair once (weight 1/2 on the doubly stored
 // 2h1p / 2p1h part), which makes full antisymmetric storage an isometric copy
 // of the unique-coefficient space.  G = e . x is bilinear (Eq. 7).
@@ -52,13 +57,16 @@ __device__ inline cplx block_sum(cplx v, double *sh) {
 }
 
 // partial[v][chunk][i] = sum_{x in chunk} wgt(x) * op(U_i[v][x]) * W[v][x],
-// U_i[v] = U + uoff[v] + i * su_i (op = conj if conjU), W[v] = W + v * n
+// U_i[v] = U + uoff[v] + i * su_i (op = conj if conjU), W[v] = W + v * n,
+// i < ni0 (+ nlist[v] when a per-slot count is given)
 __global__ __launch_bounds__(256) void k_dots(const cplx *__restrict__ U, const long long *__restrict__ uoff,
-                                              long long su_i, int ni, const cplx *__restrict__ W, long long n,
+                                              long long su_i, int ni0, const cplx *__restrict__ W, long long n,
                                               int n1, int conjU, const int *__restrict__ active,
-                                              cplx *__restrict__ partial, int nchunk, int ldp) {
+                                              cplx *__restrict__ partial, int nchunk, int ldp,
+                                              const int *__restrict__ nlist) {
   const int v = blockIdx.y, ch = blockIdx.x;
   if (active && !active[v]) return;
+  const int ni = nlist ? nlist[v] + ni0 : ni0;
   __shared__ double sh[16];
   const long long base = (long long)ch * DOT_CHUNK;
   cplx wv[DOT_ITEMS];
@@ -84,12 +92,16 @@ __global__ __launch_bounds__(256) void k_dots(const cplx *__restrict__ U, const 
   }
 }
 
-// out[v][i] = sum_chunk partial; if H != null also H[v][i][col] += out (and H2 likewise)
-__global__ void k_dots_reduce(const cplx *__restrict__ partial, int nchunk, int ldp, int ni,
+// out[v][i] = sum_chunk partial; if H != null also H[v][i][col] += out (and H2 likewise);
+// per-slot counts and columns as in k_dots
+__global__ void k_dots_reduce(const cplx *__restrict__ partial, int nchunk, int ldp, int ni0,
                               const int *__restrict__ active, cplx *__restrict__ out, int ldo,
-                              cplx *__restrict__ H, int ldh, long long shv, int col, cplx *__restrict__ H2 = nullptr) {
+                              cplx *__restrict__ H, int ldh, long long shv, int col0, cplx *__restrict__ H2,
+                              const int *__restrict__ nlist, const int *__restrict__ colv) {
   const int v = blockIdx.x;
   if (active && !active[v]) return;
+  const int ni = nlist ? nlist[v] + ni0 : ni0;
+  const int col = colv ? colv[v] : col0;
   for (int i = threadIdx.x; i < ni; i += blockDim.x) {
     cplx s = mkc(0, 0);
     for (int ch = 0; ch < nchunk; ++ch) s = cadd(s, partial[((size_t)v * nchunk + ch) * ldp + i]);
@@ -107,10 +119,11 @@ __global__ void k_dots_reduce(const cplx *__restrict__ partial, int nchunk, int 
 
 // W[v] -= sum_i h[v][i] * V_i[v],  V_i[v] = V + i * svi + v * n
 __global__ __launch_bounds__(256) void k_sub_proj(cplx *__restrict__ W, const cplx *__restrict__ V, long long svi,
-                                                  long long n, int ni, const cplx *__restrict__ h, int ldh,
-                                                  const int *__restrict__ active) {
+                                                  long long n, int ni0, const cplx *__restrict__ h, int ldh,
+                                                  const int *__restrict__ active, const int *__restrict__ nlist) {
   const int v = blockIdx.y;
   if (active && !active[v]) return;
+  const int ni = nlist ? nlist[v] + ni0 : ni0;
   long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= n) return;
   cplx acc = W[(size_t)v * n + x];
@@ -169,14 +182,15 @@ __global__ void k_precond(cplx *__restrict__ z, const cplx *__restrict__ Vj, con
   z[(size_t)v * n + x] = mkc((u.x * dd.x + u.y * dd.y) / den, (u.y * dd.x - u.x * dd.y) / den);
 }
 
-// compact gather: z[slot] = X[idx[slot]] / (shift + sM diag)  (sM = 0 and nodiv: plain copy)
+// compact gather: z[slot] = X[idx[slot]] / (shift + sM diag)  (sM = 0 and nodiv: plain copy);
+// with jv the source is column jv[v] of a basis with stride svi
 __global__ void k_gather_precond(cplx *__restrict__ z, const cplx *__restrict__ X, const cplx *__restrict__ diag,
                                  const cplx *__restrict__ shift, double sM, long long n, const int *__restrict__ idx,
-                                 int divide) {
+                                 int divide, const int *__restrict__ jv, long long svi) {
   const int slot = blockIdx.y, v = idx[slot];
   long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= n) return;
-  cplx u = X[(size_t)v * n + x];
+  cplx u = X[(jv ? (size_t)jv[v] * svi : 0) + (size_t)v * n + x];
   if (divide) {
     cplx dd = cadd(shift[v], cscale(diag[x], sM));
     double den = dd.x * dd.x + dd.y * dd.y;
@@ -237,22 +251,41 @@ __global__ void k_scale(cplx *out, const cplx *w, const double *__restrict__ inv
 }
 
 // out[idx[slot]] = w[idx[slot]] * inv[idx[slot]]
+// out column jv[v] + 1 (stride svi) of slot idx[...] = w * inv
 __global__ void k_scale_idx(cplx *__restrict__ out, const cplx *__restrict__ w, const double *__restrict__ inv,
-                            long long n, const int *__restrict__ idx) {
+                            long long n, const int *__restrict__ idx, const int *__restrict__ jv, long long svi) {
   const int v = idx[blockIdx.y];
   long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= n) return;
-  out[(size_t)v * n + x] = cscale(w[(size_t)v * n + x], inv[v]);
+  out[(size_t)(jv[v] + 1) * svi + (size_t)v * n + x] = cscale(w[(size_t)v * n + x], inv[v]);
 }
 
-// One Givens step per right-hand side (column j of its Hessenberg matrix).
+// Start an Arnoldi cycle in the flagged slots: zero H, H0 and the recycled-space
+// coefficients, g = (||r||, 0, ...), no columns used yet.
+__global__ void k_cycle_start(int m, int kslots, const int *__restrict__ start, const double *__restrict__ rn,
+                              cplx *__restrict__ H, cplx *__restrict__ H0, cplx *__restrict__ Bm,
+                              cplx *__restrict__ g, int *__restrict__ kused) {
+  const int v = blockIdx.x;
+  if (!start[v]) return;
+  const size_t hs = (size_t)(m + 1) * m;
+  for (size_t i = threadIdx.x; i < hs; i += blockDim.x) {
+    H[(size_t)v * hs + i] = mkc(0, 0);
+    H0[(size_t)v * hs + i] = mkc(0, 0);
+  }
+  for (size_t i = threadIdx.x; i < (size_t)kslots * m; i += blockDim.x) Bm[(size_t)v * kslots * m + i] = mkc(0, 0);
+  for (int i = threadIdx.x; i <= m; i += blockDim.x) g[(size_t)v * (m + 1) + i] = mkc(i == 0 ? rn[v] : 0.0, 0);
+  if (threadIdx.x == 0) kused[v] = 0;
+}
+
+// One Givens step per right-hand side (column jv[v] of its Hessenberg matrix).
 // H[v] is (m+1) x m row-major with leading dimension m.
-__global__ void k_givens(int nvec, int m, int j, cplx *__restrict__ H, cplx *__restrict__ cs, cplx *__restrict__ sn,
-                         cplx *__restrict__ g, const cplx *__restrict__ nrm2, int ldn, double *__restrict__ inv,
-                         int *__restrict__ active, int *__restrict__ kused, const double *__restrict__ thresh,
-                         const int *__restrict__ jlim, cplx *__restrict__ H0) {
+__global__ void k_givens(int nvec, int m, const int *__restrict__ jv, cplx *__restrict__ H, cplx *__restrict__ cs,
+                         cplx *__restrict__ sn, cplx *__restrict__ g, const cplx *__restrict__ nrm2, int ldn,
+                         double *__restrict__ inv, int *__restrict__ active, int *__restrict__ kused,
+                         const double *__restrict__ thresh, const int *__restrict__ jlim, cplx *__restrict__ H0) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nvec || !active[v]) return;
+  const int j = jv[v];
   cplx *Hv = H + (size_t)v * (m + 1) * m;
   cplx *c = cs + (size_t)v * m, *s = sn + (size_t)v * m, *gv = g + (size_t)v * (m + 1);
   double hn = sqrt(fmax(nrm2[(size_t)v * ldn].x, 0.0));
@@ -286,21 +319,26 @@ __global__ void k_givens(int nvec, int m, int j, cplx *__restrict__ H, cplx *__r
   if (res <= thresh[v] || hn == 0.0 || j + 1 >= jlim[v]) active[v] = 0;
 }
 
-// y = R^-1 g (upper triangular, kused[v] columns), in place into ysol
+// y = R^-1 g (upper triangular, kused[v] columns) into ysol; one block per slot,
+// column-oriented back substitution (the updates of each column run in parallel)
 __global__ void k_backsolve(int nvec, int m, const cplx *__restrict__ H, const cplx *__restrict__ g,
                             const int *__restrict__ kused, cplx *__restrict__ ysol, const int *__restrict__ done) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.x;
   if (v >= nvec || done[v]) return;
   const cplx *Hv = H + (size_t)v * (m + 1) * m;
-  const cplx *gv = g + (size_t)v * (m + 1);
   cplx *y = ysol + (size_t)v * m;
-  int k = kused[v];
-  for (int i = k - 1; i >= 0; --i) {
-    cplx s = gv[i];
-    for (int l = i + 1; l < k; ++l) s = csub(s, cmul(Hv[(size_t)i * m + l], y[l]));
-    cplx d = Hv[(size_t)i * m + i];
+  const int k = kused[v];
+  for (int i = threadIdx.x; i < k; i += blockDim.x) y[i] = g[(size_t)v * (m + 1) + i];
+  __syncthreads();
+  for (int l = k - 1; l >= 0; --l) {
+    cplx d = Hv[(size_t)l * m + l];
     double den = d.x * d.x + d.y * d.y;
-    y[i] = den > 0 ? mkc((s.x * d.x + s.y * d.y) / den, (s.y * d.x - s.x * d.y) / den) : mkc(0, 0);
+    cplx s = y[l];
+    cplx yl = den > 0 ? mkc((s.x * d.x + s.y * d.y) / den, (s.y * d.x - s.x * d.y) / den) : mkc(0, 0);
+    __syncthreads();  // every thread has read y[l]
+    if (threadIdx.x == 0) y[l] = yl;
+    for (int i = threadIdx.x; i < l; i += blockDim.x) y[i] = csub(y[i], cmul(Hv[(size_t)i * m + l], yl));
+    __syncthreads();
   }
 }
 
@@ -325,28 +363,29 @@ __global__ void k_take_norm(int nvec, const cplx *__restrict__ nrm2, int ld, dou
   w0n[v] = nrm2[(size_t)v * ld].x;
 }
 
-// second Gram-Schmidt pass only where one pass lost more than half of ||w||^2
+// second Gram-Schmidt pass only where one pass left less than ratio2 of ||w||^2
 __global__ void k_need_reorth(int nvec, const cplx *__restrict__ nrm2, int ld, const double *__restrict__ w0n,
-                              const int *__restrict__ active, int *__restrict__ need) {
+                              const int *__restrict__ active, int *__restrict__ need, double ratio2) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nvec) return;
-  need[v] = active[v] && nrm2[(size_t)v * ld].x < 0.5 * w0n[v];
+  need[v] = active[v] && nrm2[(size_t)v * ld].x < ratio2 * w0n[v];
 }
 
-// t = Bm y (recycled-space coefficients, kc entries) and d = H0 y (kused + 1 entries)
+// t = Bm y (recycled-space coefficients, kc entries) and d = H0 y (kused + 1 entries);
+// one block per slot, one thread per output entry
 __global__ void k_gcrot_small(int nvec, int m, int kc, const cplx *__restrict__ Bm, const cplx *__restrict__ H0,
                               const cplx *__restrict__ ysol, const int *__restrict__ kused, cplx *__restrict__ t,
                               cplx *__restrict__ d, const int *__restrict__ skip, int ldt) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.x;
   if (v >= nvec || skip[v]) return;
   const int k = kused[v];
   const cplx *y = ysol + (size_t)v * m;
-  for (int l = 0; l < kc; ++l) {
+  for (int l = threadIdx.x; l < kc; l += blockDim.x) {
     cplx acc = mkc(0, 0);
     for (int i = 0; i < k; ++i) cfma(acc, Bm[(size_t)v * ldt * m + (size_t)l * m + i], y[i]);
     t[(size_t)v * ldt + l] = acc;
   }
-  for (int r = 0; r <= k; ++r) {
+  for (int r = threadIdx.x; r <= k; r += blockDim.x) {
     cplx acc = mkc(0, 0);
     for (int i = 0; i < k; ++i) cfma(acc, H0[(size_t)v * (m + 1) * m + (size_t)r * m + i], y[i]);
     d[(size_t)v * (m + 1) + r] = acc;
@@ -553,6 +592,8 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
   int *jlim = (int *)walloc(W, sizeof(int) * Bmax);
   int *aidx = (int *)walloc(W, sizeof(int) * Bmax);
   int *need = (int *)walloc(W, sizeof(int) * Bmax);
+  int *fmask = (int *)walloc(W, sizeof(int) * Bmax);
+  int *jvd = (int *)walloc(W, sizeof(int) * Bmax);
   double *w0n = (double *)walloc(W, sizeof(double) * Bmax);
   long long *uoff = (long long *)walloc(W, sizeof(long long) * Bmax);
   long long *eoff = (long long *)walloc(W, sizeof(long long) * Bmax);
@@ -566,9 +607,11 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
 
   int status = CCGF_OK;
   const double peta = std::max(eta, c->opt.precond_eta);
-  std::vector<cplx> hshift(Bmax), hpshift(Bmax), hh((size_t)Bmax * ldp), g0((size_t)Bmax * (m + 1));
+  const double rr = c->opt.reorth_ratio > 0 ? c->opt.reorth_ratio : 0.1;
+  const double ratio2 = rr * rr;
+  std::vector<cplx> hshift(Bmax), hpshift(Bmax), hh((size_t)Bmax * ldp);
   std::vector<double> hbnorm(Bmax), hthr(Bmax), hrn(Bmax), hinv(Bmax);
-  std::vector<int> hconv(Bmax), hkused(Bmax), hact(Bmax), hskip(Bmax), its(Bmax), hjlim(Bmax);
+  std::vector<int> hconv(Bmax), hkused(Bmax), hact(Bmax), hskip(Bmax), its(Bmax), hjlim(Bmax), hneed(Bmax);
   std::vector<long long> hoff(Bmax), heoff(Bmax);
   std::vector<int> alist;
   alist.reserve(Bmax);
@@ -581,16 +624,16 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
   // weighted squared norms of the B vectors at Xp into hh[v * ldp]
   auto norms = [&](const cplx *Xp, int B) {
     hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Xp, uoff, 0LL, 1, Xp, n, n1, 1,
-                       (const int *)nullptr, partial, nchunk, ldp);
+                       (const int *)nullptr, partial, nchunk, ldp, (const int *)nullptr);
     hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, 1, (const int *)nullptr, htmp,
-                       ldp, (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr);
+                       ldp, (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
   };
   // true residual b - A x of the listed right-hand sides into R and its norm into hh
   auto true_residual = [&](int B) -> int {
     const int np = (int)alist.size();
     if (np == 0) return CCGF_OK;
     hipMemcpyAsync(aidx, alist.data(), sizeof(int) * np, hipMemcpyHostToDevice, s);
-    hipLaunchKernelGGL(k_gather_precond, dim3(gx, np), dim3(256), 0, s, Z, X, diag, shift, 0.0, n, aidx, 0);
+    hipLaunchKernelGGL(k_gather_precond, dim3(gx, np), dim3(256), 0, s, Z, X, diag, shift, 0.0, n, aidx, 0, (const int *)nullptr, 0LL);
     int rc = sigma_apply(c, part, K, np, Z, Wc);
     if (rc != CCGF_OK) return rc;
     if (st) st->n_sigma += np;
@@ -600,214 +643,47 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
     return sync("true residual");
   };
 
-  for (int r0 = 0; r0 < nrhs; r0 += Bmax) {
-    const int B = std::min(Bmax, nrhs - r0);
-    for (int v = 0; v < B; ++v) {
-      hshift[v] = mkc(rhs_omega[r0 + v], sE * eta);
-      hpshift[v] = mkc(rhs_omega[r0 + v], sE * peta);
-      hoff[v] = (long long)v * n;  // each RHS's own vector inside a [B][n] batch
-      heoff[v] = (long long)rhs_orb[r0 + v] * n;
-      hipMemcpyAsync(Bv + (size_t)v * n, Bvecs + (size_t)rhs_orb[r0 + v] * n, sizeof(cplx) * n,
-                     hipMemcpyDeviceToDevice, s);
-    }
-    hipMemcpyAsync(shift, hshift.data(), sizeof(cplx) * B, hipMemcpyHostToDevice, s);
-    hipMemcpyAsync(pshift, hpshift.data(), sizeof(cplx) * B, hipMemcpyHostToDevice, s);
-    hipMemcpyAsync(uoff, hoff.data(), sizeof(long long) * B, hipMemcpyHostToDevice, s);
-    hipMemcpyAsync(eoff, heoff.data(), sizeof(long long) * B, hipMemcpyHostToDevice, s);
-    hipMemsetAsync(X, 0, sizeof(cplx) * (size_t)B * n, s);
-    hipMemcpyAsync(R, Bv, sizeof(cplx) * (size_t)B * n, hipMemcpyDeviceToDevice, s);  // x0 = 0: r0 = b
-    norms(Bv, B);
-    hipMemcpyAsync(hh.data(), htmp, sizeof(cplx) * B * ldp, hipMemcpyDeviceToHost, s);
-    if (int rc = sync("solver start")) {
-      wfree(W);
-      return rc;
-    }
-    for (int v = 0; v < B; ++v) {
-      hbnorm[v] = std::sqrt(std::max(hh[(size_t)v * ldp].x, 0.0));
-      hrn[v] = hbnorm[v];
-      hthr[v] = tol * hbnorm[v];
-      hconv[v] = hbnorm[v] == 0.0;
-      its[v] = 0;
-    }
-    hipMemcpyAsync(thresh, hthr.data(), sizeof(double) * B, hipMemcpyHostToDevice, s);
-    int cyc = 0;
-    while (true) {  // outer cycles
-      int npart = 0;
-      for (int v = 0; v < B; ++v) {
-        hact[v] = (!hconv[v] && its[v] < maxit) ? 1 : 0;
-        hskip[v] = !hact[v];
-        hjlim[v] = std::min(m, std::max(0, maxit - its[v]));  // iteration budget of this cycle
-        hinv[v] = hrn[v] > 0 ? 1.0 / hrn[v] : 0.0;
-        npart += hact[v];
-      }
-      if (npart == 0) break;
-      const int kc = std::min(cyc, kr);  // recycled pairs in use
-      const int slot = kr > 0 ? cyc % kr : 0;
-      hipMemcpyAsync(jlim, hjlim.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
-      hipMemcpyAsync(active, hact.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
-      hipMemcpyAsync(skip, hskip.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
-      hipMemcpyAsync(inv, hinv.data(), sizeof(double) * B, hipMemcpyHostToDevice, s);
-      hipLaunchKernelGGL(k_scale, dim3(gx, B), dim3(256), 0, s, V, R, inv, n, active);  // V_0 = r / ||r||
-      hipMemsetAsync(H, 0, sizeof(cplx) * B * (m + 1) * m, s);
-      hipMemsetAsync(H0, 0, sizeof(cplx) * B * (m + 1) * m, s);
-      hipMemsetAsync(Bm, 0, sizeof(cplx) * B * kslots * m, s);
-      std::fill(g0.begin(), g0.end(), mkc(0, 0));
-      for (int v = 0; v < B; ++v) g0[(size_t)v * (m + 1)] = mkc(hrn[v], 0);
-      hipMemcpyAsync(g, g0.data(), sizeof(cplx) * B * (m + 1), hipMemcpyHostToDevice, s);
-      hipMemsetAsync(kused, 0, sizeof(int) * B, s);
-      for (int j = 0; j < m; ++j) {
-        cplx *Vj = V + (size_t)j * svi;
-        // only the right-hand sides still iterating enter the sigma product
-        alist.clear();
-        for (int v = 0; v < B; ++v)
-          if (hact[v]) alist.push_back(v);
-        const int na = (int)alist.size();
-        hipMemcpyAsync(aidx, alist.data(), sizeof(int) * na, hipMemcpyHostToDevice, s);
-        hipLaunchKernelGGL(k_gather_precond, dim3(gx, na), dim3(256), 0, s, Z, Vj, diag, pshift, sM, n, aidx, 1);
-        int rc = sigma_apply(c, part, K, na, Z, Wc, c->opt.precision);
-        if (rc != CCGF_OK) {
-          wfree(W);
-          return rc;
-        }
-        if (st) st->n_sigma += na;
-        hipLaunchKernelGGL(k_scatter_shift, dim3(gx, na), dim3(256), 0, s, Wv, Z, Wc, shift, sM, n, aidx);
-        // ||w||^2 before projection (for the reorthogonalisation test)
-        hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Wv, uoff, 0LL, 1, Wv, n, n1, 1, active, partial,
-                           nchunk, ldp);
-        hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, 1, active, htmp, ldp,
-                           (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr);
-        hipLaunchKernelGGL(k_take_norm, dim3((B + 63) / 64), dim3(64), 0, s, B, htmp, ldp, w0n, active);
-        // classical Gram-Schmidt against the recycled C and V_0..V_j; a second pass only for the
-        // right-hand sides whose norm fell below 1/sqrt(2) of its value (Daniel-Gragg-Kaufman-Stewart)
-        for (int pass = 0; pass < 2; ++pass) {
-          const int *mask = pass == 0 ? active : need;
-          if (kc > 0) {
-            hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Cb, uoff, (long long)svi, kc, Wv, n, n1, 1,
-                               mask, partial, nchunk, ldp);
-            hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, kc, mask, htmp, ldp,
-                               Bm, m, (long long)kslots * m, j, (cplx *)nullptr);
-            hipLaunchKernelGGL(k_sub_proj, dim3(gx, B), dim3(256), 0, s, Wv, Cb, (long long)svi, n, kc, htmp, ldp,
-                               mask);
-          }
-          hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, V, uoff, (long long)svi, j + 1, Wv, n, n1, 1,
-                             mask, partial, nchunk, ldp);
-          hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, j + 1, mask, htmp, ldp,
-                             H, m, (long long)(m + 1) * m, j, H0);
-          hipLaunchKernelGGL(k_sub_proj, dim3(gx, B), dim3(256), 0, s, Wv, V, (long long)svi, n, j + 1, htmp, ldp,
-                             mask);
-          hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Wv, uoff, 0LL, 1, Wv, n, n1, 1, mask, partial,
-                             nchunk, ldp);
-          hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, 1, mask, htmp, ldp,
-                             (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr);
-          if (pass == 0)
-            hipLaunchKernelGGL(k_need_reorth, dim3((B + 63) / 64), dim3(64), 0, s, B, htmp, ldp, w0n, active, need);
-        }
-        hipLaunchKernelGGL(k_givens, dim3((B + 63) / 64), dim3(64), 0, s, B, m, j, H, cs, sn, g, htmp, ldp, inv,
-                           active, kused, thresh, jlim, H0);
-        // V_{j+1} = w / h_{j+1,j} (also for j + 1 = m: the image c = V H y uses it).  k_givens
-        // clears `active` of right-hand sides that finish here, so use this step's list aidx.
-        hipLaunchKernelGGL(k_scale_idx, dim3(gx, na), dim3(256), 0, s, V + (size_t)(j + 1) * svi, Wv, inv, n, aidx);
-        hipMemcpyAsync(hact.data(), active, sizeof(int) * B, hipMemcpyDeviceToHost, s);
-        if (int rc2 = sync("solver iteration")) {
-          wfree(W);
-          return rc2;
-        }
-        int any = 0;
-        for (int v = 0; v < B; ++v) any |= hact[v];
-        if (!any) break;  // every right-hand side has finished this cycle
-      }
-      // minimal-residual correction of this cycle and its image under A
-      hipLaunchKernelGGL(k_backsolve, dim3((B + 63) / 64), dim3(64), 0, s, B, m, H, g, kused, ysol, skip);
-      hipLaunchKernelGGL(k_gcrot_small, dim3((B + 63) / 64), dim3(64), 0, s, B, m, kc, Bm, H0, ysol, kused, tv, dv,
-                         skip, kslots);
-      cplx *us = Ub + (size_t)slot * svi, *cs_ = Cb + (size_t)slot * svi;
-      hipLaunchKernelGGL(k_gcrot_combine, dim3(gx, B), dim3(256), 0, s, n, m, (long long)svi, V, ysol, dv, kused, kc,
-                         Ub, tv, kslots, diag, pshift, sM, us, cs_, X, R, skip);
-      if (kr > 0) {  // normalise the new pair so that c has unit norm
-        norms(cs_, B);
-        hipLaunchKernelGGL(k_inv_sqrt, dim3((B + 63) / 64), dim3(64), 0, s, B, htmp, ldp, inv, skip);
-        hipLaunchKernelGGL(k_scale2, dim3(gx, B), dim3(256), 0, s, us, cs_, inv, n, skip);
-      }
-      norms(R, B);
-      hipMemcpyAsync(hh.data(), htmp, sizeof(cplx) * B * ldp, hipMemcpyDeviceToHost, s);
-      hipMemcpyAsync(hkused.data(), kused, sizeof(int) * B, hipMemcpyDeviceToHost, s);
-      if (int rc2 = sync("solver cycle")) {
-        wfree(W);
-        return rc2;
-      }
-      alist.clear();
-      for (int v = 0; v < B; ++v) {
-        if (hskip[v]) continue;
-        hrn[v] = std::sqrt(std::max(hh[(size_t)v * ldp].x, 0.0));
-        its[v] += hkused[v];
-        hconv[v] = hrn[v] <= tol * hbnorm[v];
-        // mixed precision: every cycle restarts from the FP64 true residual (iterative refinement)
-        if (hconv[v] || c->opt.precision != CCGF_PLAIN_F64) alist.push_back(v);
-      }
-      // confirm convergence with the true residual (the recursive one can drift)
-      if (!alist.empty()) {
-        std::vector<int> cand = alist;
-        if (int rc = true_residual(B)) {
-          wfree(W);
-          return rc;
-        }
-        std::vector<int> redo(B, 0);
-        int nredo = 0;
-        for (int v : cand) {
-          hrn[v] = std::sqrt(std::max(hh[(size_t)v * ldp].x, 0.0));
-          hconv[v] = hrn[v] <= tol * hbnorm[v];
-          if (!hconv[v]) redo[v] = 1, ++nredo;
-        }
-        const int kcn = std::min(cyc + 1, kr);
-        if (nredo && kcn > 0) {
-          // restore r _|_ C for the restarted residuals: x += U (C^H r), r -= C (C^H r)
-          hipMemcpyAsync(active, redo.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
-          hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Cb, uoff, (long long)svi, kcn, R, n, n1, 1,
-                             active, partial, nchunk, ldp);
-          hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, kcn, active, htmp, ldp,
-                             (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr);
-          hipLaunchKernelGGL(k_add_proj, dim3(gx, B), dim3(256), 0, s, X, Ub, (long long)svi, n, kcn, htmp, ldp,
-                             active);
-          hipLaunchKernelGGL(k_sub_proj, dim3(gx, B), dim3(256), 0, s, R, Cb, (long long)svi, n, kcn, htmp, ldp,
-                             active);
-          norms(R, B);
-          hipMemcpyAsync(hh.data(), htmp, sizeof(cplx) * B * ldp, hipMemcpyDeviceToHost, s);
-          if (int rc2 = sync("residual projection")) {
-            wfree(W);
-            return rc2;
-          }
-          for (int v = 0; v < B; ++v)
-            if (redo[v]) hrn[v] = std::sqrt(std::max(hh[(size_t)v * ldp].x, 0.0));
-        }
-      }
-      ++cyc;
-    }
-    // final true residual of right-hand sides that stopped unconverged (budget exhausted)
+  // Slots of the batch hold right-hand sides; a slot whose right-hand side has
+  // converged (or spent maxiter) is retired at the next cycle boundary (G = e.x,
+  // statistics) and refilled with the next pending right-hand side, so the batch
+  // stays full while any remain.  With recycling (GCROT) the recycled space
+  // belongs to the whole batch, which is therefore refilled only when empty.
+  const int B = Bmax;
+  const bool refill_each = kr == 0;
+  std::vector<int> rhs_of(B, -1);
+  int next = 0;
+  for (int v = 0; v < B; ++v) {
+    hoff[v] = (long long)v * n;  // each slot's own vector inside a [B][n] batch
+    heoff[v] = 0;
+    hconv[v] = 1;
+    its[v] = 0;
+    hbnorm[v] = hrn[v] = 0;
+  }
+  hipMemcpyAsync(uoff, hoff.data(), sizeof(long long) * B, hipMemcpyHostToDevice, s);
+  // G = e . x (bilinear, Eq. 7), statistics and solutions of the listed slots; frees them
+  auto retire = [&](const std::vector<int> &fin) -> int {
     alist.clear();
-    for (int v = 0; v < B; ++v)
+    for (int v : fin)
       if (!hconv[v] && hbnorm[v] > 0) alist.push_back(v);
-    if (!alist.empty()) {
+    if (!alist.empty()) {  // final true residual of right-hand sides that spent their budget
       std::vector<int> cand = alist;
-      if (int rc = true_residual(B)) {
-        wfree(W);
-        return rc;
-      }
+      if (int rc = true_residual(B)) return rc;
       for (int v : cand) hrn[v] = std::sqrt(std::max(hh[(size_t)v * ldp].x, 0.0));
     }
-    // G = e . x (bilinear, Eq. 7)
+    std::vector<int> msk(B, 0);
+    for (int v : fin) msk[v] = 1;
+    hipMemcpyAsync(fmask, msk.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
     hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Evecs, eoff, 0LL, 1, X, n, n1, 0,
-                       (const int *)nullptr, partial, nchunk, ldp);
-    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, 1, (const int *)nullptr, htmp, ldp,
-                       (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr);
+                       (const int *)fmask, partial, nchunk, ldp, (const int *)nullptr);
+    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, 1, (const int *)fmask, htmp,
+                       ldp, (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
     hipMemcpyAsync(hh.data(), htmp, sizeof(cplx) * B * ldp, hipMemcpyDeviceToHost, s);
-    if (int rc2 = sync("G assembly")) {
-      wfree(W);
-      return rc2;
-    }
-    if (Xout)  // solutions of this chunk, for the reduced model
-      hipMemcpyAsync(Xout + (size_t)r0 * n, X, sizeof(cplx) * (size_t)B * n, hipMemcpyDeviceToDevice, s);
-    for (int v = 0; v < B; ++v) {
-      Gout[r0 + v] = hh[(size_t)v * ldp];
+    if (Xout)  // solutions, for the reduced model
+      for (int v : fin)
+        hipMemcpyAsync(Xout + (size_t)rhs_of[v] * n, X + (size_t)v * n, sizeof(cplx) * n, hipMemcpyDeviceToDevice, s);
+    if (int rc2 = sync("G assembly")) return rc2;
+    for (int v : fin) {
+      Gout[rhs_of[v]] = hh[(size_t)v * ldp];
       double rel = hbnorm[v] > 0 ? hrn[v] / hbnorm[v] : 0.0;
       bool ok = hbnorm[v] == 0.0 || rel <= tol;
       if (st) {
@@ -818,7 +694,258 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
         if (!ok) st->n_unconverged += 1;
       }
       if (!ok) status = CCGF_ENOCONV;
+      rhs_of[v] = -1;
     }
+    return CCGF_OK;
+  };
+  // start the listed (just assigned) slots from x0 = 0, r0 = b
+  auto load = [&](const std::vector<int> &fresh) -> int {
+    std::vector<int> msk(B, 0);
+    for (int v : fresh) {
+      const int r = rhs_of[v];
+      msk[v] = 1;
+      hshift[v] = mkc(rhs_omega[r], sE * eta);
+      hpshift[v] = mkc(rhs_omega[r], sE * peta);
+      heoff[v] = (long long)rhs_orb[r] * n;
+      hipMemcpyAsync(Bv + (size_t)v * n, Bvecs + (size_t)rhs_orb[r] * n, sizeof(cplx) * n, hipMemcpyDeviceToDevice,
+                     s);
+      hipMemsetAsync(X + (size_t)v * n, 0, sizeof(cplx) * n, s);
+      hipMemcpyAsync(R + (size_t)v * n, Bvecs + (size_t)rhs_orb[r] * n, sizeof(cplx) * n, hipMemcpyDeviceToDevice,
+                     s);
+    }
+    hipMemcpyAsync(shift, hshift.data(), sizeof(cplx) * B, hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(pshift, hpshift.data(), sizeof(cplx) * B, hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(eoff, heoff.data(), sizeof(long long) * B, hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(fmask, msk.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
+    hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Bv, uoff, 0LL, 1, Bv, n, n1, 1, (const int *)fmask,
+                       partial, nchunk, ldp, (const int *)nullptr);
+    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, 1, (const int *)fmask, htmp,
+                       ldp, (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
+    hipMemcpyAsync(hh.data(), htmp, sizeof(cplx) * B * ldp, hipMemcpyDeviceToHost, s);
+    if (int rc = sync("solver start")) return rc;
+    for (int v : fresh) {
+      hbnorm[v] = std::sqrt(std::max(hh[(size_t)v * ldp].x, 0.0));
+      hrn[v] = hbnorm[v];
+      hthr[v] = tol * hbnorm[v];
+      hconv[v] = hbnorm[v] == 0.0;
+      its[v] = 0;
+    }
+    hipMemcpyAsync(thresh, hthr.data(), sizeof(double) * B, hipMemcpyHostToDevice, s);
+    return CCGF_OK;
+  };
+
+  // Each slot runs its own restart cycles: one Arnoldi step per loop pass for
+  // every slot inside a cycle (per-slot column hj), the cycle end (correction,
+  // residual, convergence) as soon as the slot's Givens step stops it, then a
+  // new cycle, or retirement and refill.  With recycling the cycles of the
+  // whole batch are kept in step instead (the recycled pairs are shared).
+  std::vector<int> hj(B, 0), incyc(B, 0), smask(B, 0);
+  int cyc = 0;  // synchronised cycles (recycling)
+  while (true) {
+    {  // retire finished slots, refill free ones
+      std::vector<int> fin, fresh;
+      bool busy = false;
+      for (int v = 0; v < B; ++v)
+        if (rhs_of[v] >= 0) {
+          if (!incyc[v] && (hconv[v] || its[v] >= maxit)) fin.push_back(v);
+          else busy = true;
+        }
+      if (!refill_each && busy) fin.clear();
+      if (!fin.empty())
+        if (int rc = retire(fin)) {
+          wfree(W);
+          return rc;
+        }
+      bool empty = true;
+      for (int v = 0; v < B; ++v) empty = empty && rhs_of[v] < 0;
+      if (refill_each || empty)
+        for (int v = 0; v < B && next < nrhs; ++v)
+          if (rhs_of[v] < 0) {
+            rhs_of[v] = next++;
+            fresh.push_back(v);
+          }
+      if (!fresh.empty()) {
+        if (int rc = load(fresh)) {
+          wfree(W);
+          return rc;
+        }
+        if (!refill_each) cyc = 0;
+      }
+    }
+    {  // start cycles
+      bool anyin = false;
+      for (int v = 0; v < B; ++v) anyin = anyin || incyc[v];
+      int nstart = 0, occupied = 0;
+      for (int v = 0; v < B; ++v) {
+        occupied += rhs_of[v] >= 0;
+        smask[v] = rhs_of[v] >= 0 && !incyc[v] && !hconv[v] && its[v] < maxit && (refill_each || !anyin);
+        if (smask[v]) {
+          ++nstart;
+          incyc[v] = 1;
+          hj[v] = 0;
+          hjlim[v] = std::min(m, std::max(0, maxit - its[v]));  // iteration budget of this cycle
+          hinv[v] = hrn[v] > 0 ? 1.0 / hrn[v] : 0.0;
+        }
+      }
+      if (nstart > 0) {  // (host arrays stay untouched until the step's synchronisation)
+        hipMemcpyAsync(fmask, smask.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
+        hipMemcpyAsync(jlim, hjlim.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
+        hipMemcpyAsync(inv, hinv.data(), sizeof(double) * B, hipMemcpyHostToDevice, s);
+        hipMemcpyAsync(w0n, hrn.data(), sizeof(double) * B, hipMemcpyHostToDevice, s);
+        hipLaunchKernelGGL(k_scale, dim3(gx, B), dim3(256), 0, s, V, R, inv, n, fmask);  // V_0 = r / ||r||
+        hipLaunchKernelGGL(k_cycle_start, dim3(B), dim3(256), 0, s, m, kslots, fmask, w0n, H, H0, Bm, g, kused);
+      }
+      bool anyc = false;
+      for (int v = 0; v < B; ++v) anyc = anyc || incyc[v];
+      if (!anyc) {
+        if (occupied == 0 && next >= nrhs) break;
+        continue;  // occupied slots are all finished: retire them first
+      }
+    }
+    const int kc = refill_each ? 0 : std::min(cyc, kr);  // recycled pairs in use
+    const int rslot = kr > 0 ? cyc % kr : 0;
+    // one Arnoldi step for every slot inside a cycle
+    alist.clear();
+    for (int v = 0; v < B; ++v) {
+      hact[v] = incyc[v];
+      if (hact[v]) alist.push_back(v);
+    }
+    const int na = (int)alist.size();
+    hipMemcpyAsync(active, hact.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(jvd, hj.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(aidx, alist.data(), sizeof(int) * na, hipMemcpyHostToDevice, s);
+    hipLaunchKernelGGL(k_gather_precond, dim3(gx, na), dim3(256), 0, s, Z, V, diag, pshift, sM, n, aidx, 1, jvd,
+                       (long long)svi);
+    int rc = sigma_apply(c, part, K, na, Z, Wc, c->opt.precision);
+    if (rc != CCGF_OK) {
+      wfree(W);
+      return rc;
+    }
+    if (st) st->n_sigma += na;
+    hipLaunchKernelGGL(k_scatter_shift, dim3(gx, na), dim3(256), 0, s, Wv, Z, Wc, shift, sM, n, aidx);
+    // ||w||^2 before projection (for the reorthogonalisation test)
+    hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Wv, uoff, 0LL, 1, Wv, n, n1, 1, active, partial,
+                       nchunk, ldp, (const int *)nullptr);
+    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, 1, active, htmp, ldp,
+                       (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
+    hipLaunchKernelGGL(k_take_norm, dim3((B + 63) / 64), dim3(64), 0, s, B, htmp, ldp, w0n, active);
+    // classical Gram-Schmidt against the recycled C and V_0..V_j, a second pass where the first
+    // removed most of w
+    for (int pass = 0; pass < 2; ++pass) {
+      const int *mask = pass == 0 ? active : need;
+      if (kc > 0) {
+        hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Cb, uoff, (long long)svi, kc, Wv, n, n1, 1,
+                           mask, partial, nchunk, ldp, (const int *)nullptr);
+        hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, kc, mask, htmp, ldp, Bm, m,
+                           (long long)kslots * m, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)jvd);
+        hipLaunchKernelGGL(k_sub_proj, dim3(gx, B), dim3(256), 0, s, Wv, Cb, (long long)svi, n, kc, htmp, ldp, mask,
+                           (const int *)nullptr);
+      }
+      hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, V, uoff, (long long)svi, 1, Wv, n, n1, 1, mask,
+                         partial, nchunk, ldp, (const int *)jvd);
+      hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, 1, mask, htmp, ldp, H, m,
+                         (long long)(m + 1) * m, 0, H0, (const int *)jvd, (const int *)jvd);
+      hipLaunchKernelGGL(k_sub_proj, dim3(gx, B), dim3(256), 0, s, Wv, V, (long long)svi, n, 1, htmp, ldp, mask,
+                         (const int *)jvd);
+      hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Wv, uoff, 0LL, 1, Wv, n, n1, 1, mask, partial,
+                         nchunk, ldp, (const int *)nullptr);
+      hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, 1, mask, htmp, ldp,
+                         (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
+      if (pass == 0)
+        hipLaunchKernelGGL(k_need_reorth, dim3((B + 63) / 64), dim3(64), 0, s, B, htmp, ldp, w0n, active, need,
+                           ratio2);
+    }
+    hipLaunchKernelGGL(k_givens, dim3((B + 63) / 64), dim3(64), 0, s, B, m, jvd, H, cs, sn, g, htmp, ldp, inv, active,
+                       kused, thresh, jlim, H0);
+    // V_{j+1} = w / h_{j+1,j} (also for j + 1 = m: the image c = V H y uses it).  k_givens
+    // clears `active` of right-hand sides that finish here, so use this step's list aidx.
+    hipLaunchKernelGGL(k_scale_idx, dim3(gx, na), dim3(256), 0, s, V, Wv, inv, n, aidx, jvd, (long long)svi);
+    hipMemcpyAsync(hact.data(), active, sizeof(int) * B, hipMemcpyDeviceToHost, s);
+    hipMemcpyAsync(hneed.data(), need, sizeof(int) * B, hipMemcpyDeviceToHost, s);
+    if (int rc2 = sync("solver iteration")) {
+      wfree(W);
+      return rc2;
+    }
+    if (st) {
+      st->n_steps += 1;
+      for (int v = 0; v < B; ++v) st->n_reorth += hneed[v];
+    }
+    // slots whose cycle ended in this step (all of them together when recycling)
+    std::vector<int> ended;
+    bool still = false;
+    for (int v : alist) {
+      hj[v] += 1;
+      if (!hact[v]) ended.push_back(v);
+      else still = true;
+    }
+    if (!refill_each && still) ended.clear();
+    if (ended.empty()) continue;
+    for (int v = 0; v < B; ++v) hskip[v] = 1;
+    for (int v : ended) hskip[v] = 0;
+    hipMemcpyAsync(skip, hskip.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
+    // minimal-residual correction of the cycle and its image under A
+    hipLaunchKernelGGL(k_backsolve, dim3(B), dim3(256), 0, s, B, m, H, g, kused, ysol, skip);
+    hipLaunchKernelGGL(k_gcrot_small, dim3(B), dim3(256), 0, s, B, m, kc, Bm, H0, ysol, kused, tv, dv, skip, kslots);
+    cplx *us = Ub + (size_t)rslot * svi, *cs_ = Cb + (size_t)rslot * svi;
+    hipLaunchKernelGGL(k_gcrot_combine, dim3(gx, B), dim3(256), 0, s, n, m, (long long)svi, V, ysol, dv, kused, kc, Ub,
+                       tv, kslots, diag, pshift, sM, us, cs_, X, R, skip);
+    if (kr > 0) {  // normalise the new pair so that c has unit norm
+      norms(cs_, B);
+      hipLaunchKernelGGL(k_inv_sqrt, dim3((B + 63) / 64), dim3(64), 0, s, B, htmp, ldp, inv, skip);
+      hipLaunchKernelGGL(k_scale2, dim3(gx, B), dim3(256), 0, s, us, cs_, inv, n, skip);
+    }
+    norms(R, B);
+    hipMemcpyAsync(hh.data(), htmp, sizeof(cplx) * B * ldp, hipMemcpyDeviceToHost, s);
+    hipMemcpyAsync(hkused.data(), kused, sizeof(int) * B, hipMemcpyDeviceToHost, s);
+    if (int rc2 = sync("solver cycle")) {
+      wfree(W);
+      return rc2;
+    }
+    alist.clear();
+    for (int v : ended) {
+      incyc[v] = 0;
+      hrn[v] = std::sqrt(std::max(hh[(size_t)v * ldp].x, 0.0));
+      its[v] += hkused[v];
+      hconv[v] = hrn[v] <= tol * hbnorm[v];
+      // mixed precision: every cycle restarts from the FP64 true residual (iterative refinement)
+      if (hconv[v] || c->opt.precision != CCGF_PLAIN_F64) alist.push_back(v);
+    }
+    // confirm convergence with the true residual (the recursive one can drift)
+    if (!alist.empty()) {
+      std::vector<int> cand = alist;
+      if (int rc3 = true_residual(B)) {
+        wfree(W);
+        return rc3;
+      }
+      std::vector<int> redo(B, 0);
+      int nredo = 0;
+      for (int v : cand) {
+        hrn[v] = std::sqrt(std::max(hh[(size_t)v * ldp].x, 0.0));
+        hconv[v] = hrn[v] <= tol * hbnorm[v];
+        if (!hconv[v]) redo[v] = 1, ++nredo;
+      }
+      const int kcn = refill_each ? 0 : std::min(cyc + 1, kr);
+      if (nredo && kcn > 0) {
+        // restore r _|_ C for the restarted residuals: x += U (C^H r), r -= C (C^H r)
+        hipMemcpyAsync(active, redo.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
+        hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Cb, uoff, (long long)svi, kcn, R, n, n1, 1,
+                           active, partial, nchunk, ldp, (const int *)nullptr);
+        hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, kcn, active, htmp, ldp,
+                           (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
+        hipLaunchKernelGGL(k_add_proj, dim3(gx, B), dim3(256), 0, s, X, Ub, (long long)svi, n, kcn, htmp, ldp, active);
+        hipLaunchKernelGGL(k_sub_proj, dim3(gx, B), dim3(256), 0, s, R, Cb, (long long)svi, n, kcn, htmp, ldp, active,
+                           (const int *)nullptr);
+        norms(R, B);
+        hipMemcpyAsync(hh.data(), htmp, sizeof(cplx) * B * ldp, hipMemcpyDeviceToHost, s);
+        if (int rc2 = sync("residual projection")) {
+          wfree(W);
+          return rc2;
+        }
+        for (int v = 0; v < B; ++v)
+          if (redo[v]) hrn[v] = std::sqrt(std::max(hh[(size_t)v * ldp].x, 0.0));
+      }
+    }
+    if (!refill_each) ++cyc;
   }
   wfree(W);
   return status;
@@ -885,9 +1012,9 @@ int mor_part(ccgf_ctx *c, int part, int K, int norb, const int *orbs, int nexp, 
   };
   auto dots = [&](const cplx *U, const long long *uoff, long long su, int ni, const cplx *Wp, int B, int conjU) {
     hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, U, uoff, su, ni, Wp, n, n1, conjU,
-                       (const int *)nullptr, partial, nchunk, ldp);
+                       (const int *)nullptr, partial, nchunk, ldp, (const int *)nullptr);
     hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, ni, (const int *)nullptr, out,
-                       ldp, (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr);
+                       ldp, (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
   };
   // norms of the solutions (drop threshold)
   for (int v = 0; v < nrhs; ++v) ha[v] = (long long)v * n;

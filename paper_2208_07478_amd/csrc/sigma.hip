@@ -380,57 +380,60 @@ static void build_plans(ccgf_ctx *c, SigmaPlan &P) {
       }
   }
   // 1p / 1h rows of sigma and the three-body intermediate: long contractions over
-  // the whole r2 vector, split over its momentum blocks (one task per block) into
-  // partial sums part[z][row][v] that k_r1_finish adds up.
+  // the whole r2 vector, split over its momentum blocks and the first occupied
+  // index (one task each, enough blocks to fill the chip) into partial sums
+  // part[z][row][v] that k_r1_finish adds up.
   {
     const int nrow = no + nv;
     GemmPlan &u = P.g_red1, &w = P.g_red2;
     if (P.part == CCGF_PART_EA) {
-      const long long b2 = (long long)no * nv * nv;
-      // rows a: 1/2 W_alcd r_l^cd, A = Wvovv[K][kl][kc](a,l,c,d)
+      const long long b2 = (long long)no * nv * nv, kl2 = (long long)nv * nv;
+      // rows a: 1/2 W_alcd r_l^cd, A = Wvovv[K][kl][kc](a,l,c,d), chunk l
       u.shape.M = nv;
-      u.shape.K = (int)b2;
+      u.shape.K = (int)kl2;
       u.shape.am = one(b2);
       u.shape.ak = one(1);
       u.shape.alpha_re = 0.5;
-      // rows k: <kl||cd> r_l^cd, A = Voovv[K][kl][kc](k,l,c,d)
+      // rows k: <kl||cd> r_l^cd, A = Voovv[K][kl][kc](k,l,c,d), chunk l
       w.shape.M = no;
-      w.shape.K = (int)b2;
+      w.shape.K = (int)kl2;
       w.shape.am = one(b2);
       w.shape.ak = one(1);
       w.shape.alpha_re = 1;
       T4 Wa{nullptr, nk, nv, no, nv, nv}, Va{nullptr, nk, no, no, nv, nv};
       for (int kl = 0; kl < nk; ++kl)
-        for (int kc = 0; kc < nk; ++kc) {
-          const long long z = kl * nk + kc, boff = nv + z * b2;
-          u.tasks.push_back(GemmTask{z * nrow * nvec, (int)u.segs.size(), 1});
-          u.segs.push_back(GemmSeg{(long long)Wa.blk(K, kl, kc), boff});
-          w.tasks.push_back(GemmTask{(z * nrow + nv) * nvec, (int)w.segs.size(), 1});
-          w.segs.push_back(GemmSeg{(long long)Va.blk(K, kl, kc), boff});
-        }
+        for (int kc = 0; kc < nk; ++kc)
+          for (int l = 0; l < no; ++l) {
+            const long long z = ((long long)kl * nk + kc) * no + l, boff = nv + (kl * nk + kc) * b2 + l * kl2;
+            u.tasks.push_back(GemmTask{z * nrow * nvec, (int)u.segs.size(), 1});
+            u.segs.push_back(GemmSeg{(long long)Wa.blk(K, kl, kc) + l * kl2, boff});
+            w.tasks.push_back(GemmTask{(z * nrow + nv) * nvec, (int)w.segs.size(), 1});
+            w.segs.push_back(GemmSeg{(long long)Va.blk(K, kl, kc) + l * kl2, boff});
+          }
     } else {
-      const long long b2 = (long long)no * no * nv;
-      // rows i: -1/2 W_mnie r_mn^e, A = Wooov[km][kn][K](m,n,i,e)
+      const long long b2 = (long long)no * no * nv, km2 = (long long)no * nv;
+      // rows i: -1/2 W_mnie r_mn^e, A = Wooov[km][kn][K](m,n,i,e), chunk m
       u.shape.M = no;
-      u.shape.K = (int)b2;
+      u.shape.K = (int)km2;
       u.shape.am = one(nv);
       u.shape.ak = two(nv, (long long)no * nv, 1);
       u.shape.alpha_re = -0.5;
-      // rows e: <mn||ef> r_mn^f, A = Voovv[km][kn][K](m,n,e,f)
+      // rows e: <mn||ef> r_mn^f, A = Voovv[km][kn][K](m,n,e,f), chunk m
       w.shape.M = nv;
-      w.shape.K = (int)b2;
+      w.shape.K = (int)km2;
       w.shape.am = one(nv);
       w.shape.ak = two(nv, (long long)nv * nv, 1);
       w.shape.alpha_re = 1;
       T4 Wa{nullptr, nk, no, no, no, nv}, Va{nullptr, nk, no, no, nv, nv};
       for (int km = 0; km < nk; ++km)
-        for (int kn = 0; kn < nk; ++kn) {
-          const long long z = km * nk + kn, boff = no + z * b2;
-          u.tasks.push_back(GemmTask{z * nrow * nvec, (int)u.segs.size(), 1});
-          u.segs.push_back(GemmSeg{(long long)Wa.blk(km, kn, K), boff});
-          w.tasks.push_back(GemmTask{(z * nrow + no) * nvec, (int)w.segs.size(), 1});
-          w.segs.push_back(GemmSeg{(long long)Va.blk(km, kn, K), boff});
-        }
+        for (int kn = 0; kn < nk; ++kn)
+          for (int mm = 0; mm < no; ++mm) {
+            const long long z = ((long long)km * nk + kn) * no + mm, boff = no + (km * nk + kn) * b2 + mm * km2;
+            u.tasks.push_back(GemmTask{z * nrow * nvec, (int)u.segs.size(), 1});
+            u.segs.push_back(GemmSeg{(long long)Wa.blk(km, kn, K) + mm * (long long)no * no * nv, boff});
+            w.tasks.push_back(GemmTask{(z * nrow + no) * nvec, (int)w.segs.size(), 1});
+            w.segs.push_back(GemmSeg{(long long)Va.blk(km, kn, K) + mm * (long long)no * nv * nv, boff});
+          }
     }
     for (GemmPlan *g : {&u, &w}) {
       g->shape.N = nvec;
@@ -637,7 +640,7 @@ int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y, 
     if (!c->sig_r1aux) return CCGF_ENOMEM;
   }
   {
-    const size_t need_part = (size_t)c->nk * c->nk * (size_t)(c->no + c->nv) * nvec;
+    const size_t need_part = (size_t)c->nk * c->nk * c->no * (size_t)(c->no + c->nv) * nvec;
     if (c->sig_part_elems < need_part) {
       if (c->sig_part) {
         for (auto &q : c->allocs)
@@ -682,54 +685,83 @@ int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y, 
   hipStream_t s = c->stream;
   const unsigned gy = (unsigned)std::min(nvec, 65535);
   const bool timing = c->opt.timing != 0;
-  if (timing && !c->ev[0])
-    for (int q = 0; q < 4; ++q) hipEventCreate(&c->ev[q]);
-  if (timing) hipEventRecord(c->ev[0], s);
+  ccgf_ctx::TimedSigma *ts = nullptr;
+  if (timing) {
+    if (c->tring.empty()) {
+      c->tring.resize(64);
+      for (auto &r : c->tring)
+        for (int q = 0; q < 4; ++q)
+          if (hipEventCreate(&r.e[q]) != hipSuccess) return hip_check(c, hipGetLastError(), "timing events");
+    }
+    // earlier products have completed by now wherever the solver or the caller
+    // synchronised the stream; the wait below only bites for back-to-back calls
+    timing_harvest(c);
+    ts = &c->tring[c->tnext];
+    c->tnext = (c->tnext + 1) % (int)c->tring.size();
+    ts->big = part == CCGF_PART_EA;
+    ts->flops = part == CCGF_PART_EA ? plan_flops(P->g_big) : 0.0;
+    hipEventRecord(ts->e[0], s);
+  }
   if (part == CCGF_PART_EA) {
-    if (timing) hipEventRecord(c->ev[2], s);
+    if (timing) hipEventRecord(ts->e[2], s);
     if (prec && !c->Wvvvv32) return set_err(c, CCGF_ESTATE, "mixed-precision operands were not built");
     gemm_launch(0, P->g_big, prec ? (const void *)c->Wvvvv32 : (const void *)c->Wvvvv, x, y, s, prec);
-    if (timing) hipEventRecord(c->ev[3], s);
+    if (timing) hipEventRecord(ts->e[3], s);
     gemm_launch(1, P->g_ovvo, prec ? (const void *)c->WvoP32 : (const void *)c->WvoP, x, c->sig_tmp, s, prec);
     gemm_launch(4, P->g_r1, c->Wvvvo, x, y, s, 0);
     gemm_launch(6, P->g_red1, c->Wvovv, x, c->sig_part, s, 0);
     gemm_launch(6, P->g_red2, c->Voovv, x, c->sig_part, s, 0);
     hipLaunchKernelGGL(k_r1_finish, dim3((unsigned)(((nv + no) * nvec + 3) / 4)), dim3(256), 0, s, 1, nk, no, nv, K,
-                       nv + no, nv, nvec, nk * nk, n, c->sig_part, x, y, c->sig_r1aux, std::max(no, nv), c->Foo,
+                       nv + no, nv, nvec, nk * nk * no, n, c->sig_part, x, y, c->sig_r1aux, std::max(no, nv), c->Foo,
                        c->Fvv, c->Fov);
     long long tot = (long long)nk * nk * no * nv * nv;
     hipLaunchKernelGGL(k_ea_local, dim3((unsigned)((tot + 255) / 256), gy), dim3(256), 0, s, nk, no, nv, K, nvec, n,
                        c->kc3, x, y, c->sig_tmp, c->sig_r1aux, c->Foo, c->Fvv, c->t2);
   } else {
-    if (timing) hipEventRecord(c->ev[2], s);
+    if (timing) hipEventRecord(ts->e[2], s);
     if (prec && !c->WooP32) return set_err(c, CCGF_ESTATE, "mixed-precision operands were not built");
     gemm_launch(2, P->g_big, prec ? (const void *)c->WooP32 : (const void *)c->WooP, x, y, s, prec);
-    if (timing) hipEventRecord(c->ev[3], s);
+    if (timing) hipEventRecord(ts->e[3], s);
     gemm_launch(3, P->g_ovvo, prec ? (const void *)c->WvoP32 : (const void *)c->WvoP, x, c->sig_tmp, s, prec);
     gemm_launch(5, P->g_r1, c->Wovoo, x, y, s, 0);
     gemm_launch(7, P->g_red1, c->Wooov, x, c->sig_part, s, 0);
     gemm_launch(7, P->g_red2, c->Voovv, x, c->sig_part, s, 0);
     hipLaunchKernelGGL(k_r1_finish, dim3((unsigned)(((nv + no) * nvec + 3) / 4)), dim3(256), 0, s, 0, nk, no, nv, K,
-                       no + nv, no, nvec, nk * nk, n, c->sig_part, x, y, c->sig_r1aux, std::max(no, nv), c->Foo,
+                       no + nv, no, nvec, nk * nk * no, n, c->sig_part, x, y, c->sig_r1aux, std::max(no, nv), c->Foo,
                        c->Fvv, c->Fov);
     long long tot = (long long)nk * nk * no * no * nv;
     hipLaunchKernelGGL(k_ip_local, dim3((unsigned)((tot + 255) / 256), gy), dim3(256), 0, s, nk, no, nv, K, nvec, n,
                        c->kc3, x, y, c->sig_tmp, c->sig_r1aux, c->Foo, c->Fvv, c->t2);
   }
   if (timing) {
-    hipEventRecord(c->ev[1], s);
-    if (hipEventSynchronize(c->ev[1]) == hipSuccess) {
-      float a = 0, b = 0;
-      hipEventElapsedTime(&a, c->ev[2], c->ev[3]);
-      hipEventElapsedTime(&b, c->ev[0], c->ev[1]);
-      if (part == CCGF_PART_EA) {
-        c->t_big_ms += a;
-        c->t_big_launches += 1;
-        c->t_big_flops += plan_flops(P->g_big);
-      }
-      c->t_sigma_ms += b;
-      c->t_sigma_launches += 1;
-    }
+    hipEventRecord(ts->e[1], s);
+    ts->pending = true;
   }
   return hip_check(c, hipGetLastError(), "sigma launch");
+}
+
+void timing_harvest(ccgf_ctx *c) {
+  for (auto &r : c->tring) {
+    if (!r.pending) continue;
+    float a = 0, b = 0;
+    if (hipEventSynchronize(r.e[1]) == hipSuccess) {
+      hipEventElapsedTime(&b, r.e[0], r.e[1]);
+      c->t_sigma_ms += b;
+      c->t_sigma_launches += 1;
+      if (r.big) {
+        hipEventElapsedTime(&a, r.e[2], r.e[3]);
+        c->t_big_ms += a;
+        c->t_big_launches += 1;
+        c->t_big_flops += r.flops;
+      }
+    }
+    r.pending = false;
+  }
+}
+
+void timing_release(ccgf_ctx *c) {
+  for (auto &r : c->tring)
+    for (int q = 0; q < 4; ++q)
+      if (r.e[q]) hipEventDestroy(r.e[q]);
+  c->tring.clear();
 }

@@ -121,6 +121,8 @@ typedef struct {
   long long sigma_launches;  /* sigma products (each over a batch of vectors) */
   long long n_steps;         /* batched Arnoldi steps (one sigma product over the active batch each) */
   long long n_reorth;        /* right-hand-side steps that needed the second Gram-Schmidt pass */
+  long long n_guess;         /* solves started from the trained network's guess */
+  long long n_guess_rejected; /* guesses discarded because ||b - A x0|| >= ||b|| (started from 0) */
 } ccgf_stats;
 
 /* Validates the system (shapes, t2 antisymmetry, factor Hermiticity, each to
@@ -140,6 +142,65 @@ int cc_gf_init(const ccgf_system *sys, const ccgf_options *opt, ccgf_ctx **out);
 int cc_gf_solve(ccgf_ctx *ctx, int nkq, const int *kidx, int norb, const int *orbs,
                 int nw, const double *omega, double eta, int parts,
                 double *G, double *Gplus_opt, double *Gminus_opt, ccgf_stats *st_opt);
+
+/* Learned initial guess (a network trained on the solver's own solutions).
+ * Not part of the paper's method: a companion to it that changes only where
+ * GMRES starts, never what it converges to. */
+typedef struct {
+  int epochs;              /* passes over the training pairs; 0 -> 300 */
+  int batch;               /* pairs per Adam step; 0 -> 256 */
+  double lr;               /* Adam step size; 0 -> 1e-3 */
+  unsigned long long seed; /* parameter initialisation and shuffling */
+  int hidden;              /* width of the two tanh hidden layers; 0 -> 256 */
+  int guess;               /* CCGF_GUESS_NETWORK (0): x0 from the network;
+                              CCGF_GUESS_NEAREST: x0 = the training solution at the
+                              nearest training frequency (no network; for comparison) */
+  double accept;           /* a guess is used only if ||b - A x0|| < accept * ||b||, in (0, 1];
+                              0 -> 0.1 (a guess that leaves most of b tends to slow GMRES:
+                              its residual is rich in the near-resonant directions) */
+} ccgf_learn_options;
+enum { CCGF_GUESS_NETWORK = 0, CCGF_GUESS_NEAREST = 1 };
+
+typedef struct {
+  long long pairs;          /* training pairs */
+  int rank;                 /* reduced-basis size per orbital (training frequencies) */
+  double loss_initial;      /* mean squared error / 2 over all pairs before and after training */
+  double loss_final;
+  double solve_seconds;     /* plain solves that produced the training solutions */
+  double train_seconds;     /* network training on the GPU */
+  long long solve_iterations;
+} ccgf_learn_stats;
+
+/* Train the initial-guess network of momentum K and the given parts
+ * (CCGF_PART_*).  The plain solver (the context's options) solves the shifted
+ * systems of Eq. 6 for every (orbs[b], omega_train[j]); per orbital, the
+ * solutions are orthonormalised (Gram-Schmidt twice, dependent columns zeroed)
+ * into a basis Q_p of rank ntrain, and c_j = Q_p^H x_j are their reduced
+ * coordinates.  A three-layer perceptron (two tanh hidden layers, FP32,
+ * trained by Adam on the GPU; zero output layer at the start) learns the move
+ *   (w, (w - w_ref)/step, Fock diagonal of p, occupied flag, c_ref) -> c(w) - c_ref
+ * from the pairs (j, j_ref) with |j - j_ref| <= 2.  Afterwards cc_gf_solve
+ * starts each (K, p, w) solve of a trained orbital from x0 = Q_p c_hat,
+ * c_hat = c_ref + network output, with c_ref taken at the training frequency
+ * nearest to w; a guess whose residual is not below accept * ||b|| is
+ * discarded and the solve starts from zero.  The model
+ * replaces any earlier one of the same (part, K).  ntrain in 1..32, sorted
+ * ascending, finite.  opt and st may be NULL.  Device memory: ntrain * norb
+ * vectors per part are kept for the basis. */
+int cc_gf_learn(ccgf_ctx *ctx, int parts, int K, int norb, const int *orbs, int ntrain,
+                const double *omega_train, double eta, const ccgf_learn_options *opt_opt,
+                ccgf_learn_stats *st_opt);
+
+/* Use (on != 0, the default) or ignore the trained networks in cc_gf_solve. */
+int cc_gf_learn_enable(ccgf_ctx *ctx, int on);
+
+/* Least-squares loss and its gradient for the network above, for checking the
+ * training kernels: theta, X [N][din], T [N][dout], grad [nparams] are HOST
+ * FP32 arrays (parameter order W1 [hidden][din], b1, W2 [hidden][hidden], b2,
+ * W3 [dout][hidden], b3); *loss_opt = |Y - T|^2 / (2N).  Runs on the current
+ * device; allocates and frees its own device buffers.  Dimensions 1..4096. */
+int cc_gf_mlp_grad(int din, int hidden, int dout, const float *theta, int N, const float *X,
+                   const float *T, float *grad, double *loss_opt);
 
 /* Largest number of expansion frequencies per part accepted by cc_gf_mor. */
 #define CCGF_MOR_MAX 32

@@ -23,7 +23,7 @@ PLAIN_F64, MIXED_F32 = 0, 1
 PRECISIONS = {"f64": PLAIN_F64, "plain_f64": PLAIN_F64, "f32": MIXED_F32, "mixed_f32": MIXED_F32}
 
 EXPORTS = ("cc_gf_init", "cc_gf_solve", "cc_gf_mor", "cc_gf_vector_size", "cc_gf_sigma", "cc_gf_vectors",
-           "cc_gf_free", "cc_gf_last_error")
+           "cc_gf_learn", "cc_gf_learn_enable", "cc_gf_mlp_grad", "cc_gf_free", "cc_gf_last_error")
 MOR_MAX = 32
 
 
@@ -49,7 +49,23 @@ class Stats(ctypes.Structure):
                 ("big_ms", ctypes.c_double), ("big_launches", ctypes.c_longlong),
                 ("big_flops", ctypes.c_double), ("sigma_ms", ctypes.c_double),
                 ("sigma_launches", ctypes.c_longlong), ("n_steps", ctypes.c_longlong),
-                ("n_reorth", ctypes.c_longlong)]
+                ("n_reorth", ctypes.c_longlong), ("n_guess", ctypes.c_longlong),
+                ("n_guess_rejected", ctypes.c_longlong)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class LearnOptions(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_double),
+                ("seed", ctypes.c_ulonglong), ("hidden", ctypes.c_int), ("guess", ctypes.c_int),
+                ("accept", ctypes.c_double)]
+
+
+class LearnStats(ctypes.Structure):
+    _fields_ = [("pairs", ctypes.c_longlong), ("rank", ctypes.c_int), ("loss_initial", ctypes.c_double),
+                ("loss_final", ctypes.c_double), ("solve_seconds", ctypes.c_double),
+                ("train_seconds", ctypes.c_double), ("solve_iterations", ctypes.c_longlong)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -91,6 +107,15 @@ def load(path: str = LIB_PATH):
     lib.cc_gf_sigma.restype = ctypes.c_int
     lib.cc_gf_vectors.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp]
     lib.cc_gf_vectors.restype = ctypes.c_int
+    lib.cc_gf_learn.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, ctypes.c_int, dp, ctypes.c_double,
+                                ctypes.POINTER(LearnOptions), ctypes.POINTER(LearnStats)]
+    lib.cc_gf_learn.restype = ctypes.c_int
+    lib.cc_gf_learn_enable.argtypes = [vp, ctypes.c_int]
+    lib.cc_gf_learn_enable.restype = ctypes.c_int
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.cc_gf_mlp_grad.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, fp, ctypes.c_int, fp, fp, fp,
+                                   ctypes.POINTER(ctypes.c_double)]
+    lib.cc_gf_mlp_grad.restype = ctypes.c_int
     lib.cc_gf_free.argtypes = [vp]
     lib.cc_gf_free.restype = None
     lib.cc_gf_last_error.argtypes = [vp]
@@ -219,6 +244,23 @@ class Context:
         self._check(rc, allow=(ENOCONV,) if allow_noconv else ())
         return G, Gp, Gm, st.as_dict()
 
+    def learn(self, K: int, orbs: Sequence[int], omega_train, eta: float, parts="both", epochs=0, batch=0, lr=0.0,
+              seed=0, hidden=0, guess="network", accept=0.0, allow_noconv=False):
+        """Train the initial-guess network of momentum K on plain solves at omega_train."""
+        orbs = np.ascontiguousarray(np.asarray(orbs, dtype=np.int32))
+        wt = np.ascontiguousarray(np.asarray(omega_train, dtype=np.float64))
+        lo = LearnOptions(int(epochs), int(batch), float(lr), int(seed), int(hidden),
+                          {"network": 0, "nearest": 1}[guess], float(accept))
+        ls = LearnStats()
+        rc = load().cc_gf_learn(self._h, _part(parts), int(K), len(orbs), orbs.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                len(wt), wt.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(eta),
+                                ctypes.byref(lo), ctypes.byref(ls))
+        self._check(rc, allow=(ENOCONV,) if allow_noconv else ())
+        return ls.as_dict()
+
+    def learn_enable(self, on: bool):
+        self._check(load().cc_gf_learn_enable(self._h, 1 if on else 0))
+
     def mor(self, kidx: Sequence[int], orbs: Sequence[int], wexp_ip, wexp_ea, omega, eta: float, parts="both",
             allow_noconv=False):
         """Model-order-reduced G, G+, G-, stats on the grid omega from full solves at the
@@ -241,3 +283,17 @@ class Context:
                               Gp.ctypes.data, Gm.ctypes.data, ctypes.byref(st))
         self._check(rc, allow=(ENOCONV,) if allow_noconv else ())
         return G, Gp, Gm, st.as_dict()
+
+
+def mlp_grad(din: int, hidden: int, dout: int, theta, X, T):
+    """(loss, gradient) of the initial-guess network on the GPU (FP32)."""
+    f32 = lambda a: np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    theta, X, T = f32(theta), f32(X), f32(T)
+    g = np.zeros_like(theta)
+    L = ctypes.c_double()
+    fp = ctypes.POINTER(ctypes.c_float)
+    rc = load().cc_gf_mlp_grad(int(din), int(hidden), int(dout), theta.ctypes.data_as(fp), int(X.shape[0]),
+                               X.ctypes.data_as(fp), T.ctypes.data_as(fp), g.ctypes.data_as(fp), ctypes.byref(L))
+    if rc != OK:
+        raise CCGFError(rc, "cc_gf_mlp_grad failed")
+    return L.value, g

@@ -275,7 +275,17 @@ extern "C" int cc_gf_solve(ccgf_ctx *c, int nkq, const int *kidx, int norb, cons
         if (rc != CCGF_OK) status = rc;
       }
       if (status != CCGF_OK && status != CCGF_ENOCONV) break;
-      int rc = solve_batched(c, part, K, nrhs, rhs_orb.data(), rhs_w.data(), eta, Bv, Ev, res.data(), S);
+      Guess gs;
+      const Guess *gp = nullptr;
+      cplx *chat = nullptr;
+      if (c->learn_on)
+        for (const LearnModel &M : c->models)
+          if (M.part == part && M.K == K) {
+            if (learn_guess(c, M, nrhs, rhs_orb.data(), orbs, rhs_w.data(), gs, &chat)) gp = &gs;
+            break;
+          }
+      int rc = solve_batched(c, part, K, nrhs, rhs_orb.data(), rhs_w.data(), eta, Bv, Ev, res.data(), S, nullptr, gp);
+      if (chat) hipFree(chat);
       if (rc != CCGF_OK) {
         if (rc == CCGF_ENOCONV) set_err(c, rc, "some shifted systems did not reach tol");
         status = (status == CCGF_OK || rc != CCGF_ENOCONV) ? rc : status;
@@ -374,9 +384,60 @@ extern "C" int cc_gf_mor(ccgf_ctx *c, int nkq, const int *kidx, int norb, const 
   return status;
 }
 
+extern "C" int cc_gf_learn(ccgf_ctx *c, int parts, int K, int norb, const int *orbs, int ntrain, const double *wtr,
+                           double eta, const ccgf_learn_options *opt, ccgf_learn_stats *st) {
+  if (!c) return CCGF_ESTATE;
+  if (parts < 1 || parts > 3) return set_err(c, CCGF_EINVAL, "parts must be CCGF_PART_IP, _EA or _BOTH");
+  if (K < 0 || K >= c->nk) return set_err(c, CCGF_EINVAL, "K out of range");
+  if (norb < 1 || !orbs) return set_err(c, CCGF_EINVAL, "no orbitals");
+  for (int b = 0; b < norb; ++b)
+    if (orbs[b] < 0 || orbs[b] >= c->nmo) return set_err(c, CCGF_EINVAL, "orbital index out of range");
+  if (ntrain < 1 || ntrain > 32 || !wtr) return set_err(c, CCGF_EINVAL, "ntrain must be in 1..32");
+  for (int j = 0; j < ntrain; ++j)
+    if (!std::isfinite(wtr[j]) || (j > 0 && !(wtr[j] > wtr[j - 1])))
+      return set_err(c, CCGF_EINVAL, "training frequencies must be finite and strictly ascending");
+  if (!(eta > 0)) return set_err(c, CCGF_EINVAL, "eta must be > 0");
+  ccgf_learn_options lo{};
+  if (opt) lo = *opt;
+  if (lo.epochs == 0) lo.epochs = 300;
+  if (lo.batch == 0) lo.batch = 256;
+  if (lo.lr == 0) lo.lr = 1e-3;
+  if (lo.hidden == 0) lo.hidden = 256;
+  if (lo.accept == 0) lo.accept = 0.1;
+  if (lo.epochs < 0 || lo.batch < 1 || !(lo.lr > 0) || lo.hidden < 1 || lo.hidden > 4096 ||
+      (lo.guess != CCGF_GUESS_NETWORK && lo.guess != CCGF_GUESS_NEAREST) || !(lo.accept > 0) || lo.accept > 1)
+    return set_err(c, CCGF_EINVAL, "learning options out of range");
+  ccgf_learn_stats local{};
+  ccgf_learn_stats *S = st ? st : &local;
+  std::memset(S, 0, sizeof(*S));
+  int status = CCGF_OK;
+  for (int part : {CCGF_PART_IP, CCGF_PART_EA}) {
+    if (!(parts & part)) continue;
+    int rc = learn_part(c, part, K, norb, orbs, ntrain, wtr, eta, lo, S);
+    if (rc == CCGF_ENOCONV) {
+      set_err(c, rc, "some training solves did not reach tol");
+      status = rc;
+    } else if (rc != CCGF_OK) {
+      return rc;
+    }
+  }
+  return status;
+}
+
+extern "C" int cc_gf_learn_enable(ccgf_ctx *c, int on) {
+  if (!c) return CCGF_ESTATE;
+  c->learn_on = on != 0;
+  return CCGF_OK;
+}
+
 extern "C" void cc_gf_free(ccgf_ctx *c) {
   if (!c) return;
   hipStreamSynchronize(c->stream);
+  for (LearnModel &M : c->models) {
+    if (M.Q) hipFree(M.Q);
+    if (M.theta) hipFree(M.theta);
+  }
+  c->models.clear();
   timing_release(c);
   free_all(c);
   delete c;

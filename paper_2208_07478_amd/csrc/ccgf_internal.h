@@ -104,6 +104,48 @@ struct SigmaPlan {  // per (part, K, batch layout)
   bool ready = false;
 };
 
+// Device buffers of the learned-guess network for up to nmax rows.
+struct MlpWork {
+  int din = 0, h = 0, dout = 0, nmax = 0;
+  float *grad = nullptr, *a1 = nullptr, *a2 = nullptr, *y = nullptr, *dy = nullptr, *d1 = nullptr, *d2 = nullptr;
+  double *lpart = nullptr;
+  std::vector<void *> ptrs;
+  bool failed = false;
+};
+long long mlp_nparams(int din, int h, int dout);
+bool mlp_alloc(MlpWork &w, int din, int h, int dout, int nmax);
+void mlp_free(MlpWork &w);
+void mlp_forward(hipStream_t s, MlpWork &w, const float *theta, int N, const float *X);
+int mlp_backward(hipStream_t s, MlpWork &w, const float *theta, int N, const float *X, const float *T);
+void mlp_adam(hipStream_t s, long long np, float *theta, const float *g, float *m, float *v, int t, float lr);
+
+// A trained initial-guess network for one (part, K): the per-orbital reduced
+// basis of the training solutions, their reduced coordinates (the network's
+// "previous solution" inputs) and the FP32 parameters.
+struct LearnModel {
+  int part = 0, K = 0, norb = 0, ntrain = 0, R = 0, din = 0, dout = 0, hidden = 0;
+  int mode = 0;                 // CCGF_GUESS_*
+  double accept = 0.1;          // residual ratio below which a guess is used
+  std::vector<int> orbs;        // orbital ids
+  std::vector<int> occ;         // 1 for occupied orbitals
+  std::vector<double> fpp;      // diagonal Fock element of each orbital at K (real part)
+  std::vector<double> wtrain;   // training frequencies
+  std::vector<double> scale;    // per orbital: 1 / largest |c|
+  std::vector<cplx> C;          // [norb][ntrain][R] reduced coordinates of the training solutions
+  double wscale = 1, wstep = 1;
+  cplx *Q = nullptr;            // device [norb][R][n] orthonormal basis (zero columns allowed)
+  float *theta = nullptr;       // device parameters
+};
+// Initial guesses for solve_batched: x0 of right-hand side r = Q[qidx[r]] chat[r]
+struct Guess {
+  const cplx *Q = nullptr;      // [nq][R][n]
+  const cplx *chat = nullptr;   // device [nrhs][R]
+  std::vector<int> qidx;        // per right-hand side, -1 for none
+  int R = 0;
+  double accept = 1.0;          // keep x0 only if ||b - A x0|| < accept ||b||
+};
+void learn_features(const LearnModel &M, int b, double w, int jr, float *f);
+
 struct ccgf_ctx {
   int m[3];
   int nk, no, nv, nmo, naux;
@@ -131,6 +173,8 @@ struct ccgf_ctx {
   cplx *sig_part = nullptr;  // split-range partial sums of the 1h / 1p rows
   size_t sig_part_elems = 0;
   std::vector<SigmaPlan> plans;
+  std::vector<LearnModel> models;  // trained initial-guess networks
+  int learn_on = 1;                 // use them in cc_gf_solve
   // event timing of the sigma products (options.timing)
   // sigma timing (options.timing): events of recent products, read once they have completed
   struct TimedSigma {
@@ -166,6 +210,13 @@ void plan_upload(ccgf_ctx *c, GemmPlan &p);
 // gmres.hip
 int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb_slot, const double *rhs_omega,
                   double eta, const cplx *Bvecs, const cplx *Evecs, cplx *Gout, ccgf_stats *st,
-                  cplx *Xout = nullptr);
+                  cplx *Xout = nullptr, const Guess *guess = nullptr);
+int learn_part(ccgf_ctx *c, int part, int K, int norb, const int *orbs, int ntrain, const double *wtrain, double eta,
+               const ccgf_learn_options &lo, ccgf_learn_stats *ls);
+// Device reduced coordinates (chat, [nrhs][R]) of the network's guesses for the listed
+// right-hand sides (call orbital index rhs_orb into orbs); fills g.qidx; returns false
+// when no guess applies.
+bool learn_guess(ccgf_ctx *c, const LearnModel &M, int nrhs, const int *rhs_orb, const int *orbs,
+                 const double *rhs_omega, Guess &g, cplx **chat_dev);
 int mor_part(ccgf_ctx *c, int part, int K, int norb, const int *orbs, int nexp, const double *wexp, int nw,
              const double *omega, double eta, cplx *Gout, ccgf_stats *st);

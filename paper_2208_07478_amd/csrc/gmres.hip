@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <random>
 
 #define DOT_ITEMS 8
 #define DOT_CHUNK (256 * DOT_ITEMS)
@@ -452,6 +453,18 @@ __global__ void k_copy_vecs(cplx *__restrict__ dst, const long long *__restrict_
   dst[doff[v] + x] = src[soff[v] + x];
 }
 
+// X[idx[y]] = sum_i Q[qoff[y] + i n] * ch[coff[y] + i]  (guess x0 = Q c_hat)
+__global__ void k_expand(cplx *__restrict__ X, const cplx *__restrict__ Q, const long long *__restrict__ qoff,
+                         const cplx *__restrict__ ch, const long long *__restrict__ coff, int R, long long n,
+                         const int *__restrict__ idx) {
+  const int y = blockIdx.y, v = idx[y];
+  long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  cplx acc = mkc(0, 0);
+  for (int i = 0; i < R; ++i) cfma(acc, ch[coff[y] + i], Q[qoff[y] + (long long)i * n + x]);
+  X[(size_t)v * n + x] = acc;
+}
+
 // W[v] -= sum_i h[v][i] * U_i[v],  U_i[v] = U + uoff[v] + i * n
 __global__ __launch_bounds__(256) void k_sub_proj_off(cplx *__restrict__ W, const cplx *__restrict__ U,
                                                       const long long *__restrict__ uoff, long long n, int ni,
@@ -546,7 +559,7 @@ static void wfree(GmresWork &W) {
 }
 
 int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, const double *rhs_omega, double eta,
-                  const cplx *Bvecs, const cplx *Evecs, cplx *Gout, ccgf_stats *st, cplx *Xout) {
+                  const cplx *Bvecs, const cplx *Evecs, cplx *Gout, ccgf_stats *st, cplx *Xout, const Guess *guess) {
   const long long n = vec_len(c, part);
   const int n1 = part == CCGF_PART_IP ? c->no : c->nv;
   const double sM = part == CCGF_PART_IP ? 1.0 : -1.0;
@@ -594,6 +607,7 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
   int *need = (int *)walloc(W, sizeof(int) * Bmax);
   int *fmask = (int *)walloc(W, sizeof(int) * Bmax);
   int *jvd = (int *)walloc(W, sizeof(int) * Bmax);
+  long long *goff = (long long *)walloc(W, sizeof(long long) * 2 * Bmax);
   double *w0n = (double *)walloc(W, sizeof(double) * Bmax);
   long long *uoff = (long long *)walloc(W, sizeof(long long) * Bmax);
   long long *eoff = (long long *)walloc(W, sizeof(long long) * Bmax);
@@ -731,6 +745,38 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
       its[v] = 0;
     }
     hipMemcpyAsync(thresh, hthr.data(), sizeof(double) * B, hipMemcpyHostToDevice, s);
+    if (guess) {  // start from the network's guess where its residual is below ||b||
+      std::vector<int> gl;
+      std::vector<long long> go(2 * B);
+      for (int v : fresh) {
+        const int q = guess->qidx[rhs_of[v]];
+        if (q < 0 || hbnorm[v] == 0.0) continue;
+        go[gl.size()] = (long long)q * guess->R * n;
+        go[B + gl.size()] = (long long)rhs_of[v] * guess->R;
+        gl.push_back(v);
+      }
+      if (!gl.empty()) {
+        const int ng = (int)gl.size();
+        hipMemcpyAsync(goff, go.data(), sizeof(long long) * 2 * B, hipMemcpyHostToDevice, s);
+        hipMemcpyAsync(aidx, gl.data(), sizeof(int) * ng, hipMemcpyHostToDevice, s);
+        hipLaunchKernelGGL(k_expand, dim3(gx, ng), dim3(256), 0, s, X, guess->Q, goff, guess->chat, goff + B,
+                           guess->R, n, aidx);
+        alist = gl;
+        if (int rc = true_residual(B)) return rc;
+        for (int v : gl) {
+          const double rn = std::sqrt(std::max(hh[(size_t)v * ldp].x, 0.0));
+          if (rn < guess->accept * hbnorm[v]) {
+            hrn[v] = rn;
+            hconv[v] = rn <= hthr[v];
+            if (st) st->n_guess += 1;
+          } else {  // discard: x0 = 0, r0 = b
+            hipMemsetAsync(X + (size_t)v * n, 0, sizeof(cplx) * n, s);
+            hipMemcpyAsync(R + (size_t)v * n, Bv + (size_t)v * n, sizeof(cplx) * n, hipMemcpyDeviceToDevice, s);
+            if (st) st->n_guess_rejected += 1;
+          }
+        }
+      }
+    }
     return CCGF_OK;
   };
 
@@ -951,6 +997,78 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
   return status;
 }
 
+// Orthonormal basis of every group of ncol columns of S ([ngroup][ncol][n]), in
+// place: Gram-Schmidt applied twice in the unique-pair inner product; a column
+// whose remainder falls below 1e-10 of its group's largest column is set to zero.
+static int group_basis(ccgf_ctx *c, long long n, int n1, int ngroup, int ncol, cplx *S) {
+  const int nrhs = ngroup * ncol;
+  const int nchunk = (int)((n + DOT_CHUNK - 1) / DOT_CHUNK);
+  const int ldp = ncol + 1;
+  hipStream_t s = c->stream;
+  GmresWork W;
+  cplx *Wt = (cplx *)walloc(W, sizeof(cplx) * (size_t)ngroup * n);
+  cplx *partial = (cplx *)walloc(W, sizeof(cplx) * (size_t)nrhs * nchunk * ldp);
+  cplx *out = (cplx *)walloc(W, sizeof(cplx) * (size_t)nrhs * ldp);
+  double *inv = (double *)walloc(W, sizeof(double) * ngroup);
+  long long *off_a = (long long *)walloc(W, sizeof(long long) * nrhs);
+  long long *off_b = (long long *)walloc(W, sizeof(long long) * ngroup);
+  long long *off_c = (long long *)walloc(W, sizeof(long long) * ngroup);
+  if (W.failed) {
+    wfree(W);
+    return set_err(c, CCGF_ENOMEM, "basis workspace allocation failed");
+  }
+  const unsigned gx = (unsigned)((n + 255) / 256);
+  std::vector<long long> ha(nrhs), hb(ngroup), hc(ngroup);
+  std::vector<cplx> hh((size_t)nrhs * ldp);
+  auto dots = [&](const cplx *U, const long long *uoff, long long su, int ni, const cplx *Wp, int B) {
+    hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, U, uoff, su, ni, Wp, n, n1, 1, (const int *)nullptr,
+                       partial, nchunk, ldp, (const int *)nullptr);
+    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, ni, (const int *)nullptr, out,
+                       ldp, (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
+  };
+  for (int v = 0; v < nrhs; ++v) ha[v] = (long long)v * n;
+  hipMemcpyAsync(off_a, ha.data(), sizeof(long long) * nrhs, hipMemcpyHostToDevice, s);
+  dots(S, off_a, 0, 1, S, nrhs);
+  hipMemcpyAsync(hh.data(), out, sizeof(cplx) * nrhs * ldp, hipMemcpyDeviceToHost, s);
+  if (int rc = hip_check(c, hipStreamSynchronize(s), "basis norms")) {
+    wfree(W);
+    return rc;
+  }
+  std::vector<double> big(ngroup, 0.0);
+  for (int b = 0; b < ngroup; ++b)
+    for (int j = 0; j < ncol; ++j)
+      big[b] = std::max(big[b], std::sqrt(std::max(hh[(size_t)(b * ncol + j) * ldp].x, 0.0)));
+  for (int b = 0; b < ngroup; ++b) hb[b] = (long long)b * n, hc[b] = (long long)b * ncol * n;
+  hipMemcpyAsync(off_b, hb.data(), sizeof(long long) * ngroup, hipMemcpyHostToDevice, s);
+  hipMemcpyAsync(off_c, hc.data(), sizeof(long long) * ngroup, hipMemcpyHostToDevice, s);
+  std::vector<double> hinv(ngroup);
+  for (int j = 0; j < ncol; ++j) {  // column j of every group against columns 0..j-1
+    for (int b = 0; b < ngroup; ++b) ha[b] = (long long)(b * ncol + j) * n;
+    hipMemcpyAsync(off_a, ha.data(), sizeof(long long) * ngroup, hipMemcpyHostToDevice, s);
+    hipLaunchKernelGGL(k_copy_vecs, dim3(gx, ngroup), dim3(256), 0, s, Wt, off_b, S, off_a, n);
+    for (int pass = 0; pass < 2 && j > 0; ++pass) {
+      dots(S, off_c, n, j, Wt, ngroup);
+      hipLaunchKernelGGL(k_sub_proj_off, dim3(gx, ngroup), dim3(256), 0, s, Wt, S, off_c, n, j, out, ldp);
+    }
+    dots(Wt, off_b, 0, 1, Wt, ngroup);
+    hipMemcpyAsync(hh.data(), out, sizeof(cplx) * ngroup * ldp, hipMemcpyDeviceToHost, s);
+    if (int rc = hip_check(c, hipStreamSynchronize(s), "basis")) {
+      wfree(W);
+      return rc;
+    }
+    for (int b = 0; b < ngroup; ++b) {
+      double nb = std::sqrt(std::max(hh[(size_t)b * ldp].x, 0.0));
+      hinv[b] = (nb > 1e-10 * big[b] && nb > 0) ? 1.0 / nb : 0.0;  // dependent column -> zero
+    }
+    hipMemcpyAsync(inv, hinv.data(), sizeof(double) * ngroup, hipMemcpyHostToDevice, s);
+    hipLaunchKernelGGL(k_scale, dim3(gx, ngroup), dim3(256), 0, s, Wt, Wt, inv, n, (const int *)nullptr);
+    hipLaunchKernelGGL(k_copy_vecs, dim3(gx, ngroup), dim3(256), 0, s, S, off_a, Wt, off_b, n);
+  }
+  int rc = hip_check(c, hipStreamSynchronize(s), "basis");
+  wfree(W);
+  return rc;
+}
+
 // Model-order reduction (MOR paragraph): full solves at the expansion
 // frequencies, an orthonormal basis S of their solutions per orbital (CGS
 // twice, columns below 1e-10 of the largest zeroed), the Galerkin model
@@ -970,7 +1088,6 @@ int mor_part(ccgf_ctx *c, int part, int K, int norb, const int *orbs, int nexp, 
   cplx *Ev = (cplx *)walloc(W, sizeof(cplx) * (size_t)norb * n);
   cplx *S = (cplx *)walloc(W, sizeof(cplx) * (size_t)nrhs * n);
   cplx *MS = (cplx *)walloc(W, sizeof(cplx) * (size_t)nrhs * n);
-  cplx *Wt = (cplx *)walloc(W, sizeof(cplx) * (size_t)norb * n);
   cplx *partial = (cplx *)walloc(W, sizeof(cplx) * (size_t)nrhs * nchunk * ldp);
   cplx *out = (cplx *)walloc(W, sizeof(cplx) * (size_t)nrhs * ldp);
   cplx *Ht = (cplx *)walloc(W, sizeof(cplx) * (size_t)norb * nexp * nexp);
@@ -978,9 +1095,7 @@ int mor_part(ccgf_ctx *c, int part, int K, int norb, const int *orbs, int nexp, 
   cplx *et = (cplx *)walloc(W, sizeof(cplx) * (size_t)norb * nexp);
   cplx *Gd = (cplx *)walloc(W, sizeof(cplx) * (size_t)norb * nw);
   double *dom = (double *)walloc(W, sizeof(double) * nw);
-  double *inv = (double *)walloc(W, sizeof(double) * nrhs);
   long long *off_a = (long long *)walloc(W, sizeof(long long) * nrhs);
-  long long *off_b = (long long *)walloc(W, sizeof(long long) * nrhs);
   long long *off_c = (long long *)walloc(W, sizeof(long long) * nrhs);
   if (W.failed) {
     wfree(W);
@@ -1004,8 +1119,7 @@ int mor_part(ccgf_ctx *c, int part, int K, int norb, const int *orbs, int nexp, 
     wfree(W);
     return status;
   }
-  const unsigned gx = (unsigned)((n + 255) / 256);
-  std::vector<long long> ha(nrhs), hb(nrhs), hc(nrhs);
+  std::vector<long long> ha(nrhs), hc(nrhs);
   std::vector<cplx> hh((size_t)nrhs * ldp);
   auto upload = [&](long long *d, const std::vector<long long> &h, int cnt) {
     hipMemcpyAsync(d, h.data(), sizeof(long long) * cnt, hipMemcpyHostToDevice, s);
@@ -1016,45 +1130,12 @@ int mor_part(ccgf_ctx *c, int part, int K, int norb, const int *orbs, int nexp, 
     hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, ni, (const int *)nullptr, out,
                        ldp, (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
   };
-  // norms of the solutions (drop threshold)
-  for (int v = 0; v < nrhs; ++v) ha[v] = (long long)v * n;
-  upload(off_a, ha, nrhs);
-  dots(S, off_a, 0, 1, S, nrhs, 1);
-  hipMemcpyAsync(hh.data(), out, sizeof(cplx) * nrhs * ldp, hipMemcpyDeviceToHost, s);
-  if (int rc = hip_check(c, hipStreamSynchronize(s), "MOR norms")) {
+  if (int rc = group_basis(c, n, n1, norb, nexp, S)) {
     wfree(W);
     return rc;
   }
-  std::vector<double> big(norb, 0.0);
-  for (int b = 0; b < norb; ++b)
-    for (int j = 0; j < nexp; ++j) big[b] = std::max(big[b], std::sqrt(std::max(hh[(size_t)(b * nexp + j) * ldp].x, 0.0)));
-  // orthonormalise column j of every orbital against columns 0..j-1
-  for (int b = 0; b < norb; ++b) hb[b] = (long long)b * n, hc[b] = (long long)b * nexp * n;
-  upload(off_b, hb, norb);
+  for (int b = 0; b < norb; ++b) hc[b] = (long long)b * nexp * n;
   upload(off_c, hc, norb);
-  std::vector<double> hinv(norb);
-  for (int j = 0; j < nexp; ++j) {
-    for (int b = 0; b < norb; ++b) ha[b] = (long long)(b * nexp + j) * n;
-    upload(off_a, ha, norb);
-    hipLaunchKernelGGL(k_copy_vecs, dim3(gx, norb), dim3(256), 0, s, Wt, off_b, S, off_a, n);
-    for (int pass = 0; pass < 2 && j > 0; ++pass) {
-      dots(S, off_c, n, j, Wt, norb, 1);
-      hipLaunchKernelGGL(k_sub_proj_off, dim3(gx, norb), dim3(256), 0, s, Wt, S, off_c, n, j, out, ldp);
-    }
-    dots(Wt, off_b, 0, 1, Wt, norb, 1);
-    hipMemcpyAsync(hh.data(), out, sizeof(cplx) * norb * ldp, hipMemcpyDeviceToHost, s);
-    if (int rc = hip_check(c, hipStreamSynchronize(s), "MOR basis")) {
-      wfree(W);
-      return rc;
-    }
-    for (int b = 0; b < norb; ++b) {
-      double nb = std::sqrt(std::max(hh[(size_t)b * ldp].x, 0.0));
-      hinv[b] = (nb > 1e-10 * big[b] && nb > 0) ? 1.0 / nb : 0.0;  // dependent column -> zero
-    }
-    hipMemcpyAsync(inv, hinv.data(), sizeof(double) * norb, hipMemcpyHostToDevice, s);
-    hipLaunchKernelGGL(k_scale, dim3(gx, norb), dim3(256), 0, s, Wt, Wt, inv, n, (const int *)nullptr);
-    hipLaunchKernelGGL(k_copy_vecs, dim3(gx, norb), dim3(256), 0, s, S, off_a, Wt, off_b, n);
-  }
   // M S, then Ht[b][j][k] = <s_bj, (M S)_bk>, bt = <s_bj, b_b>, et = e_b . s_bj
   int rc = sigma_apply(c, part, K, nrhs, S, MS, 0);
   if (rc != CCGF_OK) {
@@ -1107,5 +1188,235 @@ int mor_part(ccgf_ctx *c, int part, int K, int norb, const int *orbs, int nexp, 
     return rc2;
   }
   wfree(W);
+  return status;
+}
+
+// Training of the initial-guess network of one (part, K): plain solves at the
+// training frequencies, per-orbital reduced basis and coordinates of their
+// solutions, pairs (w_j, w_ref, c_ref) -> c_j, Adam on the GPU.
+int learn_part(ccgf_ctx *c, int part, int K, int norb, const int *orbs, int ntrain, const double *wtr, double eta,
+               const ccgf_learn_options &lo, ccgf_learn_stats *ls) {
+  const long long n = vec_len(c, part);
+  const int n1 = part == CCGF_PART_IP ? c->no : c->nv;
+  const int nrhs = norb * ntrain, R = ntrain;
+  const int nchunk = (int)((n + DOT_CHUNK - 1) / DOT_CHUNK);
+  const int ldp = R + 1;
+  hipStream_t s = c->stream;
+  auto t0 = std::chrono::steady_clock::now();
+  LearnModel M;
+  M.part = part;
+  M.K = K;
+  M.norb = norb;
+  M.ntrain = ntrain;
+  M.R = R;
+  M.hidden = lo.hidden;
+  M.mode = lo.guess;
+  M.accept = lo.accept;
+  M.din = 4 + 2 * R;
+  M.dout = 2 * R;
+  if (hipMalloc(&M.Q, sizeof(cplx) * (size_t)nrhs * n) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_err(c, CCGF_ENOMEM, "no device memory for the learned basis");
+  }
+  auto fail = [&](int rc) {
+    if (M.Q) hipFree(M.Q);
+    if (M.theta) hipFree(M.theta);
+    return rc;
+  };
+  GmresWork W;
+  cplx *Bv = (cplx *)walloc(W, sizeof(cplx) * (size_t)norb * n);
+  cplx *Ev = (cplx *)walloc(W, sizeof(cplx) * (size_t)norb * n);
+  cplx *X = (cplx *)walloc(W, sizeof(cplx) * (size_t)nrhs * n);
+  cplx *partial = (cplx *)walloc(W, sizeof(cplx) * (size_t)nrhs * nchunk * ldp);
+  cplx *out = (cplx *)walloc(W, sizeof(cplx) * (size_t)nrhs * ldp);
+  long long *off_a = (long long *)walloc(W, sizeof(long long) * nrhs);
+  if (W.failed) {
+    wfree(W);
+    return fail(set_err(c, CCGF_ENOMEM, "learning workspace allocation failed"));
+  }
+  for (int b = 0; b < norb; ++b)
+    if (int rc = build_vectors(c, part, K, orbs[b], Bv + (size_t)b * n, Ev + (size_t)b * n)) {
+      wfree(W);
+      return fail(rc);
+    }
+  std::vector<int> rorb(nrhs);
+  std::vector<double> rw(nrhs);
+  for (int b = 0; b < norb; ++b)
+    for (int j = 0; j < ntrain; ++j) rorb[b * ntrain + j] = b, rw[b * ntrain + j] = wtr[j];
+  std::vector<cplx> gtr(nrhs);
+  ccgf_stats st{};
+  int status = solve_batched(c, part, K, nrhs, rorb.data(), rw.data(), eta, Bv, Ev, gtr.data(), &st, X);
+  if (status != CCGF_OK && status != CCGF_ENOCONV) {
+    wfree(W);
+    return fail(status);
+  }
+  auto t1 = std::chrono::steady_clock::now();
+  hipMemcpyAsync(M.Q, X, sizeof(cplx) * (size_t)nrhs * n, hipMemcpyDeviceToDevice, s);
+  if (int rc = group_basis(c, n, n1, norb, R, M.Q)) {
+    wfree(W);
+    return fail(rc);
+  }
+  // C[b][j][i] = <q_{b,i}, x_{b,j}>
+  std::vector<long long> ha(nrhs);
+  for (int v = 0; v < nrhs; ++v) ha[v] = (long long)(v / ntrain) * ntrain * n;
+  hipMemcpyAsync(off_a, ha.data(), sizeof(long long) * nrhs, hipMemcpyHostToDevice, s);
+  hipLaunchKernelGGL(k_dots, dim3(nchunk, nrhs), dim3(256), 0, s, M.Q, off_a, n, R, X, n, n1, 1, (const int *)nullptr,
+                     partial, nchunk, ldp, (const int *)nullptr);
+  hipLaunchKernelGGL(k_dots_reduce, dim3(nrhs), dim3(64), 0, s, partial, nchunk, ldp, R, (const int *)nullptr, out, ldp,
+                     (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
+  std::vector<cplx> hh((size_t)nrhs * ldp);
+  hipMemcpyAsync(hh.data(), out, sizeof(cplx) * nrhs * ldp, hipMemcpyDeviceToHost, s);
+  // diagonal Fock elements of the orbitals at K (features)
+  std::vector<cplx> fd(norb);
+  for (int b = 0; b < norb; ++b) {
+    const int p = orbs[b];
+    const cplx *src = p < c->no ? c->Foo + ((size_t)K * c->no + p) * c->no + p
+                                : c->Fvv + ((size_t)K * c->nv + (p - c->no)) * c->nv + (p - c->no);
+    hipMemcpyAsync(&fd[b], src, sizeof(cplx), hipMemcpyDeviceToHost, s);
+  }
+  if (int rc = hip_check(c, hipStreamSynchronize(s), "learning coordinates")) {
+    wfree(W);
+    return fail(rc);
+  }
+  wfree(W);
+  M.orbs.assign(orbs, orbs + norb);
+  M.wtrain.assign(wtr, wtr + ntrain);
+  M.C.resize((size_t)nrhs * R);
+  M.scale.assign(norb, 1.0);
+  M.occ.resize(norb);
+  M.fpp.resize(norb);
+  for (int b = 0; b < norb; ++b) {
+    M.occ[b] = orbs[b] < c->no;
+    M.fpp[b] = fd[b].x;
+    double big = 0;
+    for (int j = 0; j < ntrain; ++j) {
+      double nn = 0;
+      for (int i = 0; i < R; ++i) {
+        cplx v = hh[(size_t)(b * ntrain + j) * ldp + i];
+        M.C[((size_t)b * ntrain + j) * R + i] = v;
+        nn += v.x * v.x + v.y * v.y;
+      }
+      big = std::max(big, std::sqrt(nn));
+    }
+    M.scale[b] = big > 0 ? 1.0 / big : 1.0;
+  }
+  double wmax = 0;
+  for (int j = 0; j < ntrain; ++j) wmax = std::max(wmax, std::fabs(wtr[j]));
+  M.wscale = wmax > 0 ? wmax : 1.0;
+  M.wstep = ntrain > 1 ? (wtr[ntrain - 1] - wtr[0]) / (ntrain - 1) : 1.0;
+  if (!(M.wstep > 0)) M.wstep = 1.0;
+  // training pairs
+  std::vector<float> F, T;
+  long long P = 0;
+  for (int b = 0; b < norb; ++b)
+    for (int j = 0; j < ntrain; ++j)
+      for (int jr = std::max(0, j - 2); jr <= std::min(ntrain - 1, j + 2); ++jr) {
+        F.resize((size_t)(P + 1) * M.din);
+        T.resize((size_t)(P + 1) * M.dout);
+        learn_features(M, b, wtr[j], jr, &F[(size_t)P * M.din]);
+        for (int i = 0; i < R; ++i) {  // target: the move of the coordinates from the reference solution
+          cplx v = M.C[((size_t)b * ntrain + j) * R + i], r0 = M.C[((size_t)b * ntrain + jr) * R + i];
+          T[(size_t)P * M.dout + i] = (float)((v.x - r0.x) * M.scale[b]);
+          T[(size_t)P * M.dout + R + i] = (float)((v.y - r0.y) * M.scale[b]);
+        }
+        ++P;
+      }
+  // parameters: uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) hidden weights, zero biases and a zero
+  // output layer, so that the untrained network proposes the reference solution itself
+  const long long np = mlp_nparams(M.din, M.hidden, M.dout);
+  std::vector<float> th(np, 0.0f);
+  std::mt19937_64 rng(lo.seed);
+  {
+    long long o = 0;
+    const int fin[3] = {M.din, M.hidden, M.hidden}, fout[3] = {M.hidden, M.hidden, M.dout};
+    for (int l = 0; l < 2; ++l) {
+      std::uniform_real_distribution<float> U(-1.0f / std::sqrt((float)fin[l]), 1.0f / std::sqrt((float)fin[l]));
+      for (long long q = 0; q < (long long)fout[l] * fin[l]; ++q) th[o + q] = U(rng);
+      o += (long long)fout[l] * fin[l] + fout[l];
+    }
+  }
+  const int bs = (int)std::min<long long>(P, lo.batch);
+  MlpWork w;
+  float *dF = nullptr, *dT = nullptr, *mm = nullptr, *vv = nullptr;
+  bool ok = mlp_alloc(w, M.din, M.hidden, M.dout, (int)P) && hipMalloc(&M.theta, sizeof(float) * np) == hipSuccess &&
+            hipMalloc(&dF, sizeof(float) * F.size()) == hipSuccess &&
+            hipMalloc(&dT, sizeof(float) * T.size()) == hipSuccess && hipMalloc(&mm, sizeof(float) * np) == hipSuccess &&
+            hipMalloc(&vv, sizeof(float) * np) == hipSuccess;
+  auto cleanup = [&]() {
+    mlp_free(w);
+    if (dF) hipFree(dF);
+    if (dT) hipFree(dT);
+    if (mm) hipFree(mm);
+    if (vv) hipFree(vv);
+  };
+  if (!ok) {
+    (void)hipGetLastError();
+    cleanup();
+    return fail(set_err(c, CCGF_ENOMEM, "no device memory for the network"));
+  }
+  hipMemcpyAsync(M.theta, th.data(), sizeof(float) * np, hipMemcpyHostToDevice, s);
+  hipMemsetAsync(mm, 0, sizeof(float) * np, s);
+  hipMemsetAsync(vv, 0, sizeof(float) * np, s);
+  auto full_loss = [&](double &L) -> int {
+    hipMemcpyAsync(dF, F.data(), sizeof(float) * F.size(), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(dT, T.data(), sizeof(float) * T.size(), hipMemcpyHostToDevice, s);
+    const int nb = mlp_backward(s, w, M.theta, (int)P, dF, dT);
+    std::vector<double> lp(nb);
+    hipMemcpyAsync(lp.data(), w.lpart, sizeof(double) * nb, hipMemcpyDeviceToHost, s);
+    int rc = hip_check(c, hipStreamSynchronize(s), "network loss");
+    L = 0;
+    for (double x : lp) L += x;
+    L *= 0.5 / (double)P;
+    return rc;
+  };
+  double L0 = 0, L1 = 0;
+  if (int rc = full_loss(L0)) {
+    cleanup();
+    return fail(rc);
+  }
+  std::vector<long long> perm(P);
+  std::vector<float> Fs(F.size()), Ts(T.size());
+  int t = 0;
+  for (int e = 0; e < lo.epochs; ++e) {
+    for (long long q = 0; q < P; ++q) perm[q] = q;
+    std::shuffle(perm.begin(), perm.end(), rng);
+    for (long long q = 0; q < P; ++q) {
+      std::copy(&F[(size_t)perm[q] * M.din], &F[(size_t)perm[q] * M.din] + M.din, &Fs[(size_t)q * M.din]);
+      std::copy(&T[(size_t)perm[q] * M.dout], &T[(size_t)perm[q] * M.dout] + M.dout, &Ts[(size_t)q * M.dout]);
+    }
+    hipMemcpyAsync(dF, Fs.data(), sizeof(float) * Fs.size(), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(dT, Ts.data(), sizeof(float) * Ts.size(), hipMemcpyHostToDevice, s);
+    for (long long q0 = 0; q0 + bs <= P; q0 += bs) {
+      mlp_backward(s, w, M.theta, bs, dF + (size_t)q0 * M.din, dT + (size_t)q0 * M.dout);
+      mlp_adam(s, np, M.theta, w.grad, mm, vv, ++t, (float)lo.lr);
+    }
+    if (int rc = hip_check(c, hipStreamSynchronize(s), "network training")) {  // host arrays reused next epoch
+      cleanup();
+      return fail(rc);
+    }
+  }
+  if (int rc = full_loss(L1)) {
+    cleanup();
+    return fail(rc);
+  }
+  cleanup();
+  auto t2 = std::chrono::steady_clock::now();
+  if (ls) {
+    ls->pairs += P;
+    ls->rank = R;
+    ls->loss_initial += L0;
+    ls->loss_final += L1;
+    ls->solve_seconds += std::chrono::duration<double>(t1 - t0).count();
+    ls->train_seconds += std::chrono::duration<double>(t2 - t1).count();
+    ls->solve_iterations += st.n_iterations;
+  }
+  for (auto it = c->models.begin(); it != c->models.end(); ++it)
+    if (it->part == part && it->K == K) {
+      if (it->Q) hipFree(it->Q);
+      if (it->theta) hipFree(it->theta);
+      c->models.erase(it);
+      break;
+    }
+  c->models.push_back(M);
   return status;
 }

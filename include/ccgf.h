@@ -103,6 +103,10 @@ typedef struct {
                           less than this fraction of ||w|| (Daniel-Gragg-Kaufman-Stewart test,
                           whose classical value is 1/sqrt(2)); 0 -> 0.1; 1 -> always two passes;
                           range [0, 1]. */
+  int autotune;          /* 0: pick each sigma GEMM's N tile width (64 or 32) by timing both on
+                            the first two launches of every new shape; -1: always 64 */
+  const char *autotune_cache; /* NULL, or a text file of earlier choices, read by cc_gf_init
+                            and rewritten by cc_gf_free */
 } ccgf_options;
 
 typedef struct {

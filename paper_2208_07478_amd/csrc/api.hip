@@ -111,11 +111,15 @@ extern "C" int cc_gf_init(const ccgf_system *s, const ccgf_options *opt, ccgf_ct
   if (o.tol == 0) o.tol = 1e-10;
   if (o.max_batch == 0) o.max_batch = 64;
   if (o.restart_m < 1 || o.restart_m > 2000 || o.maxiter < 1 || o.tol < 0 || o.max_batch < 1 ||
-      o.recycle_k < 0 || o.recycle_k > 200 || o.precond_eta < 0 || o.reorth_ratio < 0 || o.reorth_ratio > 1)
+      o.recycle_k < 0 || o.recycle_k > 200 || o.precond_eta < 0 || o.reorth_ratio < 0 || o.reorth_ratio > 1 ||
+      o.autotune < -1 || o.autotune > 0)
     return set_err(nullptr, CCGF_EINVAL, "options out of range");
 
   ccgf_ctx *c = new ccgf_ctx();
   c->opt = o;
+  if (o.autotune_cache) c->tune_path = o.autotune_cache;
+  c->opt.autotune_cache = nullptr;  // the path is kept in the context
+  tune_load(c);
   c->stream = (hipStream_t)o.hip_stream;
   for (int d = 0; d < 3; ++d) c->m[d] = s->kmesh[d];
   c->nk = s->kmesh[0] * s->kmesh[1] * s->kmesh[2];
@@ -439,6 +443,9 @@ extern "C" void cc_gf_free(ccgf_ctx *c) {
   }
   c->models.clear();
   timing_release(c);
+  tune_save(c);
+  for (int q = 0; q < 2; ++q)
+    if (c->tev[q]) hipEventDestroy(c->tev[q]);
   free_all(c);
   delete c;
 }

@@ -4,6 +4,8 @@
 
 #include <cstdint>
 #include <string>
+#include <map>
+#include <string>
 #include <vector>
 
 #include "../../include/ccgf.h"
@@ -86,6 +88,9 @@ struct GemmShape {
 
 struct GemmPlan {
   GemmShape shape;
+  int tn = 0;                   // N tile width picked by the autotuner (0: not yet)
+  int trials = 0;               // timed trial launches so far
+  float tms[2] = {0, 0};        // their times (64-wide, 32-wide)
   int ntask;
   GemmTask *d_tasks;
   GemmSeg *d_segs;
@@ -174,6 +179,10 @@ struct ccgf_ctx {
   size_t sig_part_elems = 0;
   std::vector<SigmaPlan> plans;
   std::vector<LearnModel> models;  // trained initial-guess networks
+  // GEMM tile autotuning: chosen N tile width per GEMM shape, and events for the trials
+  std::map<std::string, int> tuned;
+  hipEvent_t tev[2] = {nullptr, nullptr};
+  std::string tune_path;
   int learn_on = 1;                 // use them in cc_gf_solve
   // event timing of the sigma products (options.timing)
   // sigma timing (options.timing): events of recent products, read once they have completed
@@ -204,7 +213,11 @@ int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y, 
 // Accumulate the timings of the recorded sigma products (waits for any still running).
 void timing_harvest(ccgf_ctx *c);
 void timing_release(ccgf_ctx *c);
-void gemm_launch(int tag, const GemmPlan &plan, const void *A, const cplx *B, cplx *C, hipStream_t s, int prec);
+// Read / write the autotuner's choices (one "key tn" line per GEMM shape).
+void tune_load(ccgf_ctx *c);
+void tune_save(const ccgf_ctx *c);
+void gemm_launch(int tag, const GemmPlan &plan, const void *A, const cplx *B, cplx *C, hipStream_t s, int prec,
+                 int tn);
 void plan_upload(ccgf_ctx *c, GemmPlan &p);
 
 // gmres.hip

@@ -14,12 +14,14 @@
 #include "ccgf_internal.h"
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 #define TM 64
-#define TN 64
 #define TK 16
 
 __device__ inline long long imap(const IdxMap &m, int x) {
@@ -55,7 +57,9 @@ struct Mf<float> {
 // TAG only separates the uses in kernel traces (0: EA W_abcd, 1: EA W_lbdi,
 // 2: IP W_mnij, 3: IP W_maei, 4: EA W_abei r^e, 5: IP W_maij r_m, 6: EA 1p-row
 // reductions W_alcd r, <kl||cd> r, 7: IP 1h-row reductions W_mnie r, <mn||ef> r).
-template <int TAG, typename R>
+// TNT is the tile width in N (64, or 32 for narrow batches); the four waves of a
+// block own 32x32 (TNT = 64) or 16x32 (TNT = 32) output sub-tiles.
+template <int TAG, typename R, int TNT>
 __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *__restrict__ tasks,
                                                   const GemmSeg *__restrict__ segs,
                                                   const typename Mf<R>::AE *__restrict__ A,
@@ -74,19 +78,24 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
   const int tm = r / tilesN, tn = r % tilesN;
   const GemmTask task = tasks[t];
 
-  __shared__ R Ar[TM][TK + 1], Ai[TM][TK + 1], Br[TN][TK + 1], Bi[TN][TK + 1];
+  constexpr int NBJ = TNT / 16;           // B rows staged per thread
+  constexpr int AM = TNT == 64 ? 2 : 1;   // MFMA row tiles per wave
+  __shared__ R Ar[TM][TK + 1], Ai[TM][TK + 1], Br[TNT][TK + 1], Bi[TNT][TK + 1];
   const int tid = threadIdx.x;
 
-  // each thread stages column kt of rows rt + 16 j (j = 0..3) of both tiles
+  // each thread stages column kt of rows rt + 16 j of both tiles
   const int kt = tid & (TK - 1), rt = tid >> 4;
-  long long aoff[4], boff[4];
-  bool aok[4], bok[4];
+  long long aoff[4], boff[NBJ];
+  bool aok[4], bok[NBJ];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     int m = tm * TM + rt + 16 * j;
     aok[j] = m < sh.M;
     aoff[j] = aok[j] ? imap(sh.am, m) : 0;
-    int n = tn * TN + rt + 16 * j;
+  }
+#pragma unroll
+  for (int j = 0; j < NBJ; ++j) {
+    int n = tn * TNT + rt + 16 * j;
     bok[j] = n < sh.N;
     boff[j] = bok[j] ? imap(sh.bn, n) : 0;
   }
@@ -95,9 +104,9 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
 
   // Gauss' three-product form: P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi);
   // C = (P1 - P2) + i (P3 - P1 - P2)
-  V4 P1[2][2], P2[2][2], P3[2][2];
+  V4 P1[AM][2], P2[AM][2], P3[AM][2];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < AM; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       P1[a][b] = (V4){0, 0, 0, 0};
@@ -106,7 +115,7 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
     }
 
   AE ra[4];
-  cplx rb[4];
+  cplx rb[NBJ];
   auto load = [&](int step) {
     int s = step / ksteps;
     int k = (step - s * ksteps) * TK + kt;
@@ -115,14 +124,15 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
     const AE *Ap = A + sg.a_off + (kok ? imap(sh.ak, k) : 0);
     const cplx *Bp = B + sg.b_off + (kok ? imap(sh.bk, k) : 0);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      ra[j] = (aok[j] && kok) ? Ap[aoff[j]] : AE{0, 0};
-      rb[j] = (bok[j] && kok) ? Bp[boff[j]] : mkc(0, 0);
-    }
+    for (int j = 0; j < 4; ++j) ra[j] = (aok[j] && kok) ? Ap[aoff[j]] : AE{0, 0};
+#pragma unroll
+    for (int j = 0; j < NBJ; ++j) rb[j] = (bok[j] && kok) ? Bp[boff[j]] : mkc(0, 0);
   };
 
   const int wave = tid >> 6, lane = tid & 63;
-  const int wr = wave >> 1, wc = wave & 1;
+  // rows [rbase, rbase + 16 AM) and columns [cbase, cbase + 32) of the tile belong to this wave
+  const int rbase = TNT == 64 ? (wave >> 1) * 32 : wave * 16;
+  const int cbase = TNT == 64 ? (wave & 1) * 32 : 0;
   const int lr = lane & 15, lk = lane >> 4;
 
   if (nsteps > 0) load(0);
@@ -132,6 +142,9 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
     for (int j = 0; j < 4; ++j) {
       Ar[rt + 16 * j][kt] = (R)ra[j].x;
       Ai[rt + 16 * j][kt] = (R)ra[j].y;
+    }
+#pragma unroll
+    for (int j = 0; j < NBJ; ++j) {
       Br[rt + 16 * j][kt] = (R)rb[j].x;
       Bi[rt + 16 * j][kt] = (R)rb[j].y;
     }
@@ -139,18 +152,21 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
     if (step + 1 < nsteps) load(step + 1);
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
-      R a_r[2], a_i[2], b_r[2], b_i[2], a_s[2], b_s[2];
+      R a_r[AM], a_i[AM], a_s[AM], b_r[2], b_i[2], b_s[2];
+#pragma unroll
+      for (int q = 0; q < AM; ++q) {
+        a_r[q] = Ar[rbase + q * 16 + lr][kk + lk];
+        a_i[q] = Ai[rbase + q * 16 + lr][kk + lk];
+        a_s[q] = a_r[q] + a_i[q];
+      }
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        a_r[q] = Ar[wr * 32 + q * 16 + lr][kk + lk];
-        a_i[q] = Ai[wr * 32 + q * 16 + lr][kk + lk];
-        b_r[q] = Br[wc * 32 + q * 16 + lr][kk + lk];
-        b_i[q] = Bi[wc * 32 + q * 16 + lr][kk + lk];
-        a_s[q] = a_r[q] + a_i[q];
+        b_r[q] = Br[cbase + q * 16 + lr][kk + lk];
+        b_i[q] = Bi[cbase + q * 16 + lr][kk + lk];
         b_s[q] = b_r[q] + b_i[q];
       }
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < AM; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
           P1[a][b] = Mf<R>::mm(a_r[a], b_r[b], P1[a][b]);
@@ -161,14 +177,14 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
   }
 
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < AM; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        int row = wr * 32 + a * 16 + Mf<R>::row(lk, v);
-        int col = wc * 32 + b * 16 + lr;
-        int m = tm * TM + row, n = tn * TN + col;
+        int row = rbase + a * 16 + Mf<R>::row(lk, v);
+        int col = cbase + b * 16 + lr;
+        int m = tm * TM + row, n = tn * TNT + col;
         if (m < sh.M && n < sh.N) {
           long long off = task.c_off + imap(sh.cm, m) + imap(sh.cn, n);
           double p1 = P1[a][b][v], p2 = P2[a][b][v];
@@ -180,34 +196,42 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
       }
 }
 
-template <int TAG, typename R>
-static void launch_t(const GemmPlan &plan, const void *A, const cplx *B, cplx *C, hipStream_t s, int tilesM,
-                     int tilesN, long long total) {
-  hipLaunchKernelGGL((k_cgemm<TAG, R>), dim3((unsigned)total), dim3(256), 0, s, plan.shape, plan.d_tasks,
-                     plan.d_segs, (const typename Mf<R>::AE *)A, B, C, tilesM, tilesN, (int)total);
+template <int TAG, typename R, int TNT>
+static void launch_t(const GemmPlan &plan, const void *A, const cplx *B, cplx *C, hipStream_t s) {
+  const GemmShape &sh = plan.shape;
+  const int tilesM = (sh.M + TM - 1) / TM, tilesN = (sh.N + TNT - 1) / TNT;
+  const long long total = (long long)plan.ntask * tilesM * tilesN;
+  hipLaunchKernelGGL((k_cgemm<TAG, R, TNT>), dim3((unsigned)total), dim3(256), 0, s, sh, plan.d_tasks, plan.d_segs,
+                     (const typename Mf<R>::AE *)A, B, C, tilesM, tilesN, (int)total);
 }
 
-// prec 0: FP64 operands (A complex double); prec 1: FP32 (A complex float)
-void gemm_launch(int tag, const GemmPlan &plan, const void *A, const cplx *B, cplx *C, hipStream_t s, int prec) {
+template <int TAG, typename R>
+static void launch_w(const GemmPlan &plan, const void *A, const cplx *B, cplx *C, hipStream_t s, int tn) {
+  if (tn == 32) launch_t<TAG, R, 32>(plan, A, B, C, s);
+  else launch_t<TAG, R, 64>(plan, A, B, C, s);
+}
+
+// prec 0: FP64 operands (A complex double); prec 1: FP32 (A complex float).
+// tn: N tile width (64 or 32), chosen per plan by the autotuner in sigma_apply.
+void gemm_launch(int tag, const GemmPlan &plan, const void *A, const cplx *B, cplx *C, hipStream_t s, int prec,
+                 int tn) {
   const GemmShape &sh = plan.shape;
   if (plan.ntask == 0 || sh.M == 0 || sh.N == 0) return;
-  int tilesM = (sh.M + TM - 1) / TM, tilesN = (sh.N + TN - 1) / TN;
-  long long total = (long long)plan.ntask * tilesM * tilesN;
 #define CASE(T)                                                                              \
   case T:                                                                                    \
-    if (prec) launch_t<T, float>(plan, A, B, C, s, tilesM, tilesN, total);                   \
-    else launch_t<T, double>(plan, A, B, C, s, tilesM, tilesN, total);                       \
+    if (prec) launch_w<T, float>(plan, A, B, C, s, tn);                                      \
+    else launch_w<T, double>(plan, A, B, C, s, tn);                                          \
     break;
   switch (tag) {
     CASE(0) CASE(1) CASE(2) CASE(3) CASE(4)
     case 6:
-      launch_t<6, double>(plan, A, B, C, s, tilesM, tilesN, total);
+      launch_w<6, double>(plan, A, B, C, s, tn);
       break;
     case 7:
-      launch_t<7, double>(plan, A, B, C, s, tilesM, tilesN, total);
+      launch_w<7, double>(plan, A, B, C, s, tn);
       break;
     default:
-      launch_t<5, double>(plan, A, B, C, s, tilesM, tilesN, total);
+      launch_w<5, double>(plan, A, B, C, s, tn);
   }
 #undef CASE
 }
@@ -612,6 +636,64 @@ __global__ __launch_bounds__(256) void k_ip_local(int nk, int no, int nv, int K,
   }
 }
 
+// Launch a plan with the N tile width the autotuner picked for its shape.  The
+// first two launches of an unseen shape are timed trials of the 64- and 32-wide
+// variants (each does the real work); the 32-wide one is kept only if it is at
+// least 5% faster.  Choices are cached per shape in the context (and in the
+// autotune file when one is configured).
+static int tuned_launch(ccgf_ctx *c, int tag, GemmPlan &p, const void *A, const cplx *B, cplx *C, hipStream_t s,
+                        int prec) {
+  if (p.tn == 0 && c->opt.autotune < 0) p.tn = 64;
+  if (p.tn == 0) {
+    char key[160];
+    std::snprintf(key, sizeof key, "t%d p%d M%d N%d K%d s%zu n%d", tag, prec, p.shape.M, p.shape.N, p.shape.K,
+                  p.segs.size(), p.ntask);
+    auto it = c->tuned.find(key);
+    if (it != c->tuned.end()) {
+      p.tn = it->second;
+    } else {
+      if (!c->tev[0])
+        for (int q = 0; q < 2; ++q)
+          if (hipEventCreate(&c->tev[q]) != hipSuccess) return hip_check(c, hipGetLastError(), "autotune events");
+      const int cand = p.trials == 0 ? 64 : 32;
+      hipEventRecord(c->tev[0], s);
+      gemm_launch(tag, p, A, B, C, s, prec, cand);
+      hipEventRecord(c->tev[1], s);
+      if (hipEventSynchronize(c->tev[1]) == hipSuccess) hipEventElapsedTime(&p.tms[p.trials], c->tev[0], c->tev[1]);
+      if (++p.trials == 2) {
+        p.tn = p.tms[1] < 0.95f * p.tms[0] ? 32 : 64;
+        c->tuned[key] = p.tn;
+      }
+      return CCGF_OK;
+    }
+  }
+  gemm_launch(tag, p, A, B, C, s, prec, p.tn);
+  return CCGF_OK;
+}
+
+void tune_load(ccgf_ctx *c) {
+  if (c->tune_path.empty()) return;
+  FILE *f = std::fopen(c->tune_path.c_str(), "r");
+  if (!f) return;
+  char line[256];
+  while (std::fgets(line, sizeof line, f)) {
+    char *sp = std::strrchr(line, ' ');
+    if (!sp) continue;
+    int tn = std::atoi(sp + 1);
+    if (tn != 32 && tn != 64) continue;
+    c->tuned[std::string(line, sp - line)] = tn;
+  }
+  std::fclose(f);
+}
+
+void tune_save(const ccgf_ctx *c) {
+  if (c->tune_path.empty() || c->tuned.empty()) return;
+  FILE *f = std::fopen(c->tune_path.c_str(), "w");
+  if (!f) return;
+  for (const auto &kv : c->tuned) std::fprintf(f, "%s %d\n", kv.first.c_str(), kv.second);
+  std::fclose(f);
+}
+
 int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y, int prec) {
   if (nvec <= 0) return CCGF_OK;
   const long long n = vec_len(c, part);
@@ -705,12 +787,15 @@ int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y, 
   if (part == CCGF_PART_EA) {
     if (timing) hipEventRecord(ts->e[2], s);
     if (prec && !c->Wvvvv32) return set_err(c, CCGF_ESTATE, "mixed-precision operands were not built");
-    gemm_launch(0, P->g_big, prec ? (const void *)c->Wvvvv32 : (const void *)c->Wvvvv, x, y, s, prec);
+    const void *Wbig = prec ? (const void *)c->Wvvvv32 : (const void *)c->Wvvvv;
+    const void *Wovvo = prec ? (const void *)c->WvoP32 : (const void *)c->WvoP;
+    int rc = tuned_launch(c, 0, P->g_big, Wbig, x, y, s, prec);
     if (timing) hipEventRecord(ts->e[3], s);
-    gemm_launch(1, P->g_ovvo, prec ? (const void *)c->WvoP32 : (const void *)c->WvoP, x, c->sig_tmp, s, prec);
-    gemm_launch(4, P->g_r1, c->Wvvvo, x, y, s, 0);
-    gemm_launch(6, P->g_red1, c->Wvovv, x, c->sig_part, s, 0);
-    gemm_launch(6, P->g_red2, c->Voovv, x, c->sig_part, s, 0);
+    if (!rc) rc = tuned_launch(c, 1, P->g_ovvo, Wovvo, x, c->sig_tmp, s, prec);
+    if (!rc) rc = tuned_launch(c, 4, P->g_r1, c->Wvvvo, x, y, s, 0);
+    if (!rc) rc = tuned_launch(c, 6, P->g_red1, c->Wvovv, x, c->sig_part, s, 0);
+    if (!rc) rc = tuned_launch(c, 6, P->g_red2, c->Voovv, x, c->sig_part, s, 0);
+    if (rc) return rc;
     hipLaunchKernelGGL(k_r1_finish, dim3((unsigned)(((nv + no) * nvec + 3) / 4)), dim3(256), 0, s, 1, nk, no, nv, K,
                        nv + no, nv, nvec, nk * nk * no, n, c->sig_part, x, y, c->sig_r1aux, std::max(no, nv), c->Foo,
                        c->Fvv, c->Fov);
@@ -720,12 +805,15 @@ int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y, 
   } else {
     if (timing) hipEventRecord(ts->e[2], s);
     if (prec && !c->WooP32) return set_err(c, CCGF_ESTATE, "mixed-precision operands were not built");
-    gemm_launch(2, P->g_big, prec ? (const void *)c->WooP32 : (const void *)c->WooP, x, y, s, prec);
+    const void *Wbig = prec ? (const void *)c->WooP32 : (const void *)c->WooP;
+    const void *Wovvo = prec ? (const void *)c->WvoP32 : (const void *)c->WvoP;
+    int rc = tuned_launch(c, 2, P->g_big, Wbig, x, y, s, prec);
     if (timing) hipEventRecord(ts->e[3], s);
-    gemm_launch(3, P->g_ovvo, prec ? (const void *)c->WvoP32 : (const void *)c->WvoP, x, c->sig_tmp, s, prec);
-    gemm_launch(5, P->g_r1, c->Wovoo, x, y, s, 0);
-    gemm_launch(7, P->g_red1, c->Wooov, x, c->sig_part, s, 0);
-    gemm_launch(7, P->g_red2, c->Voovv, x, c->sig_part, s, 0);
+    if (!rc) rc = tuned_launch(c, 3, P->g_ovvo, Wovvo, x, c->sig_tmp, s, prec);
+    if (!rc) rc = tuned_launch(c, 5, P->g_r1, c->Wovoo, x, y, s, 0);
+    if (!rc) rc = tuned_launch(c, 7, P->g_red1, c->Wooov, x, c->sig_part, s, 0);
+    if (!rc) rc = tuned_launch(c, 7, P->g_red2, c->Voovv, x, c->sig_part, s, 0);
+    if (rc) return rc;
     hipLaunchKernelGGL(k_r1_finish, dim3((unsigned)(((nv + no) * nvec + 3) / 4)), dim3(256), 0, s, 0, nk, no, nv, K,
                        no + nv, no, nvec, nk * nk * no, n, c->sig_part, x, y, c->sig_r1aux, std::max(no, nv), c->Foo,
                        c->Fvv, c->Fov);

@@ -5,15 +5,15 @@ b/e vectors, solve every shifted IP and EA system of the batch with the batched
 GMRES (sigma products on MFMA), assemble G = G+ + G-.  The workload is the
 Si-like 2x2x2 k-mesh system (4 occupied + 26 virtual spin orbitals per cell,
 complex k-blocks, eta = 0.005 Ha): each step covers all 30 orbitals at K = Gamma
-and 16 frequencies spread over the 64-point grid on [-1, 1] Ha (480 points), with
+and 8 frequencies spread over the 64-point grid on [-1, 1] Ha (240 points), with
 120 right-hand sides in flight per part.
 
-Each solver form (plain FP64, mixed FP32 sigma with FP64 refinement) is timed on
-the same batch at the same GMRES tolerance, and its G is compared with a tight
-plain-FP64 solve of every 4th frequency of the batch (all orbitals); a point
-counts at the 1e-6 relative-error target (per orbital: max over the checked
-frequencies of |dG| / max |G|).  `value` is
-the points/s of the fastest form that meets it.
+Each solver form (plain FP64; mixed FP32 or BF16-split sigma with FP64
+refinement) is timed on the same batch at the same GMRES tolerance, and its G
+is compared with a tight plain-FP64 solve of every 4th frequency of the batch
+(all orbitals); a point counts at the 1e-6 relative-error target (per orbital:
+max over the checked frequencies of |dG| / max |G|).  `value` is the points/s
+of the fastest form that meets it.
 
 Prints ONE JSON line.
 """
@@ -33,9 +33,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "G(ω) points/sec at 1e-6 rel. error, learned+mixed vs plain FP64; MFMA util"
-PEAK = {"plain_f64": 78.6e12, "mixed_f32": 157.3e12}  # MI355X dense FP64 / FP32 matrix peaks, FLOP/s
-GEMM_NAME = {"plain_f64": "k_cgemm<0, double>", "mixed_f32": "k_cgemm<0, float>"}
-PRECISION = {"plain_f64": "f64", "mixed_f32": "f32"}
+# MI355X dense matrix peaks of each form's MFMA dtype, FLOP/s
+PEAK = {"plain_f64": 78.6e12, "mixed_f32": 157.3e12, "mixed_bf16x3": 2.5e15}
+GEMM_NAME = {"plain_f64": "k_cgemm<0, double>", "mixed_f32": "k_cgemm<0, float>", "mixed_bf16x3": "k_cgemm_b3<0>"}
+PRECISION = {"plain_f64": "f64", "mixed_f32": "f32", "mixed_bf16x3": "bf16x3"}
+DTYPE = {"plain_f64": "c128", "mixed_f32": "c64 sigma / c128 Krylov", "mixed_bf16x3": "bf16x3 sigma / c128 Krylov"}
 TARGET = 1e-6
 
 
@@ -45,9 +47,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="si_k222")
-    ap.add_argument("--nw", type=int, default=16, help="frequencies per step (spread over the grid)")
+    ap.add_argument("--nw", type=int, default=8, help="frequencies per step (spread over the grid)")
     ap.add_argument("--batch", type=int, default=120, help="right-hand sides in flight")
-    ap.add_argument("--forms", default="plain_f64,mixed_f32")
+    ap.add_argument("--forms", default="plain_f64,mixed_f32,mixed_bf16x3")
     ap.add_argument("--tol", type=float, default=2e-7)
     ap.add_argument("--ref-tol", type=float, default=1e-9)
     ap.add_argument("--check-every", type=int, default=4, help="reference solve on every k-th step frequency")
@@ -266,7 +268,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 sigma / c128 Krylov" if head == "mixed_f32" else "c128",
+        "dtype": DTYPE[head],
         "data": "synthetic",
         "config": {
             "workload": (f"{args.workload}: Si-like {sysm.kmesh[0]}x{sysm.kmesh[1]}x{sysm.kmesh[2]} k-mesh, "

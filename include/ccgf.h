@@ -67,7 +67,7 @@ enum { CCGF_PART_IP = 1, CCGF_PART_EA = 2, CCGF_PART_BOTH = 3 };
  * and the solution updates are FP64 in every mode; in the mixed mode the FP64
  * true residual restarts every cycle, so the restarted solve is an iterative
  * refinement and still reaches tol. */
-enum { CCGF_PLAIN_F64 = 0, CCGF_MIXED_F32 = 1 };
+enum { CCGF_PLAIN_F64 = 0, CCGF_MIXED_F32 = 1, CCGF_MIXED_BF16X3 = 2 };
 
 /* One periodic system.  All pointers are borrowed for the duration of
  * cc_gf_init only (the library copies what it needs to the device); they are
@@ -87,8 +87,13 @@ typedef struct {
 } ccgf_system;
 
 typedef struct {
-  int precision;    /* CCGF_PLAIN_F64 or CCGF_MIXED_F32 (W_abcd, W_mbej, W_mnij GEMMs in complex
-                       float on FP32 MFMA; needs half the size of those blocks again in memory) */
+  int precision;    /* CCGF_PLAIN_F64; CCGF_MIXED_F32: the Krylov steps' sigma products take the
+                       W_abcd, W_lbdi (EA) and W_mnij, W_maei (IP) GEMMs in complex float on FP32
+                       MFMA; CCGF_MIXED_BF16X3: the same GEMMs as three BF16 products per real
+                       product (hi*hi + hi*lo + lo*hi, FP32 accumulation) on BF16 MFMA.  Both
+                       mixed forms keep residuals, orthogonalisation, the Hessenberg least
+                       squares and a refinement from the FP64 true residual every cycle in
+                       FP64, and need half the size of those blocks again in memory. */
   int restart_m;    /* Krylov vectors per cycle, 1..2000; 0 -> 30 */
   int maxiter;      /* total GMRES iterations per solve; 0 -> 2000 */
   double tol;       /* relative residual ||b - A x|| / ||b|| in the unique-pair norm; 0 -> 1e-10 */
@@ -107,6 +112,9 @@ typedef struct {
                             the first two launches of every new shape; -1: always 64 */
   const char *autotune_cache; /* NULL, or a text file of earlier choices, read by cc_gf_init
                             and rewritten by cc_gf_free */
+  int graphs;            /* 0: once a sigma plan's GEMM widths are tuned, capture its launch
+                            sequence (per operand pair and precision, up to 8) into a HIP graph
+                            and replay it; -1: launch eagerly.  Timed runs launch eagerly. */
 } ccgf_options;
 
 typedef struct {

@@ -19,8 +19,9 @@ LIB_PATH = os.path.join(HERE, "libccgf.so")
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 HOST, DEVICE = 0, 1
 PART_IP, PART_EA, PART_BOTH = 1, 2, 3
-PLAIN_F64, MIXED_F32 = 0, 1
-PRECISIONS = {"f64": PLAIN_F64, "plain_f64": PLAIN_F64, "f32": MIXED_F32, "mixed_f32": MIXED_F32}
+PLAIN_F64, MIXED_F32, MIXED_BF16X3 = 0, 1, 2
+PRECISIONS = {"f64": PLAIN_F64, "plain_f64": PLAIN_F64, "f32": MIXED_F32, "mixed_f32": MIXED_F32,
+              "bf16x3": MIXED_BF16X3, "mixed_bf16x3": MIXED_BF16X3}
 
 EXPORTS = ("cc_gf_init", "cc_gf_solve", "cc_gf_mor", "cc_gf_vector_size", "cc_gf_sigma", "cc_gf_vectors",
            "cc_gf_learn", "cc_gf_learn_enable", "cc_gf_mlp_grad", "cc_gf_free", "cc_gf_last_error")
@@ -39,7 +40,7 @@ class Options(ctypes.Structure):
                 ("tol", ctypes.c_double), ("max_batch", ctypes.c_int), ("hip_stream", ctypes.c_void_p),
                 ("timing", ctypes.c_int), ("precond_eta", ctypes.c_double), ("recycle_k", ctypes.c_int),
                 ("reorth_ratio", ctypes.c_double), ("autotune", ctypes.c_int),
-                ("autotune_cache", ctypes.c_char_p)]
+                ("autotune_cache", ctypes.c_char_p), ("graphs", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -140,7 +141,7 @@ class Context:
 
     def __init__(self, system, *, tol=1e-10, restart_m=30, maxiter=2000, max_batch=64, stream=None,
                  timing=False, foo=None, fvv=None, precond_eta=0.0, recycle_k=0, precision="f64",
-                 reorth_ratio=0.0, autotune=True, autotune_cache=None):
+                 reorth_ratio=0.0, autotune=True, autotune_cache=None, graphs=True):
         lib = load()
         import torch  # device memory and streams only
         self._torch = torch
@@ -168,7 +169,7 @@ class Context:
         opt = Options(prec, int(restart_m), int(maxiter), float(tol), int(max_batch),
                       ctypes.c_void_p(stream.cuda_stream), 1 if timing else 0, float(precond_eta),
                       int(recycle_k), float(reorth_ratio), 0 if autotune else -1,
-                      None if autotune_cache is None else str(autotune_cache).encode())
+                      None if autotune_cache is None else str(autotune_cache).encode(), 0 if graphs else -1)
         self._opt = opt
         h = ctypes.c_void_p()
         rc = lib.cc_gf_init(ctypes.byref(cs), ctypes.byref(opt), ctypes.byref(h))

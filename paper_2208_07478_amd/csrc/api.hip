@@ -104,15 +104,15 @@ extern "C" int cc_gf_init(const ccgf_system *s, const ccgf_options *opt, ccgf_ct
     return set_err(nullptr, CCGF_EINVAL, "mem_space must be CCGF_HOST or CCGF_DEVICE");
   ccgf_options o{};
   if (opt) o = *opt;
-  if (o.precision != CCGF_PLAIN_F64 && o.precision != CCGF_MIXED_F32)
-    return set_err(nullptr, CCGF_EUNSUPPORTED, "precision must be CCGF_PLAIN_F64 or CCGF_MIXED_F32");
+  if (o.precision != CCGF_PLAIN_F64 && o.precision != CCGF_MIXED_F32 && o.precision != CCGF_MIXED_BF16X3)
+    return set_err(nullptr, CCGF_EUNSUPPORTED, "precision must be CCGF_PLAIN_F64, CCGF_MIXED_F32 or CCGF_MIXED_BF16X3");
   if (o.restart_m == 0) o.restart_m = 30;
   if (o.maxiter == 0) o.maxiter = 2000;
   if (o.tol == 0) o.tol = 1e-10;
   if (o.max_batch == 0) o.max_batch = 64;
   if (o.restart_m < 1 || o.restart_m > 2000 || o.maxiter < 1 || o.tol < 0 || o.max_batch < 1 ||
       o.recycle_k < 0 || o.recycle_k > 200 || o.precond_eta < 0 || o.reorth_ratio < 0 || o.reorth_ratio > 1 ||
-      o.autotune < -1 || o.autotune > 0)
+      o.autotune < -1 || o.autotune > 0 || o.graphs < -1 || o.graphs > 0)
     return set_err(nullptr, CCGF_EINVAL, "options out of range");
 
   ccgf_ctx *c = new ccgf_ctx();
@@ -444,6 +444,10 @@ extern "C" void cc_gf_free(ccgf_ctx *c) {
   c->models.clear();
   timing_release(c);
   tune_save(c);
+  for (auto &P : c->plans)
+    for (auto &g : P.graphs) hipGraphExecDestroy(g.exec);
+  c->plans.clear();
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   for (int q = 0; q < 2; ++q)
     if (c->tev[q]) hipEventDestroy(c->tev[q]);
   free_all(c);

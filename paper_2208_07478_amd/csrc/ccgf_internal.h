@@ -88,9 +88,9 @@ struct GemmShape {
 
 struct GemmPlan {
   GemmShape shape;
-  int tn = 0;                   // N tile width picked by the autotuner (0: not yet)
-  int trials = 0;               // timed trial launches so far
-  float tms[2] = {0, 0};        // their times (64-wide, 32-wide)
+  int tn[3] = {0, 0, 0};        // N tile width picked by the autotuner per precision (0: not yet)
+  int trials[3] = {0, 0, 0};    // timed trial launches so far
+  float tms[3][2] = {};         // their times (64-wide, 32-wide)
   int ntask;
   GemmTask *d_tasks;
   GemmSeg *d_segs;
@@ -106,6 +106,12 @@ struct SigmaPlan {  // per (part, K, batch layout)
   GemmPlan g_r1;    // EA: W_abei r^e; IP: -W_maij r_m  (accumulates into sigma2)
   GemmPlan g_red1;  // split-K partial sums of the 1p / 1h rows of sigma (EA W_alcd, IP W_mnie)
   GemmPlan g_red2;  // split-K partial sums of the three-body intermediate (<kl||cd> r / <mn||ef> r)
+  struct Captured {
+    const void *x, *y;
+    int prec;
+    hipGraphExec_t exec;
+  };
+  std::vector<Captured> graphs;  // captured launch sequences, most recent last
   bool ready = false;
 };
 
@@ -166,9 +172,10 @@ struct ccgf_ctx {
   cplx *Woooo = nullptr, *Wooov = nullptr, *Wovoo = nullptr, *Wovvo = nullptr;
   cplx *Wvovv = nullptr, *Wvvvo = nullptr, *Wvvvv = nullptr, *Voovv = nullptr;
   cplx *WvoP = nullptr;   // W_ovvo permuted to [kx][ki][km](x, i, m, e)
+  cplx *WvoPea = nullptr; // the same with F_vv added on the blocks km = ki, m = i (EA operand)
   cplx *WooP = nullptr;   // W_oooo permuted to [ki][kj][km](i, j, m, n)
   // complex-float copies of the GEMM operands for the mixed-precision products
-  float2 *Wvvvv32 = nullptr, *WvoP32 = nullptr, *WooP32 = nullptr;
+  float2 *Wvvvv32 = nullptr, *WvoP32 = nullptr, *WooP32 = nullptr, *WvoPea32 = nullptr;
   std::vector<void *> allocs;
   // sigma workspace
   cplx *sig_tmp = nullptr;  // scratch vector batch for the W_ovvo term
@@ -182,6 +189,7 @@ struct ccgf_ctx {
   // GEMM tile autotuning: chosen N tile width per GEMM shape, and events for the trials
   std::map<std::string, int> tuned;
   hipEvent_t tev[2] = {nullptr, nullptr};
+  hipStream_t cap_stream = nullptr;  // private stream on which sigma launch sequences are captured
   std::string tune_path;
   int learn_on = 1;                 // use them in cc_gf_solve
   // event timing of the sigma products (options.timing)

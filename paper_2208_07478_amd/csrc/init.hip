@@ -335,9 +335,21 @@ int build_hbar(ccgf_ctx *c) {
     int ki = x.k1, kj = x.k2, km = x.k3, kn = kt.c3(ki, kj, km);
     WooP.p[i] = Woooo(km, kn, ki, x.c, x.d, x.a, x.b);
   });
+  // EA operand of the same product with the virtual Fock block folded in: the sigma_EA term
+  // F_bd r_i^ad has the form of W_lbdi r_l^ad with l = i, so [kb][ki][ki](b, i, i, d) += F_bd(kb)
+  T4 WvoPea = make_t4(c, nv, no, no, nv);
+  if (!WvoPea.p) return CCGF_ENOMEM;
+  c->WvoPea = WvoPea.p;
+  const cplx *Fvv_ = c->Fvv;
+  foreach_(s, WvoPea.size(), [=] __device__(size_t i) {
+    I7 x = dec(i, nk, nv, no, no, nv);
+    cplx w = WvoP.p[i];
+    if (x.k3 == x.k2 && x.c == x.b) w = cadd(w, Fvv_[((size_t)x.k1 * nv + x.a) * nv + x.d]);
+    WvoPea.p[i] = w;
+  });
 
   c->Voovv = Voovv.p;
-  if (c->opt.precision == CCGF_MIXED_F32) {
+  if (c->opt.precision != CCGF_PLAIN_F64) {  // FP32 operands of the big products (both mixed forms)
     // complex-float copies of the GEMM operands (rounded once, here)
     auto to32 = [&](const cplx *src, size_t nel) -> float2 * {
       float2 *d = (float2 *)dev_alloc(c, nel * sizeof(float2));
@@ -348,7 +360,8 @@ int build_hbar(ccgf_ctx *c) {
     c->Wvvvv32 = to32(Wvvvv.p, Wvvvv.size());
     c->WvoP32 = to32(WvoP.p, WvoP.size());
     c->WooP32 = to32(WooP.p, WooP.size());
-    if (!c->Wvvvv32 || !c->WvoP32 || !c->WooP32) return CCGF_ENOMEM;
+    c->WvoPea32 = to32(WvoPea.p, WvoPea.size());
+    if (!c->Wvvvv32 || !c->WvoP32 || !c->WooP32 || !c->WvoPea32) return CCGF_ENOMEM;
   }
   if (hip_check(c, hipStreamSynchronize(s), "building Hbar blocks") != CCGF_OK) return CCGF_EDEVICE;
   // release the integral classes that the products do not read

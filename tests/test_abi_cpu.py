@@ -74,3 +74,32 @@ def test_invalid_inputs_are_rejected_on_the_host():
     assert lib.cc_gf_mor(None, 0, None, 0, None, 1, None, 1, None, 0, None, 0.1, 3, None, None, None,
                          None) == ccgf.ESTATE
     lib.cc_gf_free(None)
+
+
+def test_options_and_new_entry_points_are_checked_on_the_host():
+    """Out-of-range options are rejected by cc_gf_init before any device work;
+    the learning and network entry points reject NULL contexts and bad sizes."""
+    lib = ccgf.load()
+    s = synth.make_system((1, 1, 1), 2, 3, seed=2, real=True, naux=8)
+    h = ctypes.c_void_p()
+    cs, keep = _system_struct(s)
+    bad = [dict(precision=7), dict(restart_m=-1), dict(restart_m=2001), dict(tol=-1.0), dict(max_batch=-2),
+           dict(recycle_k=201), dict(precond_eta=-0.1), dict(reorth_ratio=1.5), dict(autotune=2),
+           dict(graphs=3)]
+    for kw in bad:
+        o = ccgf.Options()
+        for k, v in kw.items():
+            setattr(o, k, v)
+        rc = lib.cc_gf_init(ctypes.byref(cs), ctypes.byref(o), ctypes.byref(h))
+        assert rc in (ccgf.EINVAL, ccgf.EUNSUPPORTED), kw
+        assert not h.value
+    ip = ctypes.POINTER(ctypes.c_int)
+    dp = ctypes.POINTER(ctypes.c_double)
+    assert lib.cc_gf_learn(None, 3, 0, 1, None, 1, None, 0.1, None, None) == ccgf.ESTATE
+    assert lib.cc_gf_learn_enable(None, 1) == ccgf.ESTATE
+    fp = ctypes.POINTER(ctypes.c_float)
+    for dims in ((0, 4, 2, 3), (3, 0, 2, 3), (3, 4, 0, 3), (3, 4, 2, 0), (5000, 4, 2, 3)):
+        din, hid, dout, N = dims
+        assert lib.cc_gf_mlp_grad(din, hid, dout, None, N, None, None, None, None) == ccgf.EINVAL
+    one = (ctypes.c_float * 64)()
+    assert lib.cc_gf_mlp_grad(3, 4, 2, None, 3, one, one, one, None) == ccgf.EINVAL

@@ -41,6 +41,37 @@ def pair(request):
 
 
 @pytest.mark.parametrize("part", ["ip", "ea"])
+def test_sigma_tile_variants_match_oracle(pair, part):
+    """The autotuner's two trial launches (64- and 32-wide N tiles), the chosen
+    variant captured into a HIP graph and its replays (with other work and
+    synchronisations in between) each give the oracle's product; so does the
+    untuned eager path."""
+    import torch
+    from paper_2208_07478_amd.ccgf import Context
+    s, E, ctx = pair
+    K = E.nk - 1
+    nu = len(E.unique_index(part, K)[0])
+    U = synth.random_vectors(nu, 37, seed=500 + K)  # a batch width no other test uses: a fresh plan
+    X = np.array([E.unpack(part, K, u) for u in U])
+    ref = np.array([E.sigma(part, K, x) for x in X])
+    Xd = torch.from_numpy(X).cuda()
+    Yd = torch.empty_like(Xd)
+    for call in range(6):
+        Y = ctx.sigma(part, K, Xd).cpu().numpy()  # calls >= 2: graph capture, then replays
+        err = np.abs(Y - ref).max() / np.abs(ref).max()
+        print(part, K, "call", call, "rel err", err, flush=True)
+        assert err <= 1e-12
+        Yd.copy_(Xd * (call + 1))  # eager work between replays
+        torch.cuda.synchronize()
+    ctx2 = Context(s, autotune=False, graphs=False)
+    try:
+        Y = ctx2.sigma(part, K, Xd).cpu().numpy()
+        assert np.abs(Y - ref).max() <= 1e-12 * np.abs(ref).max()
+    finally:
+        ctx2.close()
+
+
+@pytest.mark.parametrize("part", ["ip", "ea"])
 def test_sigma_matches_oracle(pair, part):
     import torch
     s, E, ctx = pair

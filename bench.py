@@ -35,7 +35,9 @@ if ROOT not in sys.path:
 METRIC = "G(ω) points/sec at 1e-6 rel. error, learned+mixed vs plain FP64; MFMA util"
 # MI355X dense matrix peaks of each form's MFMA dtype, FLOP/s
 PEAK = {"plain_f64": 78.6e12, "mixed_f32": 157.3e12, "mixed_bf16x3": 2.5e15}
-GEMM_NAME = {"plain_f64": "k_cgemm<0, double>", "mixed_f32": "k_cgemm<0, float>", "mixed_bf16x3": "k_cgemm_b3<0>"}
+# the dominant kernel of each form (EA 1/2 W_abcd r_i^cd); the traffic record is the 64-wide tile's
+GEMM_NAME = {"plain_f64": "k_cgemm<0, double, 64>", "mixed_f32": "k_cgemm<0, float, 64>",
+             "mixed_bf16x3": "k_cgemm_b3<0>"}
 PRECISION = {"plain_f64": "f64", "mixed_f32": "f32", "mixed_bf16x3": "bf16x3"}
 DTYPE = {"plain_f64": "c128", "mixed_f32": "c64 sigma / c128 Krylov", "mixed_bf16x3": "bf16x3 sigma / c128 Krylov"}
 TARGET = 1e-6
@@ -222,7 +224,7 @@ def main():
             "max_rel_residual": tot["max_rel_residual"],
             "unconverged": tot["n_unconverged"],
             "init_s": init_s,
-            "roofline": {"bound": "mfma", "kernel": GEMM_NAME[form] + " (EA 1/2 W_abcd r_i^cd)",
+            "roofline": {"bound": "mfma", "kernel": GEMM_NAME[form] + " (EA 1/2 W_abcd r_i^cd; autotuned 64/32 tiles)",
                          "achieved": ach / 1e12, "peak": PEAK[form] / 1e12, "unit": "TFLOP/s",
                          "frac": ach / PEAK[form], "avg_ms": avg_ms, "flops_per_launch": fl,
                          "launches": tot["big_launches"]},

@@ -112,6 +112,10 @@ typedef struct {
                             the first two launches of every new shape; -1: always 64 */
   const char *autotune_cache; /* NULL, or a text file of earlier choices, read by cc_gf_init
                             and rewritten by cc_gf_free */
+  int restart_tail;      /* restart length for cycles that start once every right-hand side of a
+                            call is in flight and at most a quarter of the batch is still
+                            iterating (the slowest solves); 0 -> restart_m; up to 2000, reduced
+                            to fit 70% of the free device memory (GMRES only, not GCROT) */
   int graphs;            /* 0: once a sigma plan's GEMM widths are tuned, capture its launch
                             sequence (per operand pair and precision, up to 8) into a HIP graph
                             and replay it; -1: launch eagerly.  Timed runs launch eagerly. */

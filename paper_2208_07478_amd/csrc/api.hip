@@ -112,7 +112,8 @@ extern "C" int cc_gf_init(const ccgf_system *s, const ccgf_options *opt, ccgf_ct
   if (o.max_batch == 0) o.max_batch = 64;
   if (o.restart_m < 1 || o.restart_m > 2000 || o.maxiter < 1 || o.tol < 0 || o.max_batch < 1 ||
       o.recycle_k < 0 || o.recycle_k > 200 || o.precond_eta < 0 || o.reorth_ratio < 0 || o.reorth_ratio > 1 ||
-      o.autotune < -1 || o.autotune > 0 || o.graphs < -1 || o.graphs > 0)
+      o.autotune < -1 || o.autotune > 0 || o.graphs < -1 || o.graphs > 0 || o.restart_tail < 0 ||
+      o.restart_tail > 2000)
     return set_err(nullptr, CCGF_EINVAL, "options out of range");
 
   ccgf_ctx *c = new ccgf_ctx();

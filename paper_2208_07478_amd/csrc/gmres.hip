@@ -564,10 +564,25 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
   const int n1 = part == CCGF_PART_IP ? c->no : c->nv;
   const double sM = part == CCGF_PART_IP ? 1.0 : -1.0;
   const double sE = part == CCGF_PART_IP ? -1.0 : 1.0;
-  const int m = c->opt.restart_m;
   const int kr = c->opt.recycle_k;          // recycled pairs (0: GMRES(m))
   const int kslots = std::max(kr, 1);
   const int Bmax = std::max(1, std::min(c->opt.max_batch, nrhs));
+  // cycle lengths: restart_m, and restart_tail for cycles that start once the queue is
+  // empty and at most a quarter of the slots are still busy (few slots: long cycles are
+  // cheap to orthogonalise and help the slowest solves most); m sizes the workspace
+  const int m_run = c->opt.restart_m;
+  int m = m_run;
+  if (kr == 0 && c->opt.restart_tail > m_run) {
+    size_t fr = 0, tot = 0;
+    const size_t per_col = sizeof(cplx) * (size_t)Bmax * n;
+    int fit = m_run;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess && per_col > 0) {
+      const double cols = 0.7 * (double)fr / (double)per_col - 8.0;  // basis columns that fit
+      if (cols > m_run) fit = (int)std::min<double>(c->opt.restart_tail, cols);
+    }
+    m = std::max(m_run, std::min(c->opt.restart_tail, fit));
+  }
+  const int m_tail = m;
   const int nchunk = (int)((n + DOT_CHUNK - 1) / DOT_CHUNK);
   const int ldp = std::max(m, kslots) + 1;
   hipStream_t s = c->stream;
@@ -820,7 +835,12 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
     }
     {  // start cycles
       bool anyin = false;
-      for (int v = 0; v < B; ++v) anyin = anyin || incyc[v];
+      int busy = 0;
+      for (int v = 0; v < B; ++v) {
+        anyin = anyin || incyc[v];
+        busy += rhs_of[v] >= 0 && !hconv[v] && its[v] < maxit;
+      }
+      const int mcyc = (refill_each && next >= nrhs && 4 * busy <= B) ? m_tail : m_run;
       int nstart = 0, occupied = 0;
       for (int v = 0; v < B; ++v) {
         occupied += rhs_of[v] >= 0;
@@ -829,7 +849,7 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
           ++nstart;
           incyc[v] = 1;
           hj[v] = 0;
-          hjlim[v] = std::min(m, std::max(0, maxit - its[v]));  // iteration budget of this cycle
+          hjlim[v] = std::min(mcyc, std::max(0, maxit - its[v]));  // iteration budget of this cycle
           hinv[v] = hrn[v] > 0 ? 1.0 / hrn[v] : 0.0;
         }
       }

@@ -34,12 +34,13 @@ if ROOT not in sys.path:
 
 METRIC = "G(ω) points/sec at 1e-6 rel. error, learned+mixed vs plain FP64; MFMA util"
 # MI355X dense matrix peaks of each form's MFMA dtype, FLOP/s
-PEAK = {"plain_f64": 78.6e12, "mixed_f32": 157.3e12, "mixed_bf16x3": 2.5e15}
+PEAK = {"plain_f64": 78.6e12, "mixed_f32": 157.3e12, "mixed_bf16x3": 2.5e15, "learned_mixed_f32": 157.3e12}
 # the dominant kernel of each form (EA 1/2 W_abcd r_i^cd); the traffic record is the 64-wide tile's
 GEMM_NAME = {"plain_f64": "k_cgemm<0, double, 64>", "mixed_f32": "k_cgemm<0, float, 64>",
-             "mixed_bf16x3": "k_cgemm_b3<0>"}
-PRECISION = {"plain_f64": "f64", "mixed_f32": "f32", "mixed_bf16x3": "bf16x3"}
-DTYPE = {"plain_f64": "c128", "mixed_f32": "c64 sigma / c128 Krylov", "mixed_bf16x3": "bf16x3 sigma / c128 Krylov"}
+             "mixed_bf16x3": "k_cgemm_b3<0>", "learned_mixed_f32": "k_cgemm<0, float, 64>"}
+PRECISION = {"plain_f64": "f64", "mixed_f32": "f32", "mixed_bf16x3": "bf16x3", "learned_mixed_f32": "f32"}
+DTYPE = {"plain_f64": "c128", "mixed_f32": "c64 sigma / c128 Krylov", "mixed_bf16x3": "bf16x3 sigma / c128 Krylov",
+         "learned_mixed_f32": "c64 sigma / c128 Krylov, FP32 network"}
 TARGET = 1e-6
 
 
@@ -51,7 +52,8 @@ def parse():
     ap.add_argument("--workload", default="si_k222")
     ap.add_argument("--nw", type=int, default=8, help="frequencies per step (spread over the grid)")
     ap.add_argument("--batch", type=int, default=120, help="right-hand sides in flight")
-    ap.add_argument("--forms", default="plain_f64,mixed_f32,mixed_bf16x3")
+    ap.add_argument("--forms", default="plain_f64,mixed_f32,mixed_bf16x3",
+                    help="comma list of plain_f64, mixed_f32, mixed_bf16x3, learned_mixed_f32")
     ap.add_argument("--tol", type=float, default=2e-7)
     ap.add_argument("--ref-tol", type=float, default=1e-9)
     ap.add_argument("--check-every", type=int, default=4, help="reference solve on every k-th step frequency")
@@ -179,6 +181,14 @@ def main():
         t0 = time.perf_counter()
         ctx = Context(sysm, timing=True, precision=PRECISION[form], **opts)
         init_s = time.perf_counter() - t0
+        learn = None
+        if form.startswith("learned"):
+            # train on the grid frequencies midway between the step's (not timed; reported)
+            wtrain = omega[stride // 2::stride][:args.nw]
+            t1 = time.perf_counter()
+            learn = ctx.learn(0, orbs, wtrain, eta, allow_noconv=True)
+            learn["seconds"] = time.perf_counter() - t1
+            print(f"{form} training: {learn['seconds']:.1f} s", file=sys.stderr, flush=True)
 
         def step():
             # one pass over the batch: IP then EA solves of all orbitals x frequencies, G = G- + G+
@@ -193,7 +203,8 @@ def main():
             step()
         torch.cuda.synchronize()
         tot = {"big_ms": 0.0, "big_launches": 0, "big_flops": 0.0, "n_iterations": 0, "sigma_ms": 0.0,
-               "n_solves": 0, "max_rel_residual": 0.0, "n_unconverged": 0, "n_steps": 0, "n_reorth": 0}
+               "n_solves": 0, "max_rel_residual": 0.0, "n_unconverged": 0, "n_steps": 0, "n_reorth": 0,
+               "n_guess": 0}
         nsig = {"ip": 0, "ea": 0}
         t1 = time.perf_counter()
         for i in range(args.steps):
@@ -216,6 +227,7 @@ def main():
             "ms_per_step": 1e3 * elapsed / args.steps,
             "G": G,
             "iterations_per_solve": tot["n_iterations"] / max(tot["n_solves"], 1),
+            "guesses_used": tot["n_guess"],
             "batched_steps": tot["n_steps"],
             "mean_active": tot["n_iterations"] / max(tot["n_steps"], 1),
             "reorth_fraction": tot["n_reorth"] / max(tot["n_iterations"], 1),
@@ -224,6 +236,7 @@ def main():
             "max_rel_residual": tot["max_rel_residual"],
             "unconverged": tot["n_unconverged"],
             "init_s": init_s,
+            "learn": learn,
             "roofline": {"bound": "mfma", "kernel": GEMM_NAME[form] + " (EA 1/2 W_abcd r_i^cd; autotuned 64/32 tiles)",
                          "achieved": ach / 1e12, "peak": PEAK[form] / 1e12, "unit": "TFLOP/s",
                          "frac": ach / PEAK[form], "avg_ms": avg_ms, "flops_per_launch": fl,

@@ -69,3 +69,32 @@ def test_green_function_points(setup):
         ref = complex(rec["g"][0], rec["g"][1])
         print(rec["part"], rec["K"], rec["p"], rec["w"], got, ref, flush=True)
         assert abs(got - ref) <= 1e-9 * abs(ref)
+
+
+@pytest.mark.parametrize("prec,bound", [("f32", 2e-5), ("bf16x3", 2e-4)])
+def test_reduced_precision_sigma_samples(setup, prec, bound):
+    """The mixed forms' products at full size (120-vector batch) against the
+    oracle samples, to the precision of each form."""
+    import torch
+    from paper_2208_07478_amd import synth
+    from paper_2208_07478_amd.ccgf import Context
+    s, gold, _ = setup
+    ctx = Context(s, max_batch=120, precision=prec)
+    try:
+        cache = {}
+        worst = 0.0
+        for rec in gold["sigma"]:
+            key = (rec["part"], rec["K"], rec["seed"])
+            if key not in cache:
+                X = synth.random_eom_vectors(s.kmesh, s.nocc, s.nvir, rec["part"], rec["K"], gold["nvec"],
+                                             seed=rec["seed"])
+                cache[key] = ctx.sigma(rec["part"], rec["K"], torch.from_numpy(X).cuda()).cpu().numpy()
+            got = cache[key][rec["vec"], rec["idx"]]
+            err = np.abs(got - c(rec["val"])).max() / rec["scale"]
+            worst = max(worst, err)
+            assert err <= bound, (rec["part"], rec["K"], rec["vec"], err)
+        print(prec, "worst sample error", worst, flush=True)
+        assert worst > 1e-10  # the reduced-precision path really ran
+    finally:
+        ctx.close()
+        torch.cuda.synchronize()

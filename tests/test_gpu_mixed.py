@@ -82,3 +82,48 @@ def test_mixed_solver_reaches_fp64_accuracy(ci, prec):
     finally:
         ctx.close()
         torch.cuda.synchronize()
+
+
+def _peaks(w, A):
+    """Local maxima of A above 5% of its maximum, refined by a 3-point parabola."""
+    out = []
+    thr = 0.05 * A.max()
+    for i in range(1, len(w) - 1):
+        if A[i] > A[i - 1] and A[i] >= A[i + 1] and A[i] > thr:
+            den = A[i - 1] - 2 * A[i] + A[i + 1]
+            off = 0.5 * (A[i - 1] - A[i + 1]) / den if den != 0 else 0.0
+            out.append(w[i] + off * (w[1] - w[0]))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_mixed_forms_keep_spectral_peaks_within_1meV(prec):
+    """A(w) = -(1/pi)[Im G+ - Im G-] on a fine grid: the mixed forms reproduce
+    plain FP64's peaks (count and positions to 1 meV) and G to 1e-6 relative,
+    at the bench's GMRES tolerance."""
+    import torch
+    from paper_2208_07478_amd.ccgf import Context
+    s = _system(CASES[0])
+    w = np.linspace(-1.2, 2.0, 321)
+    eta = 0.01
+    nmo = s.nocc + s.nvir
+    ks = list(range(int(np.prod(s.kmesh))))
+    res = {}
+    for p in ("f64", prec):
+        ctx = Context(s, max_batch=64, maxiter=12000, restart_m=60, tol=2e-7, precision=p)
+        try:
+            res[p] = ctx.solve(ks, list(range(nmo)), w, eta)
+        finally:
+            ctx.close()
+            torch.cuda.synchronize()
+    G0, Gp0, Gm0, _ = res["f64"]
+    G1, Gp1, Gm1, _ = res[prec]
+    mev = 1e-3 / 27.211386
+    for a in range(len(ks)):
+        for p in range(nmo):
+            A0 = -(Gp0[a, p].imag - Gm0[a, p].imag) / np.pi
+            A1 = -(Gp1[a, p].imag - Gm1[a, p].imag) / np.pi
+            assert np.abs(G1[a, p] - G0[a, p]).max() <= 1e-6 * np.abs(G0[a, p]).max()
+            p0, p1 = _peaks(w, A0), _peaks(w, A1)
+            assert len(p0) == len(p1) and len(p0) > 0, (a, p)
+            assert np.abs(p0 - p1).max() <= mev, (a, p, np.abs(p0 - p1).max())

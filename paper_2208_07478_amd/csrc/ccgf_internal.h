@@ -76,6 +76,7 @@ struct GemmTask {
 };
 struct GemmSeg {
   long long a_off, b_off;
+  double w = 1.0;  // weight of this segment's products (exact: 1 or 1/2)
 };
 struct GemmShape {
   int M, N, K;
@@ -106,6 +107,11 @@ struct SigmaPlan {  // per (part, K, batch layout)
   GemmPlan g_r1;    // EA: W_abei r^e; IP: -W_maij r_m  (accumulates into sigma2)
   GemmPlan g_red1;  // split-K partial sums of the 1p / 1h rows of sigma (EA W_alcd, IP W_mnie)
   GemmPlan g_red2;  // split-K partial sums of the three-body intermediate (<kl||cd> r / <mn||ef> r)
+  // EA: output blocks of the W_abcd product left to antisymmetry, sigma[ki][ka](i,a,b) =
+  // -sigma[ki][kb](i,b,a): offsets of the destination and source blocks in a vector
+  int nfill = 0;
+  long long *d_fill = nullptr;  // [2][nfill]
+  std::vector<long long> fill_h;  // host copy, checked against the vector size
   struct Captured {
     const void *x, *y;
     int prec;

@@ -126,7 +126,7 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
 #pragma unroll
     for (int j = 0; j < 4; ++j) ra[j] = (aok[j] && kok) ? Ap[aoff[j]] : AE{0, 0};
 #pragma unroll
-    for (int j = 0; j < NBJ; ++j) rb[j] = (bok[j] && kok) ? Bp[boff[j]] : mkc(0, 0);
+    for (int j = 0; j < NBJ; ++j) rb[j] = (bok[j] && kok) ? cscale(Bp[boff[j]], sg.w) : mkc(0, 0);
   };
 
   const int wave = tid >> 6, lane = tid & 63;
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(256, 2) void k_cgemm_b3(GemmShape sh, const GemmTas
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       ra[j] = (aok[j] && kok) ? Ap[aoff[j]] : float2{0, 0};
-      cplx bv = (bok[j] && kok) ? Bp[boff[j]] : mkc(0, 0);
+      cplx bv = (bok[j] && kok) ? cscale(Bp[boff[j]], sg.w) : mkc(0, 0);
       rb[j] = float2{(float)bv.x, (float)bv.y};
     }
   };
@@ -430,18 +430,40 @@ static void build_plans(ccgf_ctx *c, SigmaPlan &P) {
     g.shape.bn = two(no, n, (long long)nv * nv);
     g.shape.cm = one(1);
     g.shape.cn = two(no, n, (long long)nv * nv);
-    g.shape.alpha_re = 0.5;
+    g.shape.alpha_re = 1.0;
     g.shape.alpha_im = 0;
     g.shape.accumulate = 0;
+    // W and r are antisymmetric in (c,kc) <-> (d,kd), so segments kc and kd = ka + kb - kc
+    // contribute alike: one of each pair at weight 1 (a self-paired segment at 1/2).  The
+    // output blocks (ki, ka) and (ki, kb) are negative transposes of each other: only
+    // ka <= kb is computed, the other block is filled afterwards.
     T4 W{nullptr, nk, nv, nv, nv, nv};
+    std::vector<long long> fill;
     for (int ki = 0; ki < nk; ++ki)
       for (int ka = 0; ka < nk; ++ka) {
         int kb = host_c3(c, K, ki, ka);
-        GemmTask t{nv + (ki * nk + ka) * b2, (int)g.segs.size(), nk};
-        for (int kc = 0; kc < nk; ++kc)
-          g.segs.push_back(GemmSeg{(long long)W.blk(ka, kb, kc), nv + (ki * nk + kc) * b2});
+        if (ka > kb) {
+          fill.push_back(nv + (ki * nk + ka) * b2);
+          fill.push_back(nv + (ki * nk + kb) * b2);
+          continue;
+        }
+        GemmTask t{nv + (ki * nk + ka) * b2, (int)g.segs.size(), 0};
+        for (int kc = 0; kc < nk; ++kc) {
+          const int kd = host_c3(c, ka, kb, kc);
+          if (kc > kd) continue;
+          g.segs.push_back(GemmSeg{(long long)W.blk(ka, kb, kc), nv + (ki * nk + kc) * b2, kc == kd ? 0.5 : 1.0});
+          ++t.nseg;
+        }
         g.tasks.push_back(t);
       }
+    P.nfill = (int)fill.size() / 2;
+    if (P.nfill > 0) {
+      std::vector<long long> &h = P.fill_h;
+      h.resize(2 * P.nfill);
+      for (int q = 0; q < P.nfill; ++q) h[q] = fill[2 * q], h[P.nfill + q] = fill[2 * q + 1];
+      P.d_fill = (long long *)dev_alloc(c, sizeof(long long) * h.size());
+      if (P.d_fill) hipMemcpy(P.d_fill, h.data(), sizeof(long long) * h.size(), hipMemcpyHostToDevice);
+    }
     // P(ab) (W_lbdi r_l^ad + F_bd r_i^ad) without the antisymmetriser: X(b,i ; a,v) over segments kl
     // (the operand is W_ovvo with F_vv folded into its blocks kl = ki, l = i)
     GemmPlan &h = P.g_ovvo;
@@ -711,6 +733,20 @@ __global__ __launch_bounds__(256) void k_r1_finish(int ea, int nk, int no, int n
   }
 }
 
+// EA blocks of the W_abcd product left to antisymmetry: y[dst](i,a,b) = -y[src](i,b,a)
+__global__ void k_vvvv_fill(cplx *__restrict__ y, long long n, int nvec, int nv, long long b2,
+                            const long long *__restrict__ dst, const long long *__restrict__ src, int nfill) {
+  const int f = blockIdx.y;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= b2) return;
+  const int b = (int)(e % nv), a = (int)((e / nv) % nv), i = (int)(e / ((long long)nv * nv));
+  const long long t = ((long long)i * nv + b) * nv + a;
+  for (int v = blockIdx.z; v < nvec; v += gridDim.z) {
+    cplx x = y[(size_t)v * n + src[f] + t];
+    y[(size_t)v * n + dst[f] + e] = mkc(-x.x, -x.y);
+  }
+}
+
 // element-wise EA 2p1h terms: one thread per sigma2 element, vectors over grid y
 __global__ __launch_bounds__(256) void k_ea_local(int nk, int no, int nv, int K, int nvec, long long n,
                                                   const int *__restrict__ kc3, const cplx *__restrict__ x,
@@ -861,6 +897,11 @@ static int sigma_enqueue(ccgf_ctx *c, SigmaPlan *P, int part, int K, int nvec, c
     const void *Wovvo = prec ? (const void *)c->WvoPea32 : (const void *)c->WvoPea;
     int rc = tuned_launch(c, 0, P->g_big, Wbig, x, y, s, prec);
     if (ts) hipEventRecord(ts->e[3], s);
+    if (P->nfill > 0) {
+      const long long b2 = (long long)no * nv * nv;
+      hipLaunchKernelGGL(k_vvvv_fill, dim3((unsigned)((b2 + 255) / 256), P->nfill, std::min(nvec, 64)), dim3(256), 0,
+                         s, y, n, nvec, nv, b2, P->d_fill, P->d_fill + P->nfill, P->nfill);
+    }
     if (!rc) rc = tuned_launch(c, 1, P->g_ovvo, Wovvo, x, c->sig_tmp, s, prec);
     if (!rc) rc = tuned_launch(c, 4, P->g_r1, c->Wvvvo, x, y, s, 0);
     if (!rc) rc = tuned_launch(c, 6, P->g_red1, c->Wvovv, x, c->sig_part, s, 0);
@@ -957,7 +998,8 @@ int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y, 
     P->nvec = nvec;
     P->n = n;
     build_plans(c, *P);
-    if (!P->g_big.d_tasks || !P->g_ovvo.d_tasks || !P->g_r1.d_tasks || !P->g_red1.d_tasks || !P->g_red2.d_tasks)
+    if (!P->g_big.d_tasks || !P->g_ovvo.d_tasks || !P->g_r1.d_tasks || !P->g_red1.d_tasks || !P->g_red2.d_tasks ||
+        (P->nfill > 0 && !P->d_fill))
       return CCGF_ENOMEM;
     const size_t nk3 = (size_t)c->nk * c->nk * c->nk;
     const size_t vb = (size_t)nvec * n;
@@ -976,6 +1018,8 @@ int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y, 
            plan_in_bounds(P->g_r1, nk3 * c->no * c->nv * c->no * c->no, vb, vb) &&
            plan_in_bounds(P->g_red1, nk3 * c->no * c->no * c->no * c->nv, vb, pe) &&
            plan_in_bounds(P->g_red2, oovv, vb, pe);
+    for (long long f : P->fill_h)  // blocks of sigma2 (no x nv x nv) inside one vector
+      ok = ok && f >= c->nv && f + (long long)c->no * c->nv * c->nv <= P->n;
     if (!ok) {
       c->plans.pop_back();
       return set_err(c, CCGF_EINVAL, "internal: sigma GEMM plan exceeds its buffers");

@@ -85,10 +85,14 @@ struct GemmShape {
   IdxMap cm, cn;  // C[m][n]
   double alpha_re, alpha_im;
   int accumulate;
+  // optional index tables (device): row m stands for mtab[m] in am and cm, k for ktab[k]
+  // in ak and bk (the strict upper triangle of an antisymmetric index pair)
+  const int *mtab = nullptr, *ktab = nullptr;
 };
 
 struct GemmPlan {
   GemmShape shape;
+  int m_ext = 0, k_ext = 0;     // index ranges reached through mtab / ktab (0: M / K)
   int tn[3] = {0, 0, 0};        // N tile width picked by the autotuner per precision (0: not yet)
   int trials[3] = {0, 0, 0};    // timed trial launches so far
   float tms[3][2] = {};         // their times (64-wide, 32-wide)
@@ -103,12 +107,16 @@ struct SigmaPlan {  // per (part, K, batch layout)
   int part, K, nvec;
   long long n;
   GemmPlan g_big;   // EA: W_vvvv term; IP: W_oooo term (writes sigma2)
+  GemmPlan g_bigt;  // EA: W_vvvv term of blocks ka = kb, segments kc = kd (both pairs a<b, c<d)
+  GemmPlan g_bigd;  // EA: W_vvvv term of blocks ka = kb, segments kc < kd (pairs a<b)
+  int *d_tri = nullptr;  // pair table p -> a * nv + b, a < b
   GemmPlan g_ovvo;  // W_ovvo term into the scratch vector
   GemmPlan g_r1;    // EA: W_abei r^e; IP: -W_maij r_m  (accumulates into sigma2)
   GemmPlan g_red1;  // split-K partial sums of the 1p / 1h rows of sigma (EA W_alcd, IP W_mnie)
   GemmPlan g_red2;  // split-K partial sums of the three-body intermediate (<kl||cd> r / <mn||ef> r)
   // EA: output blocks of the W_abcd product left to antisymmetry, sigma[ki][ka](i,a,b) =
-  // -sigma[ki][kb](i,b,a): offsets of the destination and source blocks in a vector
+  // -sigma[ki][kb](i,b,a): offsets of the destination and source blocks in a vector (equal
+  // offsets: the rows a >= b of a block ka = kb)
   int nfill = 0;
   long long *d_fill = nullptr;  // [2][nfill]
   std::vector<long long> fill_h;  // host copy, checked against the vector size

@@ -56,7 +56,8 @@ struct Mf<float> {
 // C[m][n] = alpha * sum_seg sum_k A[m][k] B[k][n] (+ C), complex, on MFMA.
 // TAG only separates the uses in kernel traces (0: EA W_abcd, 1: EA W_lbdi,
 // 2: IP W_mnij, 3: IP W_maei, 4: EA W_abei r^e, 5: IP W_maij r_m, 6: EA 1p-row
-// reductions W_alcd r, <kl||cd> r, 7: IP 1h-row reductions W_mnie r, <mn||ef> r).
+// reductions W_alcd r, <kl||cd> r, 7: IP 1h-row reductions W_mnie r, <mn||ef> r,
+// 8 and 9: EA W_abcd on the blocks ka = kb, pairs kc = kd and kc < kd).
 // TNT is the tile width in N (64, or 32 for narrow batches); the four waves of a
 // block own 32x32 (TNT = 64) or 16x32 (TNT = 32) output sub-tiles.
 template <int TAG, typename R, int TNT>
@@ -91,7 +92,7 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
   for (int j = 0; j < 4; ++j) {
     int m = tm * TM + rt + 16 * j;
     aok[j] = m < sh.M;
-    aoff[j] = aok[j] ? imap(sh.am, m) : 0;
+    aoff[j] = aok[j] ? imap(sh.am, sh.mtab ? sh.mtab[m] : m) : 0;
   }
 #pragma unroll
   for (int j = 0; j < NBJ; ++j) {
@@ -121,6 +122,7 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
     int k = (step - s * ksteps) * TK + kt;
     GemmSeg sg = segs[task.seg_begin + s];
     const bool kok = k < sh.K;
+    if (kok && sh.ktab) k = sh.ktab[k];
     const AE *Ap = A + sg.a_off + (kok ? imap(sh.ak, k) : 0);
     const cplx *Bp = B + sg.b_off + (kok ? imap(sh.bk, k) : 0);
 #pragma unroll
@@ -186,7 +188,7 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
         int col = cbase + b * 16 + lr;
         int m = tm * TM + row, n = tn * TNT + col;
         if (m < sh.M && n < sh.N) {
-          long long off = task.c_off + imap(sh.cm, m) + imap(sh.cn, n);
+          long long off = task.c_off + imap(sh.cm, sh.mtab ? sh.mtab[m] : m) + imap(sh.cn, n);
           double p1 = P1[a][b][v], p2 = P2[a][b][v];
           double re = p1 - p2, im = (double)P3[a][b][v] - p1 - p2;
           cplx val = mkc(sh.alpha_re * re - sh.alpha_im * im, sh.alpha_re * im + sh.alpha_im * re);
@@ -248,7 +250,7 @@ __global__ __launch_bounds__(256, 2) void k_cgemm_b3(GemmShape sh, const GemmTas
   for (int j = 0; j < 8; ++j) {
     int m = tm * TM + rt + 8 * j;
     aok[j] = m < sh.M;
-    aoff[j] = aok[j] ? imap(sh.am, m) : 0;
+    aoff[j] = aok[j] ? imap(sh.am, sh.mtab ? sh.mtab[m] : m) : 0;
     int n = tn * 64 + rt + 8 * j;
     bok[j] = n < sh.N;
     boff[j] = bok[j] ? imap(sh.bn, n) : 0;
@@ -270,6 +272,7 @@ __global__ __launch_bounds__(256, 2) void k_cgemm_b3(GemmShape sh, const GemmTas
     int k = (step - s * ksteps) * TKB + kt;
     GemmSeg sg = segs[task.seg_begin + s];
     const bool kok = k < sh.K;
+    if (kok && sh.ktab) k = sh.ktab[k];
     const float2 *Ap = A + sg.a_off + (kok ? imap(sh.ak, k) : 0);
     const cplx *Bp = B + sg.b_off + (kok ? imap(sh.bk, k) : 0);
 #pragma unroll
@@ -333,7 +336,7 @@ __global__ __launch_bounds__(256, 2) void k_cgemm_b3(GemmShape sh, const GemmTas
         int col = cbase + b * 16 + lr;
         int m = tm * TM + row, n = tn * 64 + col;
         if (m < sh.M && n < sh.N) {
-          long long off = task.c_off + imap(sh.cm, m) + imap(sh.cn, n);
+          long long off = task.c_off + imap(sh.cm, sh.mtab ? sh.mtab[m] : m) + imap(sh.cn, n);
           double p1 = P1[a][b][v], p2 = P2[a][b][v];
           double re = p1 - p2, im = (double)P3[a][b][v] - p1 - p2;
           cplx val = mkc(sh.alpha_re * re - sh.alpha_im * im, sh.alpha_re * im + sh.alpha_im * re);
@@ -380,9 +383,9 @@ void gemm_launch(int tag, const GemmPlan &plan, const void *A, const cplx *B, cp
     else if (prec) launch_w<T, float>(plan, A, B, C, s, tn);                                 \
     else launch_w<T, double>(plan, A, B, C, s, tn);                                          \
     break;
-  if (prec == 2 && tag > 3) prec = 0;  // only the four big products have FP32 operand copies
+  if (prec == 2 && tag > 3 && tag < 8) prec = 0;  // only the big products have FP32 operand copies
   switch (tag) {
-    CASE(0) CASE(1) CASE(2) CASE(3) CASE(4)
+    CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(8) CASE(9)
     case 6:
       launch_w<6, double>(plan, A, B, C, s, tn);
       break;
@@ -436,18 +439,46 @@ static void build_plans(ccgf_ctx *c, SigmaPlan &P) {
     // W and r are antisymmetric in (c,kc) <-> (d,kd), so segments kc and kd = ka + kb - kc
     // contribute alike: one of each pair at weight 1 (a self-paired segment at 1/2).  The
     // output blocks (ki, ka) and (ki, kb) are negative transposes of each other: only
-    // ka <= kb is computed, the other block is filled afterwards.
+    // ka <= kb is computed, the other block is filled afterwards.  A block ka = kb is itself
+    // antisymmetric in (a, b): its rows a < b are computed (g_bigt, g_bigd) and the rest filled,
+    // and its self-paired segments kc = kd (there is always kc = ka) run over c < d only.
     T4 W{nullptr, nk, nv, nv, nv, nv};
     std::vector<long long> fill;
+    GemmPlan &gt = P.g_bigt, &gd = P.g_bigd;
+    const int np = nv * (nv - 1) / 2;
+    gt.shape = g.shape;
+    gt.shape.M = np;
+    gt.shape.K = np;
+    gt.m_ext = gt.k_ext = nv * nv;
+    gd.shape = g.shape;
+    gd.shape.M = np;
+    gd.shape.accumulate = 1;  // after g_bigt, which writes every block ka = kb
+    gd.m_ext = nv * nv;
     for (int ki = 0; ki < nk; ++ki)
       for (int ka = 0; ka < nk; ++ka) {
         int kb = host_c3(c, K, ki, ka);
+        const long long cblk = nv + (ki * nk + ka) * b2;
         if (ka > kb) {
-          fill.push_back(nv + (ki * nk + ka) * b2);
+          fill.push_back(cblk);
           fill.push_back(nv + (ki * nk + kb) * b2);
           continue;
         }
-        GemmTask t{nv + (ki * nk + ka) * b2, (int)g.segs.size(), 0};
+        if (ka == kb) {
+          fill.push_back(cblk);
+          fill.push_back(cblk);
+          GemmTask tt{cblk, (int)gt.segs.size(), 0}, td{cblk, (int)gd.segs.size(), 0};
+          for (int kc = 0; kc < nk; ++kc) {
+            const int kd = host_c3(c, ka, kb, kc);
+            if (kc > kd) continue;
+            GemmSeg sg{(long long)W.blk(ka, kb, kc), nv + (ki * nk + kc) * b2, 1.0};
+            if (kc == kd) gt.segs.push_back(sg), ++tt.nseg;
+            else gd.segs.push_back(sg), ++td.nseg;
+          }
+          gt.tasks.push_back(tt);
+          if (td.nseg) gd.tasks.push_back(td);
+          continue;
+        }
+        GemmTask t{cblk, (int)g.segs.size(), 0};
         for (int kc = 0; kc < nk; ++kc) {
           const int kd = host_c3(c, ka, kb, kc);
           if (kc > kd) continue;
@@ -456,6 +487,20 @@ static void build_plans(ccgf_ctx *c, SigmaPlan &P) {
         }
         g.tasks.push_back(t);
       }
+    // heaviest tasks first: the last blocks of the grid then finish together
+    std::stable_sort(g.tasks.begin(), g.tasks.end(),
+                     [](const GemmTask &x, const GemmTask &y) { return x.nseg > y.nseg; });
+    if (np > 0) {
+      std::vector<int> tri;
+      for (int a = 0; a < nv; ++a)
+        for (int b = a + 1; b < nv; ++b) tri.push_back(a * nv + b);
+      P.d_tri = (int *)dev_alloc(c, sizeof(int) * tri.size());
+      if (P.d_tri) hipMemcpy(P.d_tri, tri.data(), sizeof(int) * tri.size(), hipMemcpyHostToDevice);
+      gt.shape.mtab = gt.shape.ktab = gd.shape.mtab = P.d_tri;
+    } else {
+      gt.tasks.clear();
+      gd.tasks.clear();
+    }
     P.nfill = (int)fill.size() / 2;
     if (P.nfill > 0) {
       std::vector<long long> &h = P.fill_h;
@@ -652,6 +697,8 @@ static void build_plans(ccgf_ctx *c, SigmaPlan &P) {
     }
   }
   plan_upload(c, P.g_big);
+  plan_upload(c, P.g_bigt);
+  plan_upload(c, P.g_bigd);
   plan_upload(c, P.g_ovvo);
   plan_upload(c, P.g_r1);
   plan_upload(c, P.g_red1);
@@ -670,9 +717,10 @@ static long long map_max(const IdxMap &m, int len) {
 // Host-side proof that every access of a plan stays inside its buffers.
 static bool plan_in_bounds(const GemmPlan &p, size_t a_elems, size_t b_elems, size_t c_elems) {
   const GemmShape &s = p.shape;
-  long long am = map_max(s.am, s.M) + map_max(s.ak, s.K);
-  long long bm = map_max(s.bk, s.K) + map_max(s.bn, s.N);
-  long long cm = map_max(s.cm, s.M) + map_max(s.cn, s.N);
+  const int me = s.mtab ? p.m_ext : s.M, ke = s.ktab ? p.k_ext : s.K;  // tables hold indices below the ext
+  long long am = map_max(s.am, me) + map_max(s.ak, ke);
+  long long bm = map_max(s.bk, ke) + map_max(s.bn, s.N);
+  long long cm = map_max(s.cm, me) + map_max(s.cn, s.N);
   for (const GemmTask &t : p.tasks) {
     if (t.c_off < 0 || (size_t)(t.c_off + cm) >= c_elems) return false;
     if (t.seg_begin < 0 || (size_t)(t.seg_begin + t.nseg) > p.segs.size()) return false;
@@ -733,7 +781,8 @@ __global__ __launch_bounds__(256) void k_r1_finish(int ea, int nk, int no, int n
   }
 }
 
-// EA blocks of the W_abcd product left to antisymmetry: y[dst](i,a,b) = -y[src](i,b,a)
+// EA blocks of the W_abcd product left to antisymmetry: y[dst](i,a,b) = -y[src](i,b,a);
+// for dst = src only the rows a >= b are written (a = b: zero)
 __global__ void k_vvvv_fill(cplx *__restrict__ y, long long n, int nvec, int nv, long long b2,
                             const long long *__restrict__ dst, const long long *__restrict__ src, int nfill) {
   const int f = blockIdx.y;
@@ -741,8 +790,10 @@ __global__ void k_vvvv_fill(cplx *__restrict__ y, long long n, int nvec, int nv,
   if (e >= b2) return;
   const int b = (int)(e % nv), a = (int)((e / nv) % nv), i = (int)(e / ((long long)nv * nv));
   const long long t = ((long long)i * nv + b) * nv + a;
+  const bool self = dst[f] == src[f];  // a block ka = kb: rows a < b are computed, a = b vanish
+  if (self && a < b) return;
   for (int v = blockIdx.z; v < nvec; v += gridDim.z) {
-    cplx x = y[(size_t)v * n + src[f] + t];
+    cplx x = a == b && self ? mkc(0, 0) : y[(size_t)v * n + src[f] + t];
     y[(size_t)v * n + dst[f] + e] = mkc(-x.x, -x.y);
   }
 }
@@ -897,6 +948,8 @@ static int sigma_enqueue(ccgf_ctx *c, SigmaPlan *P, int part, int K, int nvec, c
     const void *Wovvo = prec ? (const void *)c->WvoPea32 : (const void *)c->WvoPea;
     int rc = tuned_launch(c, 0, P->g_big, Wbig, x, y, s, prec);
     if (ts) hipEventRecord(ts->e[3], s);
+    if (!rc && P->g_bigt.ntask) rc = tuned_launch(c, 8, P->g_bigt, Wbig, x, y, s, prec);
+    if (!rc && P->g_bigd.ntask) rc = tuned_launch(c, 9, P->g_bigd, Wbig, x, y, s, prec);
     if (P->nfill > 0) {
       const long long b2 = (long long)no * nv * nv;
       hipLaunchKernelGGL(k_vvvv_fill, dim3((unsigned)((b2 + 255) / 256), P->nfill, std::min(nvec, 64)), dim3(256), 0,
@@ -998,8 +1051,9 @@ int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y, 
     P->nvec = nvec;
     P->n = n;
     build_plans(c, *P);
-    if (!P->g_big.d_tasks || !P->g_ovvo.d_tasks || !P->g_r1.d_tasks || !P->g_red1.d_tasks || !P->g_red2.d_tasks ||
-        (P->nfill > 0 && !P->d_fill))
+    if (!P->g_big.d_tasks || !P->g_bigt.d_tasks || !P->g_bigd.d_tasks || !P->g_ovvo.d_tasks || !P->g_r1.d_tasks ||
+        !P->g_red1.d_tasks || !P->g_red2.d_tasks || (P->nfill > 0 && !P->d_fill) ||
+        (P->g_bigt.ntask > 0 && !P->d_tri))
       return CCGF_ENOMEM;
     const size_t nk3 = (size_t)c->nk * c->nk * c->nk;
     const size_t vb = (size_t)nvec * n;
@@ -1008,6 +1062,8 @@ int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y, 
     bool ok;
     if (part == CCGF_PART_EA)
       ok = plan_in_bounds(P->g_big, nk3 * c->nv * c->nv * c->nv * c->nv, vb, vb) &&
+           plan_in_bounds(P->g_bigt, nk3 * c->nv * c->nv * c->nv * c->nv, vb, vb) &&
+           plan_in_bounds(P->g_bigd, nk3 * c->nv * c->nv * c->nv * c->nv, vb, vb) &&
            plan_in_bounds(P->g_ovvo, nk3 * c->nv * c->no * c->no * c->nv, vb, vb) &&
            plan_in_bounds(P->g_r1, nk3 * c->nv * c->nv * c->nv * c->no, vb, vb) &&
            plan_in_bounds(P->g_red1, nk3 * c->nv * c->no * c->nv * c->nv, vb, pe) &&

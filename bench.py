@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--restart", type=int, default=150)
     ap.add_argument("--maxiter", type=int, default=12000)
     ap.add_argument("--precond-eta", type=float, default=0.2)
+    ap.add_argument("--seed-m", type=int, default=128,
+                    help="shared-Krylov seed steps per orbital before the solves (0: start from zero)")
     ap.add_argument("--no-check", action="store_true", help="skip the reference solve (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe", choices=["sigma", "copy"], default=None,
@@ -162,7 +164,7 @@ def main():
     stride = len(omega) // args.nw
     wsel = omega[::stride][:args.nw]
     opts = dict(tol=args.tol, restart_m=args.restart, maxiter=args.maxiter, max_batch=args.batch,
-                precond_eta=args.precond_eta)
+                precond_eta=args.precond_eta, seed_m=args.seed_m)
     if args.probe == "sigma":
         ctx = Context(sysm, precision=args.probe_precision, **opts)
         for part in ("ea", "ip"):
@@ -247,7 +249,7 @@ def main():
     if not args.no_check:
         # tight plain-FP64 solve of every `check_every`-th frequency of the step, all orbitals
         sub = slice(None, None, args.check_every)
-        ctx = Context(sysm, **dict(opts, tol=args.ref_tol, maxiter=3 * args.maxiter))
+        ctx = Context(sysm, **dict(opts, tol=args.ref_tol, maxiter=3 * args.maxiter, seed_m=0))
         _, _, Gm, sti = ctx.solve([0], orbs, wsel[sub], eta, parts="ip", allow_noconv=True)
         print(f"reference IP: {sti['seconds']:.1f} s", file=sys.stderr, flush=True)
         _, Gp, _, ste = ctx.solve([0], orbs, wsel[sub], eta, parts="ea", allow_noconv=True)

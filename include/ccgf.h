@@ -119,6 +119,15 @@ typedef struct {
   int graphs;            /* 0: once a sigma plan's GEMM widths are tuned, capture its launch
                             sequence (per operand pair and precision, up to 8) into a HIP graph
                             and replay it; -1: launch eagerly.  Timed runs launch eagerly. */
+  int seed_m;            /* 0: every solve starts from x0 = 0.  > 0 (up to 2000): before the
+                            solves of a (part, K), seed_m Arnoldi steps of sigma itself from
+                            each orbital's b (all orbitals of the call batched together); the
+                            Krylov space of sigma from b is that of every shifted operator
+                            (w -/+ i eta) -/+ sigma, so each (orbital, w) takes the GMRES
+                            minimiser over it as its starting guess where that leaves less
+                            than 1e-4 ||b|| of residual (elsewhere x0 = 0).  Needs (seed_m + 1) x
+                            norb vectors of device memory; without it the solves start from 0.
+                            Ignored while a trained guess network is enabled. */
 } ccgf_options;
 
 typedef struct {
@@ -137,8 +146,9 @@ typedef struct {
   long long sigma_launches;  /* sigma products (each over a batch of vectors) */
   long long n_steps;         /* batched Arnoldi steps (one sigma product over the active batch each) */
   long long n_reorth;        /* right-hand-side steps that needed the second Gram-Schmidt pass */
-  long long n_guess;         /* solves started from the trained network's guess */
-  long long n_guess_rejected; /* guesses discarded because ||b - A x0|| >= ||b|| (started from 0) */
+  long long n_guess;         /* solves started from a guess (trained network or Krylov seed) */
+  long long n_guess_rejected; /* guesses discarded, started from 0 instead: ||b - A x0|| was not
+                                 below accept ||b|| (network) or 1e-4 ||b|| (Krylov seed) */
 } ccgf_stats;
 
 /* Validates the system (shapes, t2 antisymmetry, factor Hermiticity, each to

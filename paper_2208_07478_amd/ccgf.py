@@ -40,7 +40,8 @@ class Options(ctypes.Structure):
                 ("tol", ctypes.c_double), ("max_batch", ctypes.c_int), ("hip_stream", ctypes.c_void_p),
                 ("timing", ctypes.c_int), ("precond_eta", ctypes.c_double), ("recycle_k", ctypes.c_int),
                 ("reorth_ratio", ctypes.c_double), ("autotune", ctypes.c_int),
-                ("autotune_cache", ctypes.c_char_p), ("restart_tail", ctypes.c_int), ("graphs", ctypes.c_int)]
+                ("autotune_cache", ctypes.c_char_p), ("restart_tail", ctypes.c_int), ("graphs", ctypes.c_int),
+                ("seed_m", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -141,7 +142,8 @@ class Context:
 
     def __init__(self, system, *, tol=1e-10, restart_m=30, maxiter=2000, max_batch=64, stream=None,
                  timing=False, foo=None, fvv=None, precond_eta=0.0, recycle_k=0, precision="f64",
-                 reorth_ratio=0.0, autotune=True, autotune_cache=None, graphs=True, restart_tail=0):
+                 reorth_ratio=0.0, autotune=True, autotune_cache=None, graphs=True, restart_tail=0,
+                 seed_m=0):
         lib = load()
         import torch  # device memory and streams only
         self._torch = torch
@@ -170,7 +172,7 @@ class Context:
                       ctypes.c_void_p(stream.cuda_stream), 1 if timing else 0, float(precond_eta),
                       int(recycle_k), float(reorth_ratio), 0 if autotune else -1,
                       None if autotune_cache is None else str(autotune_cache).encode(), int(restart_tail),
-                      0 if graphs else -1)
+                      0 if graphs else -1, int(seed_m))
         self._opt = opt
         h = ctypes.c_void_p()
         rc = lib.cc_gf_init(ctypes.byref(cs), ctypes.byref(opt), ctypes.byref(h))

@@ -113,7 +113,7 @@ extern "C" int cc_gf_init(const ccgf_system *s, const ccgf_options *opt, ccgf_ct
   if (o.restart_m < 1 || o.restart_m > 2000 || o.maxiter < 1 || o.tol < 0 || o.max_batch < 1 ||
       o.recycle_k < 0 || o.recycle_k > 200 || o.precond_eta < 0 || o.reorth_ratio < 0 || o.reorth_ratio > 1 ||
       o.autotune < -1 || o.autotune > 0 || o.graphs < -1 || o.graphs > 0 || o.restart_tail < 0 ||
-      o.restart_tail > 2000)
+      o.restart_tail > 2000 || o.seed_m < 0 || o.seed_m > 2000)
     return set_err(nullptr, CCGF_EINVAL, "options out of range");
 
   ccgf_ctx *c = new ccgf_ctx();
@@ -289,8 +289,18 @@ extern "C" int cc_gf_solve(ccgf_ctx *c, int nkq, const int *kidx, int norb, cons
             if (learn_guess(c, M, nrhs, rhs_orb.data(), orbs, rhs_w.data(), gs, &chat)) gp = &gs;
             break;
           }
+      cplx *seedQ = nullptr;
+      if (!gp && c->opt.seed_m > 0) {
+        int rs = seed_krylov(c, part, K, norb, Bv, nrhs, rhs_orb.data(), rhs_w.data(), eta, gs, &seedQ, &chat, S);
+        if (rs == CCGF_OK && seedQ) gp = &gs;
+        else if (rs == CCGF_EDEVICE) {
+          status = rs;
+          break;
+        }
+      }
       int rc = solve_batched(c, part, K, nrhs, rhs_orb.data(), rhs_w.data(), eta, Bv, Ev, res.data(), S, nullptr, gp);
       if (chat) hipFree(chat);
+      if (seedQ) hipFree(seedQ);
       if (rc != CCGF_OK) {
         if (rc == CCGF_ENOCONV) set_err(c, rc, "some shifted systems did not reach tol");
         status = (status == CCGF_OK || rc != CCGF_ENOCONV) ? rc : status;

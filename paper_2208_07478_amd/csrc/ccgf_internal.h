@@ -168,6 +168,7 @@ struct Guess {
   std::vector<int> qidx;        // per right-hand side, -1 for none
   int R = 0;
   double accept = 1.0;          // keep x0 only if ||b - A x0|| < accept ||b||
+  long long qs_i = 0, qs_q = 0; // strides of Q between columns and between q (0: n and R n)
 };
 void learn_features(const LearnModel &M, int b, double w, int jr, float *f);
 
@@ -243,6 +244,11 @@ void gemm_launch(int tag, const GemmPlan &plan, const void *A, const cplx *B, cp
 void plan_upload(ccgf_ctx *c, GemmPlan &p);
 
 // gmres.hip
+// Shared Krylov seed of the solves of one (part, K): Arnoldi of sigma from every orbital's b,
+// then the GMRES minimiser of each right-hand side's own shift over it (Guess with Q = the
+// bases, owned by *Q; chat owned by *chat).  On CCGF_ENOMEM nothing is seeded and both stay NULL.
+int seed_krylov(ccgf_ctx *c, int part, int K, int norb, const cplx *Bvecs, int nrhs, const int *rhs_orb,
+                const double *rhs_omega, double eta, Guess &g, cplx **Q, cplx **chat, ccgf_stats *st);
 int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb_slot, const double *rhs_omega,
                   double eta, const cplx *Bvecs, const cplx *Evecs, cplx *Gout, ccgf_stats *st,
                   cplx *Xout = nullptr, const Guess *guess = nullptr);

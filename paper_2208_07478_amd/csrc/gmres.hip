@@ -453,15 +453,15 @@ __global__ void k_copy_vecs(cplx *__restrict__ dst, const long long *__restrict_
   dst[doff[v] + x] = src[soff[v] + x];
 }
 
-// X[idx[y]] = sum_i Q[qoff[y] + i n] * ch[coff[y] + i]  (guess x0 = Q c_hat)
+// X[idx[y]] = sum_i Q[qoff[y] + i qs] * ch[coff[y] + i]  (guess x0 = Q c_hat)
 __global__ void k_expand(cplx *__restrict__ X, const cplx *__restrict__ Q, const long long *__restrict__ qoff,
                          const cplx *__restrict__ ch, const long long *__restrict__ coff, int R, long long n,
-                         const int *__restrict__ idx) {
+                         const int *__restrict__ idx, long long qs) {
   const int y = blockIdx.y, v = idx[y];
   long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= n) return;
   cplx acc = mkc(0, 0);
-  for (int i = 0; i < R; ++i) cfma(acc, ch[coff[y] + i], Q[qoff[y] + (long long)i * n + x]);
+  for (int i = 0; i < R; ++i) cfma(acc, ch[coff[y] + i], Q[qoff[y] + (long long)i * qs + x]);
   X[(size_t)v * n + x] = acc;
 }
 
@@ -766,7 +766,7 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
       for (int v : fresh) {
         const int q = guess->qidx[rhs_of[v]];
         if (q < 0 || hbnorm[v] == 0.0) continue;
-        go[gl.size()] = (long long)q * guess->R * n;
+        go[gl.size()] = (long long)q * (guess->qs_q ? guess->qs_q : guess->R * n);
         go[B + gl.size()] = (long long)rhs_of[v] * guess->R;
         gl.push_back(v);
       }
@@ -775,7 +775,7 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
         hipMemcpyAsync(goff, go.data(), sizeof(long long) * 2 * B, hipMemcpyHostToDevice, s);
         hipMemcpyAsync(aidx, gl.data(), sizeof(int) * ng, hipMemcpyHostToDevice, s);
         hipLaunchKernelGGL(k_expand, dim3(gx, ng), dim3(256), 0, s, X, guess->Q, goff, guess->chat, goff + B,
-                           guess->R, n, aidx);
+                           guess->R, n, aidx, guess->qs_i ? guess->qs_i : n);
         alist = gl;
         if (int rc = true_residual(B)) return rc;
         for (int v : gl) {
@@ -1015,6 +1015,201 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
   }
   wfree(W);
   return status;
+}
+
+// ------------------------------------------------------------------ shared Krylov seed
+// The Krylov space of sigma from b is also that of every shifted operator
+// shift I -/+ sigma, so one Arnoldi run per orbital serves all its frequencies:
+// with sigma Q_m = Q_{m+1} H (H of size (m+1) x m), (shift I + sM sigma) Q_m =
+// Q_{m+1} (shift I + sM H), and the GMRES iterate of each (orbital, w) over that
+// space is x0 = Q_m y with y minimising || beta e_1 - (shift I + sM H) y ||.
+
+// H[v][j + 1][j] = ||w_v|| after orthogonalisation (row-major, ldh = m) and the
+// scale 1 / ||w_v|| of the next basis vector; a right-hand side whose remainder is
+// negligible next to ||sigma v_j|| (the norm of H's column) has reached an
+// invariant space: its basis stops at j + 1 columns
+__global__ void k_seed_norm(int B, const cplx *__restrict__ htmp, int ldp, cplx *__restrict__ H, int m, int j,
+                            double *__restrict__ inv, int *__restrict__ act, int *__restrict__ mlen) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= B || !act[v]) return;
+  cplx *Hv = H + (size_t)v * (m + 1) * m;
+  const double h = sqrt(fmax(htmp[(size_t)v * ldp].x, 0.0));
+  double col2 = h * h;
+  for (int i = 0; i <= j; ++i) col2 += Hv[(size_t)i * m + j].x * Hv[(size_t)i * m + j].x + Hv[(size_t)i * m + j].y * Hv[(size_t)i * m + j].y;
+  Hv[(size_t)(j + 1) * m + j] = mkc(h, 0);
+  if (!(h > 1e-13 * sqrt(col2))) {
+    mlen[v] = j + 1;
+    act[v] = 0;
+    inv[v] = 0.0;
+  } else {
+    inv[v] = 1.0 / h;
+  }
+}
+
+// Per right-hand side r (one thread each): Givens QR of (shift_r I + sM H[orb_r])
+// restricted to the orbital's mlen columns, then y by back substitution into
+// chat[r][0 .. m) (zero beyond mlen, and all zero if the triangle is singular).
+// R (upper triangle, column j at Rw + j m), the rotations and g are per-r scratch.
+__global__ void k_seed_ls(int nrhs, int m, const cplx *__restrict__ H, const int *__restrict__ mlen,
+                          const int *__restrict__ orb, const cplx *__restrict__ shift, double sM,
+                          const double *__restrict__ beta, cplx *__restrict__ Rw, cplx *__restrict__ cs,
+                          cplx *__restrict__ sn, cplx *__restrict__ gv, cplx *__restrict__ chat) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  const int q = orb[r];
+  const int me = q >= 0 ? mlen[q] : 0;
+  cplx *y = chat + (size_t)r * m;
+  for (int i = 0; i < m; ++i) y[i] = mkc(0, 0);
+  if (me == 0) return;
+  const cplx *Hq = H + (size_t)q * (m + 1) * m;
+  cplx *Rr = Rw + (size_t)r * m * m, *c = cs + (size_t)r * m, *sv = sn + (size_t)r * m, *g = gv + (size_t)r * (m + 1);
+  const cplx sh = shift[r];
+  g[0] = mkc(beta[q], 0);
+  for (int j = 0; j < me; ++j) {
+    cplx *col = Rr + (size_t)j * m;
+    for (int i = 0; i <= j; ++i) col[i] = cscale(Hq[(size_t)i * m + j], sM);
+    col[j] = cadd(col[j], sh);
+    cplx sub = cscale(Hq[(size_t)(j + 1) * m + j], sM);
+    for (int i = 0; i < j; ++i) {  // earlier rotations on rows (i, i + 1)
+      const cplx a0 = col[i], a1 = col[i + 1];
+      col[i] = cadd(cmul(cconj(c[i]), a0), cmul(cconj(sv[i]), a1));
+      col[i + 1] = csub(cmul(c[i], a1), cmul(sv[i], a0));
+    }
+    const double rr = hypot(hypot(col[j].x, col[j].y), hypot(sub.x, sub.y));
+    if (rr == 0.0) return;  // singular: no guess
+    c[j] = cscale(col[j], 1.0 / rr);
+    sv[j] = cscale(sub, 1.0 / rr);
+    col[j] = mkc(rr, 0);
+    const cplx gj = g[j];
+    g[j] = cmul(cconj(c[j]), gj);
+    g[j + 1] = cscale(cmul(sv[j], gj), -1.0);
+  }
+  for (int i = me - 1; i >= 0; --i) {
+    cplx acc = g[i];
+    for (int k = i + 1; k < me; ++k) acc = csub(acc, cmul(Rr[(size_t)k * m + i], y[k]));
+    y[i] = cscale(acc, 1.0 / Rr[(size_t)i * m + i].x);  // the diagonal of R is real, > 0
+  }
+}
+
+int seed_krylov(ccgf_ctx *c, int part, int K, int norb, const cplx *Bvecs, int nrhs, const int *rhs_orb,
+                const double *rhs_omega, double eta, Guess &gs, cplx **Qout, cplx **chat_out, ccgf_stats *st) {
+  *Qout = nullptr;
+  *chat_out = nullptr;
+  const int m = c->opt.seed_m;
+  if (m <= 0 || norb <= 0 || nrhs <= 0) return CCGF_OK;
+  const long long n = vec_len(c, part);
+  const int n1 = part == CCGF_PART_IP ? c->no : c->nv;
+  const double sM = part == CCGF_PART_IP ? 1.0 : -1.0;
+  const double sE = part == CCGF_PART_IP ? -1.0 : 1.0;
+  const int B = norb;
+  const int nchunk = (int)((n + DOT_CHUNK - 1) / DOT_CHUNK);
+  const int ldp = m + 2;
+  const size_t vb = (size_t)B * n;
+  hipStream_t s = c->stream;
+  GmresWork W;
+  cplx *Q = nullptr, *chat = nullptr;
+  if (hipMalloc(&Q, sizeof(cplx) * vb * (m + 1)) != hipSuccess ||
+      hipMalloc(&chat, sizeof(cplx) * (size_t)nrhs * m) != hipSuccess) {
+    (void)hipGetLastError();
+    if (Q) hipFree(Q);
+    return CCGF_ENOMEM;
+  }
+  cplx *Z = (cplx *)walloc(W, sizeof(cplx) * vb);
+  cplx *Wv = (cplx *)walloc(W, sizeof(cplx) * vb);
+  cplx *H = (cplx *)walloc(W, sizeof(cplx) * B * (size_t)(m + 1) * m);
+  cplx *htmp = (cplx *)walloc(W, sizeof(cplx) * B * ldp);
+  cplx *partial = (cplx *)walloc(W, sizeof(cplx) * (size_t)B * nchunk * ldp);
+  double *inv = (double *)walloc(W, sizeof(double) * B);
+  double *beta = (double *)walloc(W, sizeof(double) * B);
+  int *act = (int *)walloc(W, sizeof(int) * B);
+  int *mlen = (int *)walloc(W, sizeof(int) * B);
+  int *orb = (int *)walloc(W, sizeof(int) * nrhs);
+  long long *uoff = (long long *)walloc(W, sizeof(long long) * B);
+  cplx *shift = (cplx *)walloc(W, sizeof(cplx) * nrhs);
+  cplx *Rw = (cplx *)walloc(W, sizeof(cplx) * (size_t)nrhs * m * m);
+  cplx *cs = (cplx *)walloc(W, sizeof(cplx) * (size_t)nrhs * m);
+  cplx *sn = (cplx *)walloc(W, sizeof(cplx) * (size_t)nrhs * m);
+  cplx *gv = (cplx *)walloc(W, sizeof(cplx) * (size_t)nrhs * (m + 1));
+  auto fail = [&](int rc) {
+    wfree(W);
+    hipFree(Q);
+    hipFree(chat);
+    return rc;
+  };
+  if (W.failed) return fail(CCGF_ENOMEM);
+  const unsigned gx = (unsigned)((n + 255) / 256);
+  std::vector<long long> hoff(B);
+  for (int v = 0; v < B; ++v) hoff[v] = (long long)v * n;
+  hipMemcpyAsync(uoff, hoff.data(), sizeof(long long) * B, hipMemcpyHostToDevice, s);
+  hipMemsetAsync(Q, 0, sizeof(cplx) * vb * (m + 1), s);
+  hipMemsetAsync(H, 0, sizeof(cplx) * B * (size_t)(m + 1) * m, s);
+  // beta_q = ||b_q||, v_0 = b_q / beta_q
+  hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Bvecs, uoff, 0LL, 1, Bvecs, n, n1, 1,
+                     (const int *)nullptr, partial, nchunk, ldp, (const int *)nullptr);
+  hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, 1, (const int *)nullptr, htmp, ldp,
+                     (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
+  std::vector<cplx> hh((size_t)B * ldp);
+  hipMemcpyAsync(hh.data(), htmp, sizeof(cplx) * B * ldp, hipMemcpyDeviceToHost, s);
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(hip_check(c, hipGetLastError(), "seed start"));
+  std::vector<double> hb(B), hinv(B);
+  std::vector<int> hact(B), hml(B);
+  for (int v = 0; v < B; ++v) {
+    hb[v] = std::sqrt(std::max(hh[(size_t)v * ldp].x, 0.0));
+    hact[v] = hb[v] > 0.0;
+    hml[v] = hact[v] ? m : 0;
+    hinv[v] = hact[v] ? 1.0 / hb[v] : 0.0;
+  }
+  hipMemcpyAsync(beta, hb.data(), sizeof(double) * B, hipMemcpyHostToDevice, s);
+  hipMemcpyAsync(inv, hinv.data(), sizeof(double) * B, hipMemcpyHostToDevice, s);
+  hipMemcpyAsync(act, hact.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
+  hipMemcpyAsync(mlen, hml.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
+  hipLaunchKernelGGL(k_scale, dim3(gx, B), dim3(256), 0, s, Q, Bvecs, inv, n, (const int *)act);
+  for (int j = 0; j < m; ++j) {
+    // sigma of column j through fixed operands (one captured launch sequence serves every step)
+    hipMemcpyAsync(Z, Q + (size_t)j * vb, sizeof(cplx) * vb, hipMemcpyDeviceToDevice, s);
+    if (int rc = sigma_apply(c, part, K, B, Z, Wv, c->opt.precision)) return fail(rc);
+    if (st) st->n_sigma += B;
+    for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
+      hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Q, uoff, (long long)vb, j + 1, Wv, n, n1, 1,
+                         (const int *)act, partial, nchunk, ldp, (const int *)nullptr);
+      hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, j + 1, (const int *)act, htmp,
+                         ldp, H, m, (long long)(m + 1) * m, j, (cplx *)nullptr, (const int *)nullptr,
+                         (const int *)nullptr);
+      hipLaunchKernelGGL(k_sub_proj, dim3(gx, B), dim3(256), 0, s, Wv, Q, (long long)vb, n, j + 1, htmp, ldp,
+                         (const int *)act, (const int *)nullptr);
+    }
+    hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Wv, uoff, 0LL, 1, Wv, n, n1, 1, (const int *)act,
+                       partial, nchunk, ldp, (const int *)nullptr);
+    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, 1, (const int *)act, htmp, ldp,
+                       (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
+    hipLaunchKernelGGL(k_seed_norm, dim3((B + 63) / 64), dim3(64), 0, s, B, htmp, ldp, H, m, j, inv, act, mlen);
+    hipLaunchKernelGGL(k_scale, dim3(gx, B), dim3(256), 0, s, Q + (size_t)(j + 1) * vb, Wv, inv, n,
+                       (const int *)act);
+  }
+  std::vector<cplx> hsh(nrhs);
+  for (int r = 0; r < nrhs; ++r) hsh[r] = mkc(rhs_omega[r], sE * eta);
+  hipMemcpyAsync(shift, hsh.data(), sizeof(cplx) * nrhs, hipMemcpyHostToDevice, s);
+  hipMemcpyAsync(orb, rhs_orb, sizeof(int) * nrhs, hipMemcpyHostToDevice, s);
+  hipLaunchKernelGGL(k_seed_ls, dim3((nrhs + 63) / 64), dim3(64), 0, s, nrhs, m, H, mlen, orb, shift, sM, beta, Rw, cs,
+                     sn, gv, chat);
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(hip_check(c, hipGetLastError(), "seed"));
+  if (int rc = hip_check(c, hipGetLastError(), "seed")) return fail(rc);
+  wfree(W);
+  gs.Q = Q;
+  gs.chat = chat;
+  gs.R = m;
+  // only near-converged seeds are kept: where the seed leaves a sizeable residual it is made
+  // of the slowly converging (near-pole) directions, and restarted, preconditioned GMRES
+  // from it took more iterations than from zero in every case measured
+  gs.accept = 1e-4;
+  gs.qs_i = (long long)vb;
+  gs.qs_q = n;
+  gs.qidx.assign(rhs_orb, rhs_orb + nrhs);
+  for (int &q : gs.qidx)
+    if (q < 0 || q >= B || !hact[q]) q = -1;
+  *Qout = Q;
+  *chat_out = chat;
+  return CCGF_OK;
 }
 
 // Orthonormal basis of every group of ncol columns of S ([ngroup][ncol][n]), in

@@ -36,30 +36,13 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// block-wide sum of a complex value; result valid in thread 0
-__device__ inline cplx block_sum(cplx v, double *sh) {
-  double re = wave_sum(v.x), im = wave_sum(v.y);
-  int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  __syncthreads();
-  if (l == 0) {
-    sh[2 * w] = re;
-    sh[2 * w + 1] = im;
-  }
-  __syncthreads();
-  cplx r = mkc(0, 0);
-  if (threadIdx.x == 0) {
-    int nw = blockDim.x >> 6;
-    for (int q = 0; q < nw; ++q) {
-      r.x += sh[2 * q];
-      r.y += sh[2 * q + 1];
-    }
-  }
-  return r;
-}
-
 // partial[v][chunk][i] = sum_{x in chunk} wgt(x) * op(U_i[v][x]) * W[v][x],
 // U_i[v] = U + uoff[v] + i * su_i (op = conj if conjU), W[v] = W + v * n,
-// i < ni0 (+ nlist[v] when a per-slot count is given)
+// i < ni0 (+ nlist[v] when a per-slot count is given).  The chunk of W stays in
+// registers; the U_i are taken DOT_G at a time with all their loads in flight
+// before one block reduction for the group (conj(U) W is formed as conj(U conj(W))
+// so that the loop has no branch on conjU).
+#define DOT_G 4
 __global__ __launch_bounds__(256) void k_dots(const cplx *__restrict__ U, const long long *__restrict__ uoff,
                                               long long su_i, int ni0, const cplx *__restrict__ W, long long n,
                                               int n1, int conjU, const int *__restrict__ active,
@@ -68,28 +51,69 @@ __global__ __launch_bounds__(256) void k_dots(const cplx *__restrict__ U, const 
   const int v = blockIdx.y, ch = blockIdx.x;
   if (active && !active[v]) return;
   const int ni = nlist ? nlist[v] + ni0 : ni0;
-  __shared__ double sh[16];
-  const long long base = (long long)ch * DOT_CHUNK;
+  __shared__ double sh[2][4][2 * DOT_G];
+  const long long base = (long long)ch * DOT_CHUNK + threadIdx.x;
+  const bool full = (long long)(ch + 1) * DOT_CHUNK <= n;
   cplx wv[DOT_ITEMS];
-  long long xs[DOT_ITEMS];
+  const cplx *Wb = W + (size_t)v * n + base;
+  if (full) {
+#pragma unroll
+    for (int t = 0; t < DOT_ITEMS; ++t) wv[t] = Wb[256 * t];
+  } else {
+#pragma unroll
+    for (int t = 0; t < DOT_ITEMS; ++t) wv[t] = base + 256LL * t < n ? Wb[256 * t] : mkc(0, 0);
+  }
 #pragma unroll
   for (int t = 0; t < DOT_ITEMS; ++t) {
-    long long x = base + threadIdx.x + 256LL * t;
-    xs[t] = x;
-    wv[t] = x < n ? cscale(W[(size_t)v * n + x], wgt(x, n1)) : mkc(0, 0);
+    const double c = wgt(base + 256LL * t, n1);
+    wv[t] = mkc(c * wv[t].x, (conjU ? -c : c) * wv[t].y);
   }
   const cplx *Ub = U + uoff[v];
-  for (int i = 0; i < ni; ++i) {
-    const cplx *Ui = Ub + (size_t)i * su_i;
-    cplx acc = mkc(0, 0);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int par = 0;
+  for (int i0 = 0; i0 < ni; i0 += DOT_G, par ^= 1) {
+    cplx acc[DOT_G];
 #pragma unroll
-    for (int t = 0; t < DOT_ITEMS; ++t)
-      if (xs[t] < n) {
-        if (conjU) cfmac(acc, Ui[xs[t]], wv[t]);
-        else cfma(acc, Ui[xs[t]], wv[t]);
+    for (int g = 0; g < DOT_G; ++g) acc[g] = mkc(0, 0);
+    const int ng = min(DOT_G, ni - i0);
+    if (full && ng == DOT_G) {
+#pragma unroll
+      for (int g = 0; g < DOT_G; ++g) {
+        const cplx *Ug = Ub + (size_t)(i0 + g) * su_i + base;
+        cplx u[DOT_ITEMS];
+#pragma unroll
+        for (int t = 0; t < DOT_ITEMS; ++t) u[t] = Ug[256 * t];
+#pragma unroll
+        for (int t = 0; t < DOT_ITEMS; ++t) cfma(acc[g], u[t], wv[t]);
       }
-    cplx r = block_sum(acc, sh);
-    if (threadIdx.x == 0) partial[((size_t)v * nchunk + ch) * ldp + i] = r;
+    } else {
+      for (int t = 0; t < DOT_ITEMS; ++t) {
+        const long long x = base + 256LL * t;
+        if (x < n)
+          for (int g = 0; g < ng; ++g) cfma(acc[g], Ub[(size_t)(i0 + g) * su_i + x], wv[t]);
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < DOT_G; ++g) {
+      acc[g].x = wave_sum(acc[g].x);
+      acc[g].y = wave_sum(acc[g].y);
+    }
+    if (lane == 0)
+#pragma unroll
+      for (int g = 0; g < DOT_G; ++g) {
+        sh[par][wave][2 * g] = acc[g].x;
+        sh[par][wave][2 * g + 1] = acc[g].y;
+      }
+    __syncthreads();  // (the next group writes the other half of sh)
+    if (threadIdx.x < ng) {
+      const int g = threadIdx.x;
+      double re = 0, im = 0;
+      for (int q = 0; q < 4; ++q) {
+        re += sh[par][q][2 * g];
+        im += sh[par][q][2 * g + 1];
+      }
+      partial[((size_t)v * nchunk + ch) * ldp + i0 + g] = mkc(re, conjU ? -im : im);
+    }
   }
 }
 
@@ -127,8 +151,18 @@ __global__ __launch_bounds__(256) void k_sub_proj(cplx *__restrict__ W, const cp
   const int ni = nlist ? nlist[v] + ni0 : ni0;
   long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= n) return;
+  const cplx *Vx = V + (size_t)v * n + x;
+  const cplx *hv = h + (size_t)v * ldh;
   cplx acc = W[(size_t)v * n + x];
-  for (int i = 0; i < ni; ++i) acc = csub(acc, cmul(h[(size_t)v * ldh + i], V[(size_t)i * svi + (size_t)v * n + x]));
+  int i = 0;
+  for (; i + 8 <= ni; i += 8) {  // eight loads in flight per thread
+    cplx u[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) u[q] = Vx[(size_t)(i + q) * svi];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc = csub(acc, cmul(hv[i + q], u[q]));
+  }
+  for (; i < ni; ++i) acc = csub(acc, cmul(hv[i], Vx[(size_t)i * svi]));
   W[(size_t)v * n + x] = acc;
 }
 

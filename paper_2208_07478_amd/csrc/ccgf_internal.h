@@ -197,6 +197,8 @@ struct ccgf_ctx {
   size_t sig_tmp_elems = 0;
   cplx *sig_r1aux = nullptr;  // per-RHS 3-body contraction (nvec x max(no, nv))
   size_t sig_r1aux_elems = 0;
+  float2 *sig_x32 = nullptr;  // complex float copy of the vectors (reduced-precision GEMMs)
+  size_t sig_x32_elems = 0;
   cplx *sig_part = nullptr;  // split-range partial sums of the 1h / 1p rows
   size_t sig_part_elems = 0;
   std::vector<SigmaPlan> plans;
@@ -239,7 +241,8 @@ void timing_release(ccgf_ctx *c);
 // Read / write the autotuner's choices (one "key tn" line per GEMM shape).
 void tune_load(ccgf_ctx *c);
 void tune_save(const ccgf_ctx *c);
-void gemm_launch(int tag, const GemmPlan &plan, const void *A, const cplx *B, cplx *C, hipStream_t s, int prec,
+// B: complex double vectors for prec 0, their complex float copy for prec 1 and 2
+void gemm_launch(int tag, const GemmPlan &plan, const void *A, const void *B, cplx *C, hipStream_t s, int prec,
                  int tn);
 void plan_upload(ccgf_ctx *c, GemmPlan &p);
 

@@ -30,7 +30,7 @@ __device__ inline long long imap(const IdxMap &m, int x) {
 }
 
 // Real arithmetic of one GEMM variant: FP64 (A complex double) or FP32 (A complex
-// float, vectors rounded to float when staged, FP32 accumulation).  ROW gives the
+// float, vectors read from their complex float copy, FP32 accumulation).  ROW gives the
 // output row of MFMA item v in lane group g (l / 16), measured per instruction:
 // the FP64 16x16x4 spreads a lane's four items over rows g, g+4, g+8, g+12, the
 // FP32 16x16x4 gives them four consecutive rows 4g .. 4g+3.
@@ -64,7 +64,8 @@ template <int TAG, typename R, int TNT>
 __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *__restrict__ tasks,
                                                   const GemmSeg *__restrict__ segs,
                                                   const typename Mf<R>::AE *__restrict__ A,
-                                                  const cplx *__restrict__ B, cplx *__restrict__ C, int tilesM,
+                                                  const typename Mf<R>::AE *__restrict__ B, cplx *__restrict__ C,
+                                                  int tilesM,
                                                   int tilesN, int total) {
   typedef typename Mf<R>::V4 V4;
   typedef typename Mf<R>::AE AE;
@@ -115,8 +116,7 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
       P3[a][b] = (V4){0, 0, 0, 0};
     }
 
-  AE ra[4];
-  cplx rb[NBJ];
+  AE ra[4], rb[NBJ];
   auto load = [&](int step) {
     int s = step / ksteps;
     int k = (step - s * ksteps) * TK + kt;
@@ -124,11 +124,15 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
     const bool kok = k < sh.K;
     if (kok && sh.ktab) k = sh.ktab[k];
     const AE *Ap = A + sg.a_off + (kok ? imap(sh.ak, k) : 0);
-    const cplx *Bp = B + sg.b_off + (kok ? imap(sh.bk, k) : 0);
+    const AE *Bp = B + sg.b_off + (kok ? imap(sh.bk, k) : 0);
+    const R w = (R)sg.w;  // 1 or 1/2: exact in either precision
 #pragma unroll
     for (int j = 0; j < 4; ++j) ra[j] = (aok[j] && kok) ? Ap[aoff[j]] : AE{0, 0};
 #pragma unroll
-    for (int j = 0; j < NBJ; ++j) rb[j] = (bok[j] && kok) ? cscale(Bp[boff[j]], sg.w) : mkc(0, 0);
+    for (int j = 0; j < NBJ; ++j) {
+      const AE b = (bok[j] && kok) ? Bp[boff[j]] : AE{0, 0};
+      rb[j] = AE{b.x * w, b.y * w};
+    }
   };
 
   const int wave = tid >> 6, lane = tid & 63;
@@ -229,7 +233,7 @@ __device__ inline v4f mm3(const Split8 &a, const Split8 &b, v4f c) {
 template <int TAG>
 __global__ __launch_bounds__(256, 2) void k_cgemm_b3(GemmShape sh, const GemmTask *__restrict__ tasks,
                                                      const GemmSeg *__restrict__ segs, const float2 *__restrict__ A,
-                                                     const cplx *__restrict__ B, cplx *__restrict__ C, int tilesM,
+                                                     const float2 *__restrict__ B, cplx *__restrict__ C, int tilesM,
                                                      int tilesN, int total) {
   int bid = blockIdx.x;
   if ((total & 7) == 0) {
@@ -274,12 +278,13 @@ __global__ __launch_bounds__(256, 2) void k_cgemm_b3(GemmShape sh, const GemmTas
     const bool kok = k < sh.K;
     if (kok && sh.ktab) k = sh.ktab[k];
     const float2 *Ap = A + sg.a_off + (kok ? imap(sh.ak, k) : 0);
-    const cplx *Bp = B + sg.b_off + (kok ? imap(sh.bk, k) : 0);
+    const float2 *Bp = B + sg.b_off + (kok ? imap(sh.bk, k) : 0);
+    const float w = (float)sg.w;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       ra[j] = (aok[j] && kok) ? Ap[aoff[j]] : float2{0, 0};
-      cplx bv = (bok[j] && kok) ? cscale(Bp[boff[j]], sg.w) : mkc(0, 0);
-      rb[j] = float2{(float)bv.x, (float)bv.y};
+      const float2 b = (bok[j] && kok) ? Bp[boff[j]] : float2{0, 0};
+      rb[j] = float2{b.x * w, b.y * w};
     }
   };
   const int wave = tid >> 6, lane = tid & 63;
@@ -347,33 +352,34 @@ __global__ __launch_bounds__(256, 2) void k_cgemm_b3(GemmShape sh, const GemmTas
 }
 
 template <int TAG>
-static void launch_b3(const GemmPlan &plan, const void *A, const cplx *B, cplx *C, hipStream_t s) {
+static void launch_b3(const GemmPlan &plan, const void *A, const void *B, cplx *C, hipStream_t s) {
   const GemmShape &sh = plan.shape;
   const int tilesM = (sh.M + TM - 1) / TM, tilesN = (sh.N + 63) / 64;
   const long long total = (long long)plan.ntask * tilesM * tilesN;
   hipLaunchKernelGGL((k_cgemm_b3<TAG>), dim3((unsigned)total), dim3(256), 0, s, sh, plan.d_tasks, plan.d_segs,
-                     (const float2 *)A, B, C, tilesM, tilesN, (int)total);
+                     (const float2 *)A, (const float2 *)B, C, tilesM, tilesN, (int)total);
 }
 
 template <int TAG, typename R, int TNT>
-static void launch_t(const GemmPlan &plan, const void *A, const cplx *B, cplx *C, hipStream_t s) {
+static void launch_t(const GemmPlan &plan, const void *A, const void *B, cplx *C, hipStream_t s) {
   const GemmShape &sh = plan.shape;
   const int tilesM = (sh.M + TM - 1) / TM, tilesN = (sh.N + TNT - 1) / TNT;
   const long long total = (long long)plan.ntask * tilesM * tilesN;
   hipLaunchKernelGGL((k_cgemm<TAG, R, TNT>), dim3((unsigned)total), dim3(256), 0, s, sh, plan.d_tasks, plan.d_segs,
-                     (const typename Mf<R>::AE *)A, B, C, tilesM, tilesN, (int)total);
+                     (const typename Mf<R>::AE *)A, (const typename Mf<R>::AE *)B, C, tilesM, tilesN, (int)total);
 }
 
 template <int TAG, typename R>
-static void launch_w(const GemmPlan &plan, const void *A, const cplx *B, cplx *C, hipStream_t s, int tn) {
+static void launch_w(const GemmPlan &plan, const void *A, const void *B, cplx *C, hipStream_t s, int tn) {
   if (tn == 32) launch_t<TAG, R, 32>(plan, A, B, C, s);
   else launch_t<TAG, R, 64>(plan, A, B, C, s);
 }
 
-// prec 0: FP64 operands (A complex double); prec 1: FP32 (A complex float);
-// prec 2: BF16-split products from the FP32 operands (64-wide tiles only).
+// prec 0: FP64 operands (A and B complex double); prec 1: FP32 (A complex float,
+// B the vectors' complex float copy); prec 2: BF16-split products from the FP32
+// operands (64-wide tiles only).  Tags 4 to 7 run in FP64 only.
 // tn: N tile width (64 or 32), chosen per plan by the autotuner in sigma_apply.
-void gemm_launch(int tag, const GemmPlan &plan, const void *A, const cplx *B, cplx *C, hipStream_t s, int prec,
+void gemm_launch(int tag, const GemmPlan &plan, const void *A, const void *B, cplx *C, hipStream_t s, int prec,
                  int tn) {
   const GemmShape &sh = plan.shape;
   if (plan.ntask == 0 || sh.M == 0 || sh.N == 0) return;
@@ -383,9 +389,11 @@ void gemm_launch(int tag, const GemmPlan &plan, const void *A, const cplx *B, cp
     else if (prec) launch_w<T, float>(plan, A, B, C, s, tn);                                 \
     else launch_w<T, double>(plan, A, B, C, s, tn);                                          \
     break;
-  if (prec == 2 && tag > 3 && tag < 8) prec = 0;  // only the big products have FP32 operand copies
   switch (tag) {
-    CASE(0) CASE(1) CASE(2) CASE(3) CASE(4) CASE(8) CASE(9)
+    CASE(0) CASE(1) CASE(2) CASE(3) CASE(8) CASE(9)
+    case 4:
+      launch_w<4, double>(plan, A, B, C, s, tn);
+      break;
     case 6:
       launch_w<6, double>(plan, A, B, C, s, tn);
       break;
@@ -881,7 +889,7 @@ __global__ __launch_bounds__(256) void k_ip_local(int nk, int no, int nv, int K,
 // variants (each does the real work); the 32-wide one is kept only if it is at
 // least 5% faster.  Choices are cached per shape in the context (and in the
 // autotune file when one is configured).
-static int tuned_launch(ccgf_ctx *c, int tag, GemmPlan &p, const void *A, const cplx *B, cplx *C, hipStream_t s,
+static int tuned_launch(ccgf_ctx *c, int tag, GemmPlan &p, const void *A, const void *B, cplx *C, hipStream_t s,
                         int prec) {
   if (p.tn[prec] == 0 && (c->opt.autotune < 0 || prec == 2)) p.tn[prec] = 64;
   if (p.tn[prec] == 0) {
@@ -935,27 +943,39 @@ void tune_save(const ccgf_ctx *c) {
   std::fclose(f);
 }
 
+__global__ void k_to_f32(const cplx *__restrict__ x, float2 *__restrict__ y, size_t tot) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < tot) y[i] = float2{(float)x[i].x, (float)x[i].y};
+}
+
 // The launches of one sigma product on stream s (event records only when ts is set).
 static int sigma_enqueue(ccgf_ctx *c, SigmaPlan *P, int part, int K, int nvec, const cplx *x, cplx *y, int prec,
                          hipStream_t s, ccgf_ctx::TimedSigma *ts) {
   const int nk = c->nk, no = c->no, nv = c->nv;
   const long long n = P->n;
   const unsigned gy = (unsigned)std::min(nvec, 65535);
+  // the reduced-precision GEMMs read the vectors through one complex float copy
+  const void *xb = x;
+  if (prec) {
+    const size_t tot = (size_t)nvec * n;
+    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, x, c->sig_x32, tot);
+    xb = c->sig_x32;
+  }
   if (part == CCGF_PART_EA) {
     if (ts) hipEventRecord(ts->e[2], s);
     if (prec && !c->Wvvvv32) return set_err(c, CCGF_ESTATE, "mixed-precision operands were not built");
     const void *Wbig = prec ? (const void *)c->Wvvvv32 : (const void *)c->Wvvvv;
     const void *Wovvo = prec ? (const void *)c->WvoPea32 : (const void *)c->WvoPea;
-    int rc = tuned_launch(c, 0, P->g_big, Wbig, x, y, s, prec);
+    int rc = tuned_launch(c, 0, P->g_big, Wbig, xb, y, s, prec);
     if (ts) hipEventRecord(ts->e[3], s);
-    if (!rc && P->g_bigt.ntask) rc = tuned_launch(c, 8, P->g_bigt, Wbig, x, y, s, prec);
-    if (!rc && P->g_bigd.ntask) rc = tuned_launch(c, 9, P->g_bigd, Wbig, x, y, s, prec);
+    if (!rc && P->g_bigt.ntask) rc = tuned_launch(c, 8, P->g_bigt, Wbig, xb, y, s, prec);
+    if (!rc && P->g_bigd.ntask) rc = tuned_launch(c, 9, P->g_bigd, Wbig, xb, y, s, prec);
     if (P->nfill > 0) {
       const long long b2 = (long long)no * nv * nv;
       hipLaunchKernelGGL(k_vvvv_fill, dim3((unsigned)((b2 + 255) / 256), P->nfill, std::min(nvec, 64)), dim3(256), 0,
                          s, y, n, nvec, nv, b2, P->d_fill, P->d_fill + P->nfill, P->nfill);
     }
-    if (!rc) rc = tuned_launch(c, 1, P->g_ovvo, Wovvo, x, c->sig_tmp, s, prec);
+    if (!rc) rc = tuned_launch(c, 1, P->g_ovvo, Wovvo, xb, c->sig_tmp, s, prec);
     if (!rc) rc = tuned_launch(c, 4, P->g_r1, c->Wvvvo, x, y, s, 0);
     if (!rc) rc = tuned_launch(c, 6, P->g_red1, c->Wvovv, x, c->sig_part, s, 0);
     if (!rc) rc = tuned_launch(c, 6, P->g_red2, c->Voovv, x, c->sig_part, s, 0);
@@ -971,9 +991,9 @@ static int sigma_enqueue(ccgf_ctx *c, SigmaPlan *P, int part, int K, int nvec, c
     if (prec && !c->WooP32) return set_err(c, CCGF_ESTATE, "mixed-precision operands were not built");
     const void *Wbig = prec ? (const void *)c->WooP32 : (const void *)c->WooP;
     const void *Wovvo = prec ? (const void *)c->WvoP32 : (const void *)c->WvoP;
-    int rc = tuned_launch(c, 2, P->g_big, Wbig, x, y, s, prec);
+    int rc = tuned_launch(c, 2, P->g_big, Wbig, xb, y, s, prec);
     if (ts) hipEventRecord(ts->e[3], s);
-    if (!rc) rc = tuned_launch(c, 3, P->g_ovvo, Wovvo, x, c->sig_tmp, s, prec);
+    if (!rc) rc = tuned_launch(c, 3, P->g_ovvo, Wovvo, xb, c->sig_tmp, s, prec);
     if (!rc) rc = tuned_launch(c, 5, P->g_r1, c->Wovoo, x, y, s, 0);
     if (!rc) rc = tuned_launch(c, 7, P->g_red1, c->Wooov, x, c->sig_part, s, 0);
     if (!rc) rc = tuned_launch(c, 7, P->g_red2, c->Voovv, x, c->sig_part, s, 0);
@@ -1015,6 +1035,17 @@ int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y, 
   }
   const int ldaux = std::max(c->no, c->nv);
   size_t need_aux = (size_t)nvec * ldaux;
+  if (prec && c->sig_x32_elems < need) {
+    drop_graphs(c);
+    if (c->sig_x32) {
+      for (auto &q : c->allocs)
+        if (q == c->sig_x32) q = nullptr;
+      hipFree(c->sig_x32);
+    }
+    c->sig_x32 = (float2 *)dev_alloc(c, need * sizeof(float2));
+    c->sig_x32_elems = c->sig_x32 ? need : 0;
+    if (!c->sig_x32) return CCGF_ENOMEM;
+  }
   if (c->sig_r1aux_elems < need_aux) {
     drop_graphs(c);
     if (c->sig_r1aux) {

@@ -95,7 +95,7 @@ struct GemmPlan {
   int m_ext = 0, k_ext = 0;     // index ranges reached through mtab / ktab (0: M / K)
   int tn[3] = {0, 0, 0};        // N tile width picked by the autotuner per precision (0: not yet)
   int trials[3] = {0, 0, 0};    // timed trial launches so far
-  float tms[3][2] = {};         // their times (64-wide, 32-wide)
+  float tms[3][3] = {};         // their times (64-wide, 32-wide, 128-wide)
   int ntask;
   GemmTask *d_tasks;
   GemmSeg *d_segs;

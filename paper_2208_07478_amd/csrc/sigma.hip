@@ -58,8 +58,9 @@ struct Mf<float> {
 // 2: IP W_mnij, 3: IP W_maei, 4: EA W_abei r^e, 5: IP W_maij r_m, 6: EA 1p-row
 // reductions W_alcd r, <kl||cd> r, 7: IP 1h-row reductions W_mnie r, <mn||ef> r,
 // 8 and 9: EA W_abcd on the blocks ka = kb, pairs kc = kd and kc < kd).
-// TNT is the tile width in N (64, or 32 for narrow batches); the four waves of a
-// block own 32x32 (TNT = 64) or 16x32 (TNT = 32) output sub-tiles.
+// TNT is the tile width in N (64, 32 for narrow batches, 128 in FP32 to read W
+// fewer times); the four waves of a block own 32x32 (TNT = 64), 16x32 (TNT = 32)
+// or 32x64 (TNT = 128) output sub-tiles.
 template <int TAG, typename R, int TNT>
 __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *__restrict__ tasks,
                                                   const GemmSeg *__restrict__ segs,
@@ -81,7 +82,8 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
   const GemmTask task = tasks[t];
 
   constexpr int NBJ = TNT / 16;           // B rows staged per thread
-  constexpr int AM = TNT == 64 ? 2 : 1;   // MFMA row tiles per wave
+  constexpr int AM = TNT == 32 ? 1 : 2;   // MFMA row tiles per wave
+  constexpr int BN = TNT == 128 ? 4 : 2;  // MFMA column tiles per wave
   __shared__ R Ar[TM][TK + 1], Ai[TM][TK + 1], Br[TNT][TK + 1], Bi[TNT][TK + 1];
   const int tid = threadIdx.x;
 
@@ -106,11 +108,11 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
 
   // Gauss' three-product form: P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi);
   // C = (P1 - P2) + i (P3 - P1 - P2)
-  V4 P1[AM][2], P2[AM][2], P3[AM][2];
+  V4 P1[AM][BN], P2[AM][BN], P3[AM][BN];
 #pragma unroll
   for (int a = 0; a < AM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < BN; ++b) {
       P1[a][b] = (V4){0, 0, 0, 0};
       P2[a][b] = (V4){0, 0, 0, 0};
       P3[a][b] = (V4){0, 0, 0, 0};
@@ -136,9 +138,9 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
   };
 
   const int wave = tid >> 6, lane = tid & 63;
-  // rows [rbase, rbase + 16 AM) and columns [cbase, cbase + 32) of the tile belong to this wave
-  const int rbase = TNT == 64 ? (wave >> 1) * 32 : wave * 16;
-  const int cbase = TNT == 64 ? (wave & 1) * 32 : 0;
+  // rows [rbase, rbase + 16 AM) and columns [cbase, cbase + 16 BN) of the tile belong to this wave
+  const int rbase = TNT == 32 ? wave * 16 : (wave >> 1) * 32;
+  const int cbase = TNT == 32 ? 0 : (wave & 1) * (TNT / 2);
   const int lr = lane & 15, lk = lane >> 4;
 
   if (nsteps > 0) load(0);
@@ -158,7 +160,7 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
     if (step + 1 < nsteps) load(step + 1);
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
-      R a_r[AM], a_i[AM], a_s[AM], b_r[2], b_i[2], b_s[2];
+      R a_r[AM], a_i[AM], a_s[AM], b_r[BN], b_i[BN], b_s[BN];
 #pragma unroll
       for (int q = 0; q < AM; ++q) {
         a_r[q] = Ar[rbase + q * 16 + lr][kk + lk];
@@ -166,7 +168,7 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
         a_s[q] = a_r[q] + a_i[q];
       }
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
+      for (int q = 0; q < BN; ++q) {
         b_r[q] = Br[cbase + q * 16 + lr][kk + lk];
         b_i[q] = Bi[cbase + q * 16 + lr][kk + lk];
         b_s[q] = b_r[q] + b_i[q];
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
 #pragma unroll
       for (int a = 0; a < AM; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < BN; ++b) {
           P1[a][b] = Mf<R>::mm(a_r[a], b_r[b], P1[a][b]);
           P2[a][b] = Mf<R>::mm(a_i[a], b_i[b], P2[a][b]);
           P3[a][b] = Mf<R>::mm(a_s[a], b_s[b], P3[a][b]);
@@ -185,7 +187,7 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
 #pragma unroll
   for (int a = 0; a < AM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < BN; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         int row = rbase + a * 16 + Mf<R>::row(lk, v);
@@ -372,6 +374,7 @@ static void launch_t(const GemmPlan &plan, const void *A, const void *B, cplx *C
 template <int TAG, typename R>
 static void launch_w(const GemmPlan &plan, const void *A, const void *B, cplx *C, hipStream_t s, int tn) {
   if (tn == 32) launch_t<TAG, R, 32>(plan, A, B, C, s);
+  else if (tn == 128 && sizeof(R) == 4) launch_t<TAG, float, 128>(plan, A, B, C, s);
   else launch_t<TAG, R, 64>(plan, A, B, C, s);
 }
 
@@ -904,13 +907,18 @@ static int tuned_launch(ccgf_ctx *c, int tag, GemmPlan &p, const void *A, const 
         for (int q = 0; q < 2; ++q)
           if (hipEventCreate(&c->tev[q]) != hipSuccess) return hip_check(c, hipGetLastError(), "autotune events");
       int &tr = p.trials[prec];
-      const int cand = tr == 0 ? 64 : 32;
+      static const int cands[3] = {64, 32, 128};  // 128 only for the FP32 GEMMs
+      const int ncand = prec == 1 ? 3 : 2;
+      const int cand = cands[tr];
       hipEventRecord(c->tev[0], s);
       gemm_launch(tag, p, A, B, C, s, prec, cand);
       hipEventRecord(c->tev[1], s);
       if (hipEventSynchronize(c->tev[1]) == hipSuccess) hipEventElapsedTime(&p.tms[prec][tr], c->tev[0], c->tev[1]);
-      if (++tr == 2) {
-        p.tn[prec] = p.tms[prec][1] < 0.95f * p.tms[prec][0] ? 32 : 64;
+      if (++tr == ncand) {  // a narrower or wider tile only where it is 5% faster than 64
+        int best = 0;
+        for (int q = 1; q < ncand; ++q)
+          if (p.tms[prec][q] < 0.95f * p.tms[prec][best]) best = q;
+        p.tn[prec] = cands[best];
         c->tuned[key] = p.tn[prec];
       }
       return CCGF_OK;
@@ -929,7 +937,7 @@ void tune_load(ccgf_ctx *c) {
     char *sp = std::strrchr(line, ' ');
     if (!sp) continue;
     int tn = std::atoi(sp + 1);
-    if (tn != 32 && tn != 64) continue;
+    if (tn != 32 && tn != 64 && tn != 128) continue;
     c->tuned[std::string(line, sp - line)] = tn;
   }
   std::fclose(f);

@@ -127,3 +127,30 @@ def test_mixed_forms_keep_spectral_peaks_within_1meV(prec):
             p0, p1 = _peaks(w, A0), _peaks(w, A1)
             assert len(p0) == len(p1) and len(p0) > 0, (a, p)
             assert np.abs(p0 - p1).max() <= mev, (a, p, np.abs(p0 - p1).max())
+
+
+@pytest.mark.parametrize("part", ["ip", "ea"])
+def test_fp32_sigma_every_tile_width_matches_oracle(part):
+    """The first FP32 products of a new shape are the autotuner's trials (64-,
+    32- and 128-wide N tiles), the next ones its choice, then a captured graph:
+    each of them is checked, on a batch whose N spans several 128-wide tiles
+    with a ragged tail."""
+    import torch
+    from paper_2208_07478_amd.ccgf import Context
+    case = dict(kmesh=(2, 1, 1), nocc=3, nvir=9, seed=17)
+    s = _system(case)
+    E = eom.EOMSystem(s)
+    ctx = Context(s, max_batch=64, precision="f32")
+    try:
+        X = synth.random_eom_vectors(s.kmesh, s.nocc, s.nvir, part, 1, 53, seed=77)
+        ref = np.array([E.sigma(part, 1, x) for x in X])
+        Xd = torch.from_numpy(X).cuda()
+        for call in range(6):
+            Y = ctx.sigma(part, 1, Xd).cpu().numpy()
+            err = np.linalg.norm((Y - ref).reshape(len(X), -1), axis=1) / np.linalg.norm(ref.reshape(len(X), -1),
+                                                                                       axis=1)
+            print(part, "call", call, "max rel err", err.max(), flush=True)
+            assert err.max() <= BOUND["f32"]
+    finally:
+        ctx.close()
+        torch.cuda.synchronize()

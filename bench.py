@@ -35,9 +35,10 @@ if ROOT not in sys.path:
 METRIC = "G(ω) points/sec at 1e-6 rel. error, learned+mixed vs plain FP64; MFMA util"
 # MI355X dense matrix peaks of each form's MFMA dtype, FLOP/s
 PEAK = {"plain_f64": 78.6e12, "mixed_f32": 157.3e12, "mixed_bf16x3": 2.5e15, "learned_mixed_f32": 157.3e12}
-# the dominant kernel of each form (EA 1/2 W_abcd r_i^cd); the traffic record is the 64-wide tile's
-GEMM_NAME = {"plain_f64": "k_cgemm<0, double, 64>", "mixed_f32": "k_cgemm<0, float, 64>",
-             "mixed_bf16x3": "k_cgemm_b3<0>", "learned_mixed_f32": "k_cgemm<0, float, 64>"}
+# the dominant kernel of each form (EA 1/2 W_abcd r_i^cd over the blocks ka < kb), all N tile
+# widths the autotuner may pick (the traffic record covers the same family)
+GEMM_NAME = {"plain_f64": "k_cgemm<0, double>", "mixed_f32": "k_cgemm<0, float>",
+             "mixed_bf16x3": "k_cgemm_b3<0>", "learned_mixed_f32": "k_cgemm<0, float>"}
 PRECISION = {"plain_f64": "f64", "mixed_f32": "f32", "mixed_bf16x3": "bf16x3", "learned_mixed_f32": "f32"}
 DTYPE = {"plain_f64": "c128", "mixed_f32": "c64 sigma / c128 Krylov", "mixed_bf16x3": "bf16x3 sigma / c128 Krylov",
          "learned_mixed_f32": "c64 sigma / c128 Krylov, FP32 network"}
@@ -65,8 +66,9 @@ def parse():
     ap.add_argument("--no-check", action="store_true", help="skip the reference solve (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe", choices=["sigma", "copy"], default=None,
-                    help="counter-collection runs: 'sigma' applies 3 EA and 3 IP sigma products to the step's "
-                         "batch; 'copy' copies a 1 GiB buffer once (HBM-traffic calibration)")
+                    help="counter-collection runs: 'sigma' applies 6 EA and 6 IP sigma products to a batch of "
+                         "--batch vectors (the first ones are the autotuner's trials, the last 3 its choice); "
+                         "'copy' copies a 1 GiB buffer once (HBM-traffic calibration)")
     ap.add_argument("--probe-precision", default="f64")
     ap.add_argument("--cpu-sample-s", type=float, default=20.0)
     return ap.parse_args()
@@ -166,15 +168,15 @@ def main():
     opts = dict(tol=args.tol, restart_m=args.restart, maxiter=args.maxiter, max_batch=args.batch,
                 precond_eta=args.precond_eta, seed_m=args.seed_m)
     if args.probe == "sigma":
-        ctx = Context(sysm, precision=args.probe_precision, **opts)
+        ctx = Context(sysm, precision=args.probe_precision, graphs=False, **opts)
         for part in ("ea", "ip"):
             X = torch.from_numpy(synth.random_eom_vectors(sysm.kmesh, sysm.nocc, sysm.nvir, part, 0, args.batch,
                                                           seed=11)).cuda()
-            for _ in range(3):
+            for _ in range(6):
                 ctx.sigma(part, 0, X)
         torch.cuda.synchronize()
         ctx.close()
-        print(json.dumps({"probe": "sigma", "nvec": args.batch, "products": 3, "precision": args.probe_precision}))
+        print(json.dumps({"probe": "sigma", "nvec": args.batch, "products": 6, "precision": args.probe_precision}))
         return
 
     forms = [f for f in args.forms.split(",") if f]
@@ -239,7 +241,8 @@ def main():
             "unconverged": tot["n_unconverged"],
             "init_s": init_s,
             "learn": learn,
-            "roofline": {"bound": "mfma", "kernel": GEMM_NAME[form] + " (EA 1/2 W_abcd r_i^cd; autotuned 64/32 tiles)",
+            "roofline": {"bound": "mfma", "kernel": GEMM_NAME[form] + " (EA 1/2 W_abcd r_i^cd, blocks ka < kb; "
+                                                                     "N tile 32/64/128 by the autotuner)",
                          "achieved": ach / 1e12, "peak": PEAK[form] / 1e12, "unit": "TFLOP/s",
                          "frac": ach / PEAK[form], "avg_ms": avg_ms, "flops_per_launch": fl,
                          "launches": tot["big_launches"]},

@@ -1135,8 +1135,10 @@ int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y, 
     timing_harvest(c);
     ts = &c->tring[c->tnext];
     c->tnext = (c->tnext + 1) % (int)c->tring.size();
-    ts->big = part == CCGF_PART_EA;
-    ts->flops = part == CCGF_PART_EA ? plan_flops(P->g_big) : 0.0;
+    // the W_abcd statistics count the products in the context's own precision only (a
+    // mixed form's FP64 true residuals go to the sigma totals alone)
+    ts->big = part == CCGF_PART_EA && prec == c->opt.precision;
+    ts->flops = ts->big ? plan_flops(P->g_big) : 0.0;
     hipEventRecord(ts->e[0], s);
   }
   // (the coupling and reduction GEMMs always run in FP64)

@@ -218,14 +218,25 @@ __global__ void k_precond(cplx *__restrict__ z, const cplx *__restrict__ Vj, con
 }
 
 // compact gather: z[slot] = X[idx[slot]] / (shift + sM diag)  (sM = 0 and nodiv: plain copy);
-// with jv the source is column jv[v] of a basis with stride svi
+// with jv the source is column jv[v] of a basis with stride svi.  Source vectors have
+// length nx; with unp they hold the unique elements only and element x of the full
+// vector is sign * X[|unp[x]| - 1] (unp[x] = 0: a structural zero).
 __global__ void k_gather_precond(cplx *__restrict__ z, const cplx *__restrict__ X, const cplx *__restrict__ diag,
                                  const cplx *__restrict__ shift, double sM, long long n, const int *__restrict__ idx,
-                                 int divide, const int *__restrict__ jv, long long svi) {
+                                 int divide, const int *__restrict__ jv, long long svi, const int *__restrict__ unp,
+                                 long long nx) {
   const int slot = blockIdx.y, v = idx[slot];
   long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= n) return;
-  cplx u = X[(jv ? (size_t)jv[v] * svi : 0) + (size_t)v * n + x];
+  const size_t base = (jv ? (size_t)jv[v] * svi : 0) + (size_t)v * nx;
+  cplx u;
+  if (unp) {
+    const int q = unp[x];
+    u = q == 0 ? mkc(0, 0) : X[base + (size_t)(abs(q) - 1)];
+    if (q < 0) u = mkc(-u.x, -u.y);
+  } else {
+    u = X[base + x];
+  }
   if (divide) {
     cplx dd = cadd(shift[v], cscale(diag[x], sM));
     double den = dd.x * dd.x + dd.y * dd.y;
@@ -234,14 +245,50 @@ __global__ void k_gather_precond(cplx *__restrict__ z, const cplx *__restrict__ 
   z[(size_t)slot * n + x] = u;
 }
 
-// w[idx[slot]] = shift z[slot] + sM s[slot]
+// w[idx[slot]] = shift z[slot] + sM s[slot], for the nout elements pk[p] of the
+// full vectors (length nz) when pk is given (the unique elements), else all of them
 __global__ void k_scatter_shift(cplx *__restrict__ w, const cplx *__restrict__ z, const cplx *__restrict__ sg,
-                                const cplx *__restrict__ shift, double sM, long long n, const int *__restrict__ idx) {
+                                const cplx *__restrict__ shift, double sM, long long nout,
+                                const int *__restrict__ idx, const long long *__restrict__ pk, long long nz) {
   const int slot = blockIdx.y, v = idx[slot];
-  long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= n) return;
-  size_t o = (size_t)slot * n + x;
-  w[(size_t)v * n + x] = cadd(cmul(shift[v], z[o]), cscale(sg[o], sM));
+  long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nout) return;
+  size_t o = (size_t)slot * nz + (pk ? pk[p] : p);
+  w[(size_t)v * nout + p] = cadd(cmul(shift[v], z[o]), cscale(sg[o], sM));
+}
+
+// Project the listed full vectors onto the antisymmetric amplitudes: each pair of
+// copies becomes (a, -a) with a = (r[pk] - r[pkm]) / 2, structural zeros become 0
+// (rounding in a product leaves the two copies unequal by a few ulps; the Krylov
+// basis holds one copy, so the residual it can reduce is this projection).
+__global__ void k_antisym(cplx *__restrict__ r, long long n, const long long *__restrict__ pk,
+                          const long long *__restrict__ pkm, long long np, const long long *__restrict__ zl,
+                          long long nz, const int *__restrict__ idx) {
+  const int v = idx[blockIdx.y];
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  cplx *rv = r + (size_t)v * n;
+  if (t < np) {
+    const long long m = pkm[t];
+    if (m >= 0) {
+      const cplx a = rv[pk[t]], b = rv[m];
+      const cplx h = mkc(0.5 * (a.x - b.x), 0.5 * (a.y - b.y));
+      rv[pk[t]] = h;
+      rv[m] = mkc(-h.x, -h.y);
+    }
+  } else if (t < np + nz) {
+    rv[zl[t - np]] = mkc(0, 0);
+  }
+}
+
+// out[v][p] = w[v][pk[p]] * inv[v] (pk = NULL: p itself); out has length nout, w length nw
+__global__ void k_scale_pack(cplx *__restrict__ out, const cplx *__restrict__ w, const double *__restrict__ inv,
+                             long long nout, const long long *__restrict__ pk, long long nw,
+                             const int *__restrict__ active) {
+  const int v = blockIdx.y;
+  if (active && !active[v]) return;
+  long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nout) return;
+  out[(size_t)v * nout + p] = cscale(w[(size_t)v * nw + (pk ? pk[p] : p)], inv[v]);
 }
 
 // out[idx[slot]] = b - (shift x + sM s[slot])
@@ -427,25 +474,35 @@ __global__ void k_gcrot_small(int nvec, int m, int kc, const cplx *__restrict__ 
   }
 }
 
-// u = D^-1 V y - U t,  c = V d;  x += u, r -= c;  u, c stored into the recycle slot
+// u = D^-1 V y - U t,  c = V d;  x += u, r -= c;  u, c stored into the recycle slot.
+// The basis columns have length nvb and stride svv; with unp they hold the unique
+// elements only (element e of the full vector is sign * V[|unp[e]| - 1], 0: zero).
 __global__ __launch_bounds__(256) void k_gcrot_combine(
     long long n, int m, long long svi, const cplx *__restrict__ V, const cplx *__restrict__ ysol,
     const cplx *__restrict__ d, const int *__restrict__ kused, int kc, const cplx *Ub,
     const cplx *__restrict__ t, int ldt, const cplx *__restrict__ diag, const cplx *__restrict__ pshift, double sM,
     cplx *uout, cplx *__restrict__ cout, cplx *__restrict__ xs, cplx *__restrict__ rs,
-    const int *__restrict__ skip) {
+    const int *__restrict__ skip, const int *__restrict__ unp, long long nvb, long long svv) {
   const int v = blockIdx.y;
   if (skip[v]) return;
   long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
   const int k = kused[v];
+  const int q = unp ? unp[e] : (int)e + 1;
   cplx vy = mkc(0, 0), cc = mkc(0, 0);
-  for (int i = 0; i < k; ++i) {
-    cplx vi = V[(size_t)i * svi + (size_t)v * n + e];
-    cfma(vy, ysol[(size_t)v * m + i], vi);
-    cfma(cc, d[(size_t)v * (m + 1) + i], vi);
+  if (q != 0) {
+    const cplx *Ve = V + (size_t)v * nvb + (size_t)(abs(q) - 1);
+    for (int i = 0; i < k; ++i) {
+      cplx vi = Ve[(size_t)i * svv];
+      cfma(vy, ysol[(size_t)v * m + i], vi);
+      cfma(cc, d[(size_t)v * (m + 1) + i], vi);
+    }
+    cfma(cc, d[(size_t)v * (m + 1) + k], Ve[(size_t)k * svv]);
+    if (q < 0) {
+      vy = mkc(-vy.x, -vy.y);
+      cc = mkc(-cc.x, -cc.y);
+    }
   }
-  cfma(cc, d[(size_t)v * (m + 1) + k], V[(size_t)k * svi + (size_t)v * n + e]);
   cplx dd = cadd(pshift[v], cscale(diag[e], sM));
   double den = dd.x * dd.x + dd.y * dd.y;
   cplx u = mkc((vy.x * dd.x + vy.y * dd.y) / den, (vy.y * dd.x - vy.x * dd.y) / den);
@@ -592,6 +649,68 @@ static void wfree(GmresWork &W) {
   W.mine.clear();
 }
 
+// Unique elements of the EOM vectors of (part, K): the 2h1p / 2p1h amplitudes are
+// stored twice (r[ki][ka](i,a,b) = -r[ki][kb](i,b,a) for EA, r[ki][kj](i,j,a) =
+// -r[kj][ki](j,i,a) for IP; zero on the diagonal of a block paired with itself).
+// pk[p] = full index of unique element p (the 1h / 1p part, then the canonical
+// copies in storage order); unp[x] = +-(p + 1) for the element x of a full vector
+// that equals +-unique p, 0 for a structural zero.  The unit weight of every
+// unique element reproduces the unique-pair inner product of the full vectors.
+// pkm[p] is the full index of the other copy (-1 for the 1h / 1p part); zl lists the
+// structural zeros.
+static void build_pack(const ccgf_ctx *c, int part, int K, long long n, std::vector<long long> &pk,
+                       std::vector<int> &unp, std::vector<long long> &pkm, std::vector<long long> &zl) {
+  const int nk = c->nk, no = c->no, nv = c->nv;
+  auto c3 = [&](int a, int b, int d) { return c->kc3_h[((size_t)a * nk + b) * nk + d]; };
+  unp.assign((size_t)n, 0);
+  pk.clear();
+  pkm.clear();
+  zl.clear();
+  const int n1 = part == CCGF_PART_IP ? no : nv;
+  for (int x = 0; x < n1; ++x) {
+    pk.push_back(x);
+    pkm.push_back(-1);
+    unp[x] = (int)pk.size();
+  }
+  if (part == CCGF_PART_EA) {
+    const long long b2 = (long long)no * nv * nv;
+    for (int ki = 0; ki < nk; ++ki)
+      for (int ka = 0; ka < nk; ++ka) {
+        const int kb = c3(K, ki, ka);
+        if (ka > kb) continue;
+        const long long off = nv + (ki * nk + ka) * b2, offm = nv + (ki * nk + kb) * b2;
+        for (int i = 0; i < no; ++i)
+          for (int a = 0; a < nv; ++a)
+            for (int b = 0; b < nv; ++b) {
+              if (ka == kb && a == b) zl.push_back(off + ((long long)i * nv + a) * nv + b);
+              if (ka == kb && a >= b) continue;
+              pk.push_back(off + ((long long)i * nv + a) * nv + b);
+              pkm.push_back(offm + ((long long)i * nv + b) * nv + a);
+              unp[off + ((long long)i * nv + a) * nv + b] = (int)pk.size();
+              unp[offm + ((long long)i * nv + b) * nv + a] = -(int)pk.size();
+            }
+      }
+  } else {
+    const long long b2 = (long long)no * no * nv;
+    for (int ki = 0; ki < nk; ++ki)
+      for (int kj = ki; kj < nk; ++kj) {
+        const long long off = no + (ki * nk + kj) * b2, offm = no + (kj * nk + ki) * b2;
+        for (int i = 0; i < no; ++i)
+          for (int j = 0; j < no; ++j) {
+            if (ki == kj && i == j)
+              for (int a = 0; a < nv; ++a) zl.push_back(off + ((long long)i * no + j) * nv + a);
+            if (ki == kj && i >= j) continue;
+            for (int a = 0; a < nv; ++a) {
+              pk.push_back(off + ((long long)i * no + j) * nv + a);
+              pkm.push_back(offm + ((long long)j * no + i) * nv + a);
+              unp[off + ((long long)i * no + j) * nv + a] = (int)pk.size();
+              unp[offm + ((long long)j * no + i) * nv + a] = -(int)pk.size();
+            }
+          }
+      }
+  }
+}
+
 int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, const double *rhs_omega, double eta,
                   const cplx *Bvecs, const cplx *Evecs, cplx *Gout, ccgf_stats *st, cplx *Xout, const Guess *guess) {
   const long long n = vec_len(c, part);
@@ -618,12 +737,27 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
   }
   const int m_tail = m;
   const int nchunk = (int)((n + DOT_CHUNK - 1) / DOT_CHUNK);
+  // GMRES keeps its Krylov basis (and w) as unique elements only, which halves the
+  // orthogonalisation traffic; GCROT keeps full vectors (its recycled pairs are full)
+  const bool packed = kr == 0;
+  std::vector<long long> hpk, hpkm, hzl;
+  std::vector<int> hunp;
+  if (packed) build_pack(c, part, K, n, hpk, hunp, hpkm, hzl);
+  const long long nb = packed ? (long long)hpk.size() : n;  // basis vector length
+  const int n1b = packed ? (int)nb : n1;                     // unit weights when packed
+  const int nchb = (int)((nb + DOT_CHUNK - 1) / DOT_CHUNK);
   const int ldp = std::max(m, kslots) + 1;
   hipStream_t s = c->stream;
   GmresWork W;
   const size_t vb = (size_t)Bmax * n;
   const size_t svi = vb;
-  cplx *V = (cplx *)walloc(W, sizeof(cplx) * vb * (m + 1));
+  const size_t svb = (size_t)Bmax * nb;  // basis column stride
+  cplx *V = (cplx *)walloc(W, sizeof(cplx) * svb * (m + 1));
+  long long *pkd = packed ? (long long *)walloc(W, sizeof(long long) * std::max<size_t>(1, hpk.size())) : nullptr;
+  int *unpd = packed ? (int *)walloc(W, sizeof(int) * (size_t)n) : nullptr;
+  long long *pkmd = packed ? (long long *)walloc(W, sizeof(long long) * std::max<size_t>(1, hpkm.size())) : nullptr;
+  long long *zld = packed ? (long long *)walloc(W, sizeof(long long) * std::max<size_t>(1, hzl.size())) : nullptr;
+  long long *uoffb = (long long *)walloc(W, sizeof(long long) * Bmax);
   cplx *Ub = (cplx *)walloc(W, sizeof(cplx) * vb * kslots);
   cplx *Cb = (cplx *)walloc(W, sizeof(cplx) * vb * kslots);
   cplx *X = (cplx *)walloc(W, sizeof(cplx) * vb);
@@ -664,9 +798,15 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
     wfree(W);
     return set_err(c, CCGF_ENOMEM, "solver workspace allocation failed (reduce max_batch, restart_m or recycle_k)");
   }
-  const unsigned gx = (unsigned)((n + 255) / 256);
+  const unsigned gx = (unsigned)((n + 255) / 256), gxb = (unsigned)((nb + 255) / 256);
   hipLaunchKernelGGL(k_diag, dim3(gx), dim3(256), 0, s, part, c->nk, c->no, c->nv, K, c->kc3, c->Foo, c->Fvv, diag,
                      n);
+  if (packed) {
+    hipMemcpyAsync(pkd, hpk.data(), sizeof(long long) * hpk.size(), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(unpd, hunp.data(), sizeof(int) * (size_t)n, hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(pkmd, hpkm.data(), sizeof(long long) * hpkm.size(), hipMemcpyHostToDevice, s);
+    if (!hzl.empty()) hipMemcpyAsync(zld, hzl.data(), sizeof(long long) * hzl.size(), hipMemcpyHostToDevice, s);
+  }
 
   int status = CCGF_OK;
   const double peta = std::max(eta, c->opt.precond_eta);
@@ -675,7 +815,7 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
   std::vector<cplx> hshift(Bmax), hpshift(Bmax), hh((size_t)Bmax * ldp);
   std::vector<double> hbnorm(Bmax), hthr(Bmax), hrn(Bmax), hinv(Bmax);
   std::vector<int> hconv(Bmax), hkused(Bmax), hact(Bmax), hskip(Bmax), its(Bmax), hjlim(Bmax), hneed(Bmax);
-  std::vector<long long> hoff(Bmax), heoff(Bmax);
+  std::vector<long long> hoff(Bmax), hoffb(Bmax), heoff(Bmax);
   std::vector<int> alist;
   alist.reserve(Bmax);
   const double tol = c->opt.tol;
@@ -696,11 +836,18 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
     const int np = (int)alist.size();
     if (np == 0) return CCGF_OK;
     hipMemcpyAsync(aidx, alist.data(), sizeof(int) * np, hipMemcpyHostToDevice, s);
-    hipLaunchKernelGGL(k_gather_precond, dim3(gx, np), dim3(256), 0, s, Z, X, diag, shift, 0.0, n, aidx, 0, (const int *)nullptr, 0LL);
+    hipLaunchKernelGGL(k_gather_precond, dim3(gx, np), dim3(256), 0, s, Z, X, diag, shift, 0.0, n, aidx, 0,
+                       (const int *)nullptr, 0LL, (const int *)nullptr, n);
     int rc = sigma_apply(c, part, K, np, Z, Wc);
     if (rc != CCGF_OK) return rc;
     if (st) st->n_sigma += np;
     hipLaunchKernelGGL(k_residual_c, dim3(gx, np), dim3(256), 0, s, R, Bv, X, Wc, shift, sM, n, aidx);
+    if (packed) {
+      const long long tot = nb + (long long)hzl.size();
+      hipLaunchKernelGGL(k_antisym, dim3((unsigned)((tot + 255) / 256), np), dim3(256), 0, s, R, n,
+                         (const long long *)pkd, (const long long *)pkmd, nb, (const long long *)zld,
+                         (long long)hzl.size(), aidx);
+    }
     norms(R, B);
     hipMemcpyAsync(hh.data(), htmp, sizeof(cplx) * B * ldp, hipMemcpyDeviceToHost, s);
     return sync("true residual");
@@ -717,12 +864,14 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
   int next = 0;
   for (int v = 0; v < B; ++v) {
     hoff[v] = (long long)v * n;  // each slot's own vector inside a [B][n] batch
+    hoffb[v] = (long long)v * nb;
     heoff[v] = 0;
     hconv[v] = 1;
     its[v] = 0;
     hbnorm[v] = hrn[v] = 0;
   }
   hipMemcpyAsync(uoff, hoff.data(), sizeof(long long) * B, hipMemcpyHostToDevice, s);
+  hipMemcpyAsync(uoffb, hoffb.data(), sizeof(long long) * B, hipMemcpyHostToDevice, s);
   // G = e . x (bilinear, Eq. 7), statistics and solutions of the listed slots; frees them
   auto retire = [&](const std::vector<int> &fin) -> int {
     alist.clear();
@@ -892,7 +1041,8 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
         hipMemcpyAsync(jlim, hjlim.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
         hipMemcpyAsync(inv, hinv.data(), sizeof(double) * B, hipMemcpyHostToDevice, s);
         hipMemcpyAsync(w0n, hrn.data(), sizeof(double) * B, hipMemcpyHostToDevice, s);
-        hipLaunchKernelGGL(k_scale, dim3(gx, B), dim3(256), 0, s, V, R, inv, n, fmask);  // V_0 = r / ||r||
+        hipLaunchKernelGGL(k_scale_pack, dim3(gxb, B), dim3(256), 0, s, V, R, inv, nb, (const long long *)pkd, n,
+                           fmask);  // V_0 = r / ||r||
         hipLaunchKernelGGL(k_cycle_start, dim3(B), dim3(256), 0, s, m, kslots, fmask, w0n, H, H0, Bm, g, kused);
       }
       bool anyc = false;
@@ -915,25 +1065,26 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
     hipMemcpyAsync(jvd, hj.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
     hipMemcpyAsync(aidx, alist.data(), sizeof(int) * na, hipMemcpyHostToDevice, s);
     hipLaunchKernelGGL(k_gather_precond, dim3(gx, na), dim3(256), 0, s, Z, V, diag, pshift, sM, n, aidx, 1, jvd,
-                       (long long)svi);
+                       (long long)svb, (const int *)unpd, nb);
     int rc = sigma_apply(c, part, K, na, Z, Wc, c->opt.precision);
     if (rc != CCGF_OK) {
       wfree(W);
       return rc;
     }
     if (st) st->n_sigma += na;
-    hipLaunchKernelGGL(k_scatter_shift, dim3(gx, na), dim3(256), 0, s, Wv, Z, Wc, shift, sM, n, aidx);
+    hipLaunchKernelGGL(k_scatter_shift, dim3(gxb, na), dim3(256), 0, s, Wv, Z, Wc, shift, sM, nb, aidx,
+                       (const long long *)pkd, n);
     // ||w||^2 before projection (for the reorthogonalisation test)
-    hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Wv, uoff, 0LL, 1, Wv, n, n1, 1, active, partial,
-                       nchunk, ldp, (const int *)nullptr);
-    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, 1, active, htmp, ldp,
+    hipLaunchKernelGGL(k_dots, dim3(nchb, B), dim3(256), 0, s, Wv, uoffb, 0LL, 1, Wv, nb, n1b, 1, active, partial,
+                       nchb, ldp, (const int *)nullptr);
+    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchb, ldp, 1, active, htmp, ldp,
                        (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
     hipLaunchKernelGGL(k_take_norm, dim3((B + 63) / 64), dim3(64), 0, s, B, htmp, ldp, w0n, active);
     // classical Gram-Schmidt against the recycled C and V_0..V_j, a second pass where the first
     // removed most of w
     for (int pass = 0; pass < 2; ++pass) {
       const int *mask = pass == 0 ? active : need;
-      if (kc > 0) {
+      if (kc > 0) {  // (GCROT: full vectors, nb = n)
         hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Cb, uoff, (long long)svi, kc, Wv, n, n1, 1,
                            mask, partial, nchunk, ldp, (const int *)nullptr);
         hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, kc, mask, htmp, ldp, Bm, m,
@@ -941,15 +1092,15 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
         hipLaunchKernelGGL(k_sub_proj, dim3(gx, B), dim3(256), 0, s, Wv, Cb, (long long)svi, n, kc, htmp, ldp, mask,
                            (const int *)nullptr);
       }
-      hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, V, uoff, (long long)svi, 1, Wv, n, n1, 1, mask,
-                         partial, nchunk, ldp, (const int *)jvd);
-      hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, 1, mask, htmp, ldp, H, m,
+      hipLaunchKernelGGL(k_dots, dim3(nchb, B), dim3(256), 0, s, V, uoffb, (long long)svb, 1, Wv, nb, n1b, 1, mask,
+                         partial, nchb, ldp, (const int *)jvd);
+      hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchb, ldp, 1, mask, htmp, ldp, H, m,
                          (long long)(m + 1) * m, 0, H0, (const int *)jvd, (const int *)jvd);
-      hipLaunchKernelGGL(k_sub_proj, dim3(gx, B), dim3(256), 0, s, Wv, V, (long long)svi, n, 1, htmp, ldp, mask,
+      hipLaunchKernelGGL(k_sub_proj, dim3(gxb, B), dim3(256), 0, s, Wv, V, (long long)svb, nb, 1, htmp, ldp, mask,
                          (const int *)jvd);
-      hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Wv, uoff, 0LL, 1, Wv, n, n1, 1, mask, partial,
-                         nchunk, ldp, (const int *)nullptr);
-      hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, 1, mask, htmp, ldp,
+      hipLaunchKernelGGL(k_dots, dim3(nchb, B), dim3(256), 0, s, Wv, uoffb, 0LL, 1, Wv, nb, n1b, 1, mask, partial,
+                         nchb, ldp, (const int *)nullptr);
+      hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchb, ldp, 1, mask, htmp, ldp,
                          (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
       if (pass == 0)
         hipLaunchKernelGGL(k_need_reorth, dim3((B + 63) / 64), dim3(64), 0, s, B, htmp, ldp, w0n, active, need,
@@ -959,7 +1110,7 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
                        kused, thresh, jlim, H0);
     // V_{j+1} = w / h_{j+1,j} (also for j + 1 = m: the image c = V H y uses it).  k_givens
     // clears `active` of right-hand sides that finish here, so use this step's list aidx.
-    hipLaunchKernelGGL(k_scale_idx, dim3(gx, na), dim3(256), 0, s, V, Wv, inv, n, aidx, jvd, (long long)svi);
+    hipLaunchKernelGGL(k_scale_idx, dim3(gxb, na), dim3(256), 0, s, V, Wv, inv, nb, aidx, jvd, (long long)svb);
     hipMemcpyAsync(hact.data(), active, sizeof(int) * B, hipMemcpyDeviceToHost, s);
     hipMemcpyAsync(hneed.data(), need, sizeof(int) * B, hipMemcpyDeviceToHost, s);
     if (int rc2 = sync("solver iteration")) {
@@ -988,7 +1139,7 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
     hipLaunchKernelGGL(k_gcrot_small, dim3(B), dim3(256), 0, s, B, m, kc, Bm, H0, ysol, kused, tv, dv, skip, kslots);
     cplx *us = Ub + (size_t)rslot * svi, *cs_ = Cb + (size_t)rslot * svi;
     hipLaunchKernelGGL(k_gcrot_combine, dim3(gx, B), dim3(256), 0, s, n, m, (long long)svi, V, ysol, dv, kused, kc, Ub,
-                       tv, kslots, diag, pshift, sM, us, cs_, X, R, skip);
+                       tv, kslots, diag, pshift, sM, us, cs_, X, R, skip, (const int *)unpd, nb, (long long)svb);
     if (kr > 0) {  // normalise the new pair so that c has unit norm
       norms(cs_, B);
       hipLaunchKernelGGL(k_inv_sqrt, dim3((B + 63) / 64), dim3(64), 0, s, B, htmp, ldp, inv, skip);

@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--tol", type=float, default=2e-7)
     ap.add_argument("--ref-tol", type=float, default=1e-9)
     ap.add_argument("--check-every", type=int, default=4, help="reference solve on every k-th step frequency")
-    ap.add_argument("--restart", type=int, default=150)
+    ap.add_argument("--restart", type=int, default=200)
     ap.add_argument("--maxiter", type=int, default=12000)
     ap.add_argument("--precond-eta", type=float, default=0.2)
     ap.add_argument("--seed-m", type=int, default=128,

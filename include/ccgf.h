@@ -125,7 +125,7 @@ typedef struct {
                             Krylov space of sigma from b is that of every shifted operator
                             (w -/+ i eta) -/+ sigma, so each (orbital, w) takes the GMRES
                             minimiser over it as its starting guess where that leaves less
-                            than 1e-4 ||b|| of residual (elsewhere x0 = 0).  Needs (seed_m + 1) x
+                            residual than x0 = 0 (elsewhere x0 = 0).  Needs (seed_m + 1) x
                             norb vectors of device memory; without it the solves start from 0.
                             Ignored while a trained guess network is enabled. */
 } ccgf_options;
@@ -148,7 +148,7 @@ typedef struct {
   long long n_reorth;        /* right-hand-side steps that needed the second Gram-Schmidt pass */
   long long n_guess;         /* solves started from a guess (trained network or Krylov seed) */
   long long n_guess_rejected; /* guesses discarded, started from 0 instead: ||b - A x0|| was not
-                                 below accept ||b|| (network) or 1e-4 ||b|| (Krylov seed) */
+                                 below accept ||b|| (network) or ||b|| (Krylov seed) */
 } ccgf_stats;
 
 /* Validates the system (shapes, t2 antisymmetry, factor Hermiticity, each to

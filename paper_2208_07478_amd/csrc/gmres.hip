@@ -1383,10 +1383,8 @@ int seed_krylov(ccgf_ctx *c, int part, int K, int norb, const cplx *Bvecs, int n
   gs.Q = Q;
   gs.chat = chat;
   gs.R = m;
-  // only near-converged seeds are kept: where the seed leaves a sizeable residual it is made
-  // of the slowly converging (near-pole) directions, and restarted, preconditioned GMRES
-  // from it took more iterations than from zero in every case measured
-  gs.accept = 1e-4;
+  // a seed is kept wherever it leaves less residual than x0 = 0
+  gs.accept = 1.0;
   gs.qs_i = (long long)vb;
   gs.qs_q = n;
   gs.qidx.assign(rhs_orb, rhs_orb + nrhs);

@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--check-every", type=int, default=4, help="reference solve on every k-th step frequency")
     ap.add_argument("--restart", type=int, default=200)
     ap.add_argument("--maxiter", type=int, default=12000)
-    ap.add_argument("--precond-eta", type=float, default=0.2)
+    ap.add_argument("--precond-eta", type=float, default=0.4)
     ap.add_argument("--seed-m", type=int, default=128,
                     help="shared-Krylov seed steps per orbital before the solves (0: start from zero)")
     ap.add_argument("--no-check", action="store_true", help="skip the reference solve (profiling runs)")

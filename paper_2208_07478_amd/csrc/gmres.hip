@@ -959,6 +959,12 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
         hipMemcpyAsync(aidx, gl.data(), sizeof(int) * ng, hipMemcpyHostToDevice, s);
         hipLaunchKernelGGL(k_expand, dim3(gx, ng), dim3(256), 0, s, X, guess->Q, goff, guess->chat, goff + B,
                            guess->R, n, aidx, guess->qs_i ? guess->qs_i : n);
+        if (packed) {  // keep x exactly antisymmetric: sigma is evaluated only on such vectors
+          const long long tot = nb + (long long)hzl.size();
+          hipLaunchKernelGGL(k_antisym, dim3((unsigned)((tot + 255) / 256), ng), dim3(256), 0, s, X, n,
+                             (const long long *)pkd, (const long long *)pkmd, nb, (const long long *)zld,
+                             (long long)hzl.size(), aidx);
+        }
         alist = gl;
         if (int rc = true_residual(B)) return rc;
         for (int v : gl) {

@@ -13,10 +13,12 @@
 // then doubles the orthogonalisation traffic for little gain in convergence).
 // The right-hand sides of one momentum K and part (orbitals x frequencies) share
 // a batch of slots that is refilled as solves finish, so one sigma product per
-// step serves the whole batch.  Inner
-// products count each unordered pair once (weight 1/2 on the doubly stored
-// 2h1p / 2p1h part), which makes full antisymmetric storage an isometric copy
-// of the unique-coefficient space.  G = e . x is bilinear (Eq. 7).
+// step serves the whole batch.  Inner products count each unordered pair once
+// (weight 1/2 on the doubly stored 2h1p / 2p1h part), which makes full
+// antisymmetric storage an isometric copy of the unique-coefficient space; the
+// GMRES basis is kept in that unique space (half the vector length), sigma
+// works on full storage, and residuals and guesses are projected onto
+// antisymmetric vectors.  G = e . x is bilinear (Eq. 7).
 #include "ccgf_internal.h"
 
 #include <algorithm>

@@ -197,6 +197,7 @@ struct ccgf_ctx {
   size_t sig_tmp_elems = 0;
   cplx *sig_r1aux = nullptr;  // per-RHS 3-body contraction (nvec x max(no, nv))
   size_t sig_r1aux_elems = 0;
+  cplx *e_overlap = nullptr;  // [max(no, nv)] scratch of the e vectors (t2 overlap term)
   float2 *sig_x32 = nullptr;  // complex float copy of the vectors (reduced-precision GEMMs)
   size_t sig_x32_elems = 0;
   cplx *sig_part = nullptr;  // split-range partial sums of the 1h / 1p rows

@@ -377,6 +377,63 @@ int build_hbar(ccgf_ctx *c) {
   return CCGF_OK;
 }
 
+// *out = sum of v over a 256-thread block
+__device__ inline void block_store_sum(cplx v, cplx *out) {
+  __shared__ double sh[2][256];
+  sh[0][threadIdx.x] = v.x;
+  sh[1][threadIdx.x] = v.y;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + o];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = mkc(sh[0][0], sh[1][0]);
+}
+
+// h[i] = sum over kl, kc, l, c, d of t2[K][kl][kc](p, l, c, d) conj(t2[K][kl][kc](i, l, c, d)),
+// one 256-thread block per occupied i (the 1h overlap term of the IP e vector)
+__global__ __launch_bounds__(256) void k_t2_overlap(T4 t2, int K, int p, cplx *__restrict__ h) {
+  const int ii = blockIdx.x, nk = t2.nk, no = t2.n2, nv = t2.n4;
+  const long long tot = (long long)nk * nk * no * nv * nv;
+  cplx acc = mkc(0, 0);
+  for (long long q = threadIdx.x; q < tot; q += blockDim.x) {
+    long long r = q;
+    const int d = (int)(r % nv);
+    r /= nv;
+    const int cc = (int)(r % nv);
+    r /= nv;
+    const int l = (int)(r % no);
+    r /= no;
+    const int kc = (int)(r % nk), kl = (int)(r / nk);
+    cfma(acc, t2(K, kl, kc, p, l, cc, d), cconj(t2(K, kl, kc, ii, l, cc, d)));
+  }
+  block_store_sum(acc, h + ii);
+}
+
+// h[a] = sum over kk, kl, k, l, d of t2[kk][kl][kd](k, l, d, c0) conj(t2[kk][kl][kd](k, l, d, a)),
+// kd = kk + kl - K, one 256-thread block per virtual a (the 1p overlap term of the EA e vector)
+__global__ __launch_bounds__(256) void k_t2_overlap_ea(T4 t2, KTab kt, int K, int c0, cplx *__restrict__ h) {
+  const int a = blockIdx.x, nk = t2.nk, no = t2.n1, nv = t2.n4;
+  const long long tot = (long long)nk * nk * no * no * nv;
+  cplx acc = mkc(0, 0);
+  for (long long q = threadIdx.x; q < tot; q += blockDim.x) {
+    long long r = q;
+    const int d = (int)(r % nv);
+    r /= nv;
+    const int l = (int)(r % no);
+    r /= no;
+    const int k = (int)(r % no);
+    r /= no;
+    const int kl = (int)(r % nk), kk = (int)(r / nk);
+    const int kd = kt.c3(kk, kl, K);
+    cfma(acc, t2(kk, kl, kd, k, l, d, c0), cconj(t2(kk, kl, kd, k, l, d, a)));
+  }
+  block_store_sum(acc, h + a);
+}
+
 // b and e vectors of orbital p at momentum K (either pointer may be null).
 int build_vectors(ccgf_ctx *c, int part, int K, int p, cplx *bv, cplx *ev) {
   const int nk = c->nk, no = c->no, nv = c->nv;
@@ -407,6 +464,10 @@ int build_vectors(ccgf_ctx *c, int part, int K, int p, cplx *bv, cplx *ev) {
       });
     }
     if (ev) {
+      if (!c->e_overlap) c->e_overlap = (cplx *)dev_alloc(c, sizeof(cplx) * (size_t)std::max(no, nv));
+      if (!c->e_overlap) return CCGF_ENOMEM;
+      cplx *hov = c->e_overlap;
+      if (p < no) hipLaunchKernelGGL(k_t2_overlap, dim3(no), dim3(256), 0, s, t2, K, p, hov);
       foreach_(s, n, [=] __device__(size_t x) {
         cplx v = mkc(0, 0);
         if (x < (size_t)no) {
@@ -416,14 +477,7 @@ int build_vectors(ccgf_ctx *c, int part, int K, int p, cplx *bv, cplx *ev) {
           } else {
             v = mkc(ii == p ? 1.0 : 0.0, 0);
             for (int cc = 0; cc < nv; ++cc) v = csub(v, cmul(t1(K, p, cc), cconj(t1(K, ii, cc))));
-            cplx h = mkc(0, 0);
-            for (int kl = 0; kl < nk; ++kl)
-              for (int kc = 0; kc < nk; ++kc)
-                for (int l = 0; l < no; ++l)
-                  for (int cc = 0; cc < nv; ++cc)
-                    for (int d = 0; d < nv; ++d)
-                      cfma(h, t2(K, kl, kc, p, l, cc, d), cconj(t2(K, kl, kc, ii, l, cc, d)));
-            v = csub(v, cscale(h, 0.5));
+            v = csub(v, cscale(hov[ii], 0.5));
           }
         } else {
           size_t y = x - no;
@@ -465,6 +519,10 @@ int build_vectors(ccgf_ctx *c, int part, int K, int p, cplx *bv, cplx *ev) {
       });
     }
     if (ev) {
+      if (!c->e_overlap) c->e_overlap = (cplx *)dev_alloc(c, sizeof(cplx) * (size_t)std::max(no, nv));
+      if (!c->e_overlap) return CCGF_ENOMEM;
+      cplx *hov = c->e_overlap;
+      if (p >= no) hipLaunchKernelGGL(k_t2_overlap_ea, dim3(nv), dim3(256), 0, s, t2, kt, K, p - no, hov);
       foreach_(s, n, [=] __device__(size_t x) {
         cplx v = mkc(0, 0);
         if (x < (size_t)nv) {
@@ -476,16 +534,7 @@ int build_vectors(ccgf_ctx *c, int part, int K, int p, cplx *bv, cplx *ev) {
             int c0 = p - no;
             v = mkc(a == c0 ? 1.0 : 0.0, 0);
             for (int j = 0; j < no; ++j) v = csub(v, cmul(t1(K, j, c0), cconj(t1(K, j, a))));
-            cplx h = mkc(0, 0);
-            for (int kk = 0; kk < nk; ++kk)
-              for (int kl = 0; kl < nk; ++kl) {
-                int kd = kt.c3(kk, kl, K);
-                for (int k = 0; k < no; ++k)
-                  for (int l = 0; l < no; ++l)
-                    for (int d = 0; d < nv; ++d)
-                      cfma(h, t2(kk, kl, kd, k, l, d, c0), cconj(t2(kk, kl, kd, k, l, d, a)));
-              }
-            v = csub(v, cscale(h, 0.5));
+            v = csub(v, cscale(hov[a], 0.5));
           }
         } else {
           size_t y = x - nv;

@@ -81,29 +81,33 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
   const int tm = r / tilesN, tn = r % tilesN;
   const GemmTask task = tasks[t];
 
-  constexpr int NBJ = TNT / 16;           // B rows staged per thread
-  constexpr int AM = TNT == 32 ? 1 : 2;   // MFMA row tiles per wave
-  constexpr int BN = TNT == 128 ? 4 : 2;  // MFMA column tiles per wave
-  __shared__ R Ar[TM][TK + 1], Ai[TM][TK + 1], Br[TNT][TK + 1], Bi[TNT][TK + 1];
+  // k-slab: 32 for the FP32 W_abcd products (half the barriers per k), else 16
+  constexpr int KS = (sizeof(R) == 4 && (TAG == 0 || TAG == 8 || TAG == 9)) ? 2 * TK : TK;
+  constexpr int RPP = 256 / KS;            // rows staged per pass of the block
+  constexpr int AJ = TM / RPP;             // A rows staged per thread
+  constexpr int NBJ = TNT / RPP;           // B rows staged per thread
+  constexpr int AM = TNT == 32 ? 1 : 2;    // MFMA row tiles per wave
+  constexpr int BN = TNT == 128 ? 4 : 2;   // MFMA column tiles per wave
+  __shared__ R Ar[TM][KS + 1], Ai[TM][KS + 1], Br[TNT][KS + 1], Bi[TNT][KS + 1];
   const int tid = threadIdx.x;
 
-  // each thread stages column kt of rows rt + 16 j of both tiles
-  const int kt = tid & (TK - 1), rt = tid >> 4;
-  long long aoff[4], boff[NBJ];
-  bool aok[4], bok[NBJ];
+  // each thread stages column kt of rows rt + RPP j of both tiles
+  const int kt = tid & (KS - 1), rt = tid / KS;
+  long long aoff[AJ], boff[NBJ];
+  bool aok[AJ], bok[NBJ];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    int m = tm * TM + rt + 16 * j;
+  for (int j = 0; j < AJ; ++j) {
+    int m = tm * TM + rt + RPP * j;
     aok[j] = m < sh.M;
     aoff[j] = aok[j] ? imap(sh.am, sh.mtab ? sh.mtab[m] : m) : 0;
   }
 #pragma unroll
   for (int j = 0; j < NBJ; ++j) {
-    int n = tn * TNT + rt + 16 * j;
+    int n = tn * TNT + rt + RPP * j;
     bok[j] = n < sh.N;
     boff[j] = bok[j] ? imap(sh.bn, n) : 0;
   }
-  const int ksteps = (sh.K + TK - 1) / TK;
+  const int ksteps = (sh.K + KS - 1) / KS;
   const int nsteps = task.nseg * ksteps;
 
   // Gauss' three-product form: P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi);
@@ -118,10 +122,10 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
       P3[a][b] = (V4){0, 0, 0, 0};
     }
 
-  AE ra[4], rb[NBJ];
+  AE ra[AJ], rb[NBJ];
   auto load = [&](int step) {
     int s = step / ksteps;
-    int k = (step - s * ksteps) * TK + kt;
+    int k = (step - s * ksteps) * KS + kt;
     GemmSeg sg = segs[task.seg_begin + s];
     const bool kok = k < sh.K;
     if (kok && sh.ktab) k = sh.ktab[k];
@@ -129,7 +133,7 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
     const AE *Bp = B + sg.b_off + (kok ? imap(sh.bk, k) : 0);
     const R w = (R)sg.w;  // 1 or 1/2: exact in either precision
 #pragma unroll
-    for (int j = 0; j < 4; ++j) ra[j] = (aok[j] && kok) ? Ap[aoff[j]] : AE{0, 0};
+    for (int j = 0; j < AJ; ++j) ra[j] = (aok[j] && kok) ? Ap[aoff[j]] : AE{0, 0};
 #pragma unroll
     for (int j = 0; j < NBJ; ++j) {
       const AE b = (bok[j] && kok) ? Bp[boff[j]] : AE{0, 0};
@@ -147,19 +151,19 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
   for (int step = 0; step < nsteps; ++step) {
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      Ar[rt + 16 * j][kt] = (R)ra[j].x;
-      Ai[rt + 16 * j][kt] = (R)ra[j].y;
+    for (int j = 0; j < AJ; ++j) {
+      Ar[rt + RPP * j][kt] = (R)ra[j].x;
+      Ai[rt + RPP * j][kt] = (R)ra[j].y;
     }
 #pragma unroll
     for (int j = 0; j < NBJ; ++j) {
-      Br[rt + 16 * j][kt] = (R)rb[j].x;
-      Bi[rt + 16 * j][kt] = (R)rb[j].y;
+      Br[rt + RPP * j][kt] = (R)rb[j].x;
+      Bi[rt + RPP * j][kt] = (R)rb[j].y;
     }
     __syncthreads();
     if (step + 1 < nsteps) load(step + 1);
 #pragma unroll
-    for (int kk = 0; kk < TK; kk += 4) {
+    for (int kk = 0; kk < KS; kk += 4) {
       R a_r[AM], a_i[AM], a_s[AM], b_r[BN], b_i[BN], b_s[BN];
 #pragma unroll
       for (int q = 0; q < AM; ++q) {

@@ -164,7 +164,12 @@ int cc_gf_init(const ccgf_system *sys, const ccgf_options *opt, ccgf_ctx **out);
  *  G, Gplus_opt, Gminus_opt: host complex [nkq][norb][nw], caller-allocated
  *  (the optional ones may be NULL).  G receives G+ + G- of the requested parts.
  *  st_opt may be NULL.  Returns CCGF_ENOCONV if any solve missed tol (G is
- *  still written). */
+ *  still written).  tol applies to the residual of the equations on the
+ *  unique 2h1p / 2p1h amplitudes (the full-storage residual projected onto
+ *  antisymmetric vectors).  Device memory per call: the GMRES basis of
+ *  (restart_m + 1) x min(max_batch, norb * nw) vectors of unique amplitudes
+ *  (about half the full vector length; full length with recycle_k > 0), a few
+ *  full-length vectors per slot, and the seed basis when seed_m > 0. */
 int cc_gf_solve(ccgf_ctx *ctx, int nkq, const int *kidx, int norb, const int *orbs,
                 int nw, const double *omega, double eta, int parts,
                 double *G, double *Gplus_opt, double *Gminus_opt, ccgf_stats *st_opt);

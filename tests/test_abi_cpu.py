@@ -85,7 +85,7 @@ def test_options_and_new_entry_points_are_checked_on_the_host():
     cs, keep = _system_struct(s)
     bad = [dict(precision=7), dict(restart_m=-1), dict(restart_m=2001), dict(tol=-1.0), dict(max_batch=-2),
            dict(recycle_k=201), dict(precond_eta=-0.1), dict(reorth_ratio=1.5), dict(autotune=2),
-           dict(graphs=3)]
+           dict(graphs=3), dict(restart_tail=2001), dict(seed_m=-1), dict(seed_m=2001)]
     for kw in bad:
         o = ccgf.Options()
         for k, v in kw.items():

@@ -203,22 +203,6 @@ __global__ void k_diag(int part, int nk, int no, int nv, int K, const int *__res
   d[x] = r;
 }
 
-// z[v] = V_j[v] / (shift_v + sM diag)   (zero for finished right-hand sides)
-__global__ void k_precond(cplx *__restrict__ z, const cplx *__restrict__ Vj, const cplx *__restrict__ diag,
-                          const cplx *__restrict__ shift, double sM, long long n, const int *__restrict__ active) {
-  const int v = blockIdx.y;
-  long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= n) return;
-  if (active && !active[v]) {
-    z[(size_t)v * n + x] = mkc(0, 0);
-    return;
-  }
-  cplx dd = cadd(shift[v], cscale(diag[x], sM));
-  cplx u = Vj[(size_t)v * n + x];
-  double den = dd.x * dd.x + dd.y * dd.y;
-  z[(size_t)v * n + x] = mkc((u.x * dd.x + u.y * dd.y) / den, (u.y * dd.x - u.x * dd.y) / den);
-}
-
 // compact gather: z[slot] = X[idx[slot]] / (shift + sM diag)  (sM = 0 and nodiv: plain copy);
 // with jv the source is column jv[v] of a basis with stride svi.  Source vectors have
 // length nx; with unp they hold the unique elements only and element x of the full
@@ -302,26 +286,6 @@ __global__ void k_residual_c(cplx *__restrict__ out, const cplx *__restrict__ b,
   if (e >= n) return;
   size_t o = (size_t)v * n + e;
   out[o] = csub(b[o], cadd(cmul(shift[v], xs[o]), cscale(sg[(size_t)slot * n + e], sM)));
-}
-
-// w = shift z + sM w
-__global__ void k_shift(cplx *__restrict__ w, const cplx *__restrict__ z, const cplx *__restrict__ shift, double sM,
-                        long long n) {
-  const int v = blockIdx.y;
-  long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= n) return;
-  size_t o = (size_t)v * n + x;
-  w[o] = cadd(cmul(shift[v], z[o]), cscale(w[o], sM));
-}
-
-// r = b - (shift x + sM s); stored into out
-__global__ void k_residual(cplx *__restrict__ out, const cplx *__restrict__ b, const cplx *__restrict__ x,
-                           const cplx *__restrict__ s, const cplx *__restrict__ shift, double sM, long long n) {
-  const int v = blockIdx.y;
-  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  size_t o = (size_t)v * n + e;
-  out[o] = csub(b[o], cadd(cmul(shift[v], x[o]), cscale(s[o], sM)));
 }
 
 // V_{j+1}[v] = w[v] * inv[v]

@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--restart", type=int, default=200)
     ap.add_argument("--maxiter", type=int, default=12000)
     ap.add_argument("--precond-eta", type=float, default=0.4)
+    ap.add_argument("--restart-tail", type=int, default=0,
+                    help="restart length once the queue is empty and at most a quarter of the slots iterate")
     ap.add_argument("--seed-m", type=int, default=128,
                     help="shared-Krylov seed steps per orbital before the solves (0: start from zero)")
     ap.add_argument("--no-check", action="store_true", help="skip the reference solve (profiling runs)")
@@ -166,7 +168,7 @@ def main():
     stride = len(omega) // args.nw
     wsel = omega[::stride][:args.nw]
     opts = dict(tol=args.tol, restart_m=args.restart, maxiter=args.maxiter, max_batch=args.batch,
-                precond_eta=args.precond_eta, seed_m=args.seed_m)
+                precond_eta=args.precond_eta, seed_m=args.seed_m, restart_tail=args.restart_tail)
     if args.probe == "sigma":
         ctx = Context(sysm, precision=args.probe_precision, graphs=False, **opts)
         for part in ("ea", "ip"):

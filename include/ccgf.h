@@ -57,7 +57,7 @@ enum {
   CCGF_EDEVICE = -3,      /* HIP runtime error */
   CCGF_ENOCONV = -4,      /* some solve missed the tolerance; G still written */
   CCGF_ESTATE = -5,       /* call out of order (e.g. NULL context) */
-  CCGF_EUNSUPPORTED = -6  /* option not available in this build */
+  CCGF_EUNSUPPORTED = -6  /* option not supported by the library */
 };
 
 enum { CCGF_HOST = 0, CCGF_DEVICE = 1 };

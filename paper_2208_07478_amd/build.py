@@ -33,13 +33,21 @@ def build(verbose: bool = False) -> str:
               # keep packed-FP32 instructions out of every kernel
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
               "-I", os.path.join(ROOT, "include"), "-Wno-unused-result", "-Wno-unused-value"]
+    cmds = []
     for src in SOURCES:
         obj = os.path.join(bdir, src.replace(".hip", ".o"))
-        cmd = [hipcc(), "-c", os.path.join(CSRC, src), "-o", obj] + common
+        cmds.append([hipcc(), "-c", os.path.join(CSRC, src), "-o", obj] + common)
+        objs.append(obj)
+    # one compiler process per source, at most 8 at a time
+    from concurrent.futures import ThreadPoolExecutor
+
+    def run(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+
+    with ThreadPoolExecutor(max_workers=min(8, len(cmds))) as ex:
+        list(ex.map(run, cmds))
     tmp = LIB + ".tmp"
     subprocess.run([hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs, check=True)
     os.replace(tmp, LIB)

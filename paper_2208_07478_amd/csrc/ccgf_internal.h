@@ -54,6 +54,32 @@ struct T4 {
   size_t size() const { return (size_t)nk * nk * nk * n1 * n2 * n3 * n4; }
 };
 
+// Read access to the stored W_abcd blocks (see ccgf_ctx::wblk_h): any block (ka, kb, kc)
+// is +-(a stored block) with the pair indices swapped where the momenta were.
+struct WPacked {
+  const cplx *p;
+  const int *tab;  // device wblk
+  KTab kt;
+  int nv;
+  __device__ inline cplx operator()(int ka, int kb, int kc, int a, int b, int c, int d) const {
+    double sg = 1.0;
+    if (ka > kb) {
+      int t = ka; ka = kb; kb = t;
+      t = a; a = b; b = t;
+      sg = -sg;
+    }
+    const int kd = kt.c3(ka, kb, kc);
+    if (kc > kd) {
+      kc = kd;
+      int t = c; c = d; d = t;
+      sg = -sg;
+    }
+    const size_t q = (size_t)tab[(ka * kt.nk + kb) * kt.nk + kc];
+    const size_t nv2 = (size_t)nv * nv;
+    return cscale(p[q * nv2 * nv2 + ((size_t)a * nv + b) * nv2 + (size_t)c * nv + d], sg);
+  }
+};
+
 // k-diagonal 2-index tensor [k][n1][n2].
 struct T2d {
   cplx *p;
@@ -184,6 +210,13 @@ struct ccgf_ctx {
   cplx *t1 = nullptr, *t2 = nullptr, *fac = nullptr, *foo = nullptr, *fvv = nullptr;
   // Hbar blocks (complex double)
   cplx *Foo = nullptr, *Fvv = nullptr, *Fov = nullptr;
+  // W_abcd is antisymmetric under (a,ka)<->(b,kb) and (c,kc)<->(d,kd): only the blocks
+  // (ka, kb, kc) with ka <= kb and kc <= kd = ka + kb - kc are stored, each whole
+  // (nv^4 elements), in the order of their flat triple; wblk_h[(ka*nk+kb)*nk+kc] is the
+  // stored block's ordinal, -1 for the blocks that antisymmetry gives
+  std::vector<int> wblk_h;
+  int *wblk = nullptr;  // device copy of wblk_h
+  long long nwblk = 0;
   cplx *Woooo = nullptr, *Wooov = nullptr, *Wovoo = nullptr, *Wovvo = nullptr;
   cplx *Wvovv = nullptr, *Wvvvo = nullptr, *Wvvvv = nullptr, *Voovv = nullptr;
   cplx *WvoP = nullptr;   // W_ovvo permuted to [kx][ki][km](x, i, m, e)

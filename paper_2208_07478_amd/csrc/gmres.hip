@@ -685,7 +685,28 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
   const double sE = part == CCGF_PART_IP ? -1.0 : 1.0;
   const int kr = c->opt.recycle_k;          // recycled pairs (0: GMRES(m))
   const int kslots = std::max(kr, 1);
-  const int Bmax = std::max(1, std::min(c->opt.max_batch, nrhs));
+  int Bmax = std::max(1, std::min(c->opt.max_batch, nrhs));
+  // GMRES keeps its Krylov basis (and w) as unique elements only, which halves the
+  // orthogonalisation traffic; GCROT keeps full vectors (its recycled pairs are full)
+  const bool packed = kr == 0;
+  std::vector<long long> hpk, hpkm, hzl;
+  std::vector<int> hunp;
+  if (packed) build_pack(c, part, K, n, hpk, hunp, hpkm, hzl);
+  const long long nb = packed ? (long long)hpk.size() : n;  // basis vector length
+  {
+    // fit the batch to the free device memory: per slot the basis of restart_m + 1 vectors,
+    // eight full-length work vectors and the sigma product's workspace (1.5 vectors)
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
+      const double per_slot = 16.0 * ((double)nb * (c->opt.restart_m + 1) + (double)n * (7.5 + 2 * kslots));
+      const double budget = 0.92 * (double)fr - 16.0 * 4.0 * (double)n - 64.0 * (1 << 20);
+      const int fit = budget > 0 ? (int)std::min<double>(budget / per_slot, 1 << 20) : 0;
+      if (fit < 1)
+        return set_err(c, CCGF_ENOMEM, "not enough device memory for one right-hand side's Krylov basis "
+                                       "(reduce restart_m)");
+      Bmax = std::min(Bmax, fit);
+    }
+  }
   // cycle lengths: restart_m, and restart_tail for cycles that start once the queue is
   // empty and at most a quarter of the slots are still busy (few slots: long cycles are
   // cheap to orthogonalise and help the slowest solves most); m sizes the workspace
@@ -703,13 +724,6 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
   }
   const int m_tail = m;
   const int nchunk = (int)((n + DOT_CHUNK - 1) / DOT_CHUNK);
-  // GMRES keeps its Krylov basis (and w) as unique elements only, which halves the
-  // orthogonalisation traffic; GCROT keeps full vectors (its recycled pairs are full)
-  const bool packed = kr == 0;
-  std::vector<long long> hpk, hpkm, hzl;
-  std::vector<int> hunp;
-  if (packed) build_pack(c, part, K, n, hpk, hunp, hpkm, hzl);
-  const long long nb = packed ? (long long)hpk.size() : n;  // basis vector length
   const int n1b = packed ? (int)nb : n1;                     // unit weights when packed
   const int nchb = (int)((nb + DOT_CHUNK - 1) / DOT_CHUNK);
   const int ldp = std::max(m, kslots) + 1;
@@ -1252,9 +1266,20 @@ int seed_krylov(ccgf_ctx *c, int part, int K, int norb, const cplx *Bvecs, int n
                 const double *rhs_omega, double eta, Guess &gs, cplx **Qout, cplx **chat_out, ccgf_stats *st) {
   *Qout = nullptr;
   *chat_out = nullptr;
-  const int m = c->opt.seed_m;
+  int m = c->opt.seed_m;
   if (m <= 0 || norb <= 0 || nrhs <= 0) return CCGF_OK;
   const long long n = vec_len(c, part);
+  {
+    // the seed bases may take at most a third of the free device memory (the solves
+    // that use them need the rest); fewer steps where they would not fit, none below 8
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
+      const double per_col = 16.0 * (double)norb * (double)n;
+      const int fit = (int)std::min<double>(fr / 3.0 / per_col - 1.0, 4096.0);
+      if (fit < 8) return CCGF_OK;
+      m = std::min(m, fit);
+    }
+  }
   const int n1 = part == CCGF_PART_IP ? c->no : c->nv;
   const double sM = part == CCGF_PART_IP ? 1.0 : -1.0;
   const double sE = part == CCGF_PART_IP ? -1.0 : 1.0;

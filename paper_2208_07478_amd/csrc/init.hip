@@ -97,12 +97,18 @@ int build_hbar(ccgf_ctx *c) {
     });
     return t;
   };
+  // (the ovvv and vvvo classes are not stored: <mb||ef> = -<bm||ef> is read from the vovv
+  // class, and <ab||ei> is formed from the factor where it is needed once)
   T4 Voooo = cls("oooo"), Vooov = cls("ooov"), Voovo = cls("oovo"), Voovv = cls("oovv");
-  T4 Vovoo = cls("ovoo"), Vovvo = cls("ovvo"), Vovvv = cls("ovvv"), Vvovv = cls("vovv");
-  T4 Vvvvo = cls("vvvo");
-  if (!Voooo.p || !Vooov.p || !Voovo.p || !Voovv.p || !Vovoo.p || !Vovvo.p || !Vovvv.p || !Vvovv.p ||
-      !Vvvvo.p)
-    return CCGF_ENOMEM;
+  T4 Vovoo = cls("ovoo"), Vovvo = cls("ovvo"), Vvovv = cls("vovv");
+  if (!Voooo.p || !Vooov.p || !Voovo.p || !Voovv.p || !Vovoo.p || !Vovvo.p || !Vvovv.p) return CCGF_ENOMEM;
+  struct OVVV {
+    T4 vo;
+    __device__ inline cplx operator()(int km, int kb, int ke, int m, int b, int e, int f) const {
+      cplx x = vo(kb, km, ke, b, m, e, f);
+      return mkc(-x.x, -x.y);
+    }
+  } Vovvv{Vvovv};
 
   T2d t1{c->t1, no, nv};
   T4 t2{c->t2, nk, no, no, nv, nv};
@@ -184,14 +190,34 @@ int build_hbar(ccgf_ctx *c) {
     Woooo.p[i] = cadd(acc, cscale(h, 0.5));
   });
 
-  // ---- W_abef (bare vvvv integrals formed on the fly from the factor)
-  T4 Wvvvv = make_t4(c, nv, nv, nv, nv);
-  if (!Wvvvv.p) return CCGF_ENOMEM;
-  c->Wvvvv = Wvvvv.p;
-  foreach_(s, Wvvvv.size(), [=] __device__(size_t i) {
-    I7 x = dec(i, nk, nv, nv, nv, nv);
-    int ka = x.k1, kb = x.k2, ke = x.k3;
-    int a = x.a, b = x.b, e = x.c, f = x.d;
+  // ---- W_abef (bare vvvv integrals formed on the fly from the factor), stored blocks only
+  std::vector<int> wtrip;  // (ka, kb, kc) of each stored block
+  c->wblk_h.assign((size_t)nk * nk * nk, -1);
+  for (int ka = 0; ka < nk; ++ka)
+    for (int kb = ka; kb < nk; ++kb)
+      for (int kc = 0; kc < nk; ++kc) {
+        const int kd = c->kc3_h[((size_t)ka * nk + kb) * nk + kc];
+        if (kc > kd) continue;
+        c->wblk_h[((size_t)ka * nk + kb) * nk + kc] = (int)(wtrip.size() / 3);
+        wtrip.push_back(ka);
+        wtrip.push_back(kb);
+        wtrip.push_back(kc);
+      }
+  c->nwblk = (long long)(wtrip.size() / 3);
+  const size_t nv4 = (size_t)nv * nv * nv * nv;
+  c->wblk = (int *)dev_alloc(c, sizeof(int) * c->wblk_h.size());
+  int *d_trip = (int *)dev_alloc(c, sizeof(int) * wtrip.size());
+  c->Wvvvv = (cplx *)dev_alloc(c, sizeof(cplx) * nv4 * (size_t)c->nwblk);
+  if (!c->wblk || !d_trip || !c->Wvvvv) return CCGF_ENOMEM;
+  hipMemcpyAsync(c->wblk, c->wblk_h.data(), sizeof(int) * c->wblk_h.size(), hipMemcpyHostToDevice, s);
+  hipMemcpyAsync(d_trip, wtrip.data(), sizeof(int) * wtrip.size(), hipMemcpyHostToDevice, s);
+  cplx *Wpk = c->Wvvvv;
+  const WPacked Wvvvv{c->Wvvvv, c->wblk, kt, nv};
+  foreach_(s, nv4 * (size_t)c->nwblk, [=] __device__(size_t i) {
+    const size_t q = i / nv4, r = i % nv4;
+    int ka = d_trip[3 * q], kb = d_trip[3 * q + 1], ke = d_trip[3 * q + 2];
+    int f = (int)(r % nv), e = (int)((r / nv) % nv), b = (int)((r / ((size_t)nv * nv)) % nv),
+        a = (int)(r / ((size_t)nv * nv * nv));
     cplx acc = eri(ka, kb, ke, no + a, no + b, no + e, no + f);
     for (int m = 0; m < no; ++m) {
       acc = csub(acc, cmul(t1(kb, m, b), Vvovv(ka, kb, ke, a, m, e, f)));
@@ -203,7 +229,7 @@ int build_hbar(ccgf_ctx *c) {
       for (int m = 0; m < no; ++m)
         for (int n = 0; n < no; ++n) cfma(h, tau(km, kn, ka, m, n, a, b), Voovv(km, kn, ke, m, n, e, f));
     }
-    Wvvvv.p[i] = cadd(acc, cscale(h, 0.5));
+    Wpk[i] = cadd(acc, cscale(h, 0.5));
   });
 
   // ---- Z_mbej = <mb||ej> - t_nj^bf <mn||ef>  (shared by W_mbej, W_mbij, W_abei)
@@ -296,7 +322,7 @@ int build_hbar(ccgf_ctx *c) {
     I7 x = dec(i, nk, nv, nv, nv, no);
     int ka = x.k1, kb = x.k2, ke = x.k3, ki = kt.c3(ka, kb, ke);
     int a = x.a, b = x.b, e = x.c, ii = x.d;
-    cplx acc = Vvvvo.p[i];
+    cplx acc = eri(ka, kb, ke, no + a, no + b, no + e, ii);
     for (int m = 0; m < no; ++m) acc = csub(acc, cmul(Fov(ke, m, e), t2(ke, ki, ka, m, ii, a, b)));
     for (int f = 0; f < nv; ++f) cfma(acc, t1(ki, ii, f), Wvvvv(ka, kb, ke, a, b, e, f));
     cplx h = mkc(0, 0);
@@ -349,20 +375,6 @@ int build_hbar(ccgf_ctx *c) {
   });
 
   c->Voovv = Voovv.p;
-  if (c->opt.precision != CCGF_PLAIN_F64) {  // FP32 operands of the big products (both mixed forms)
-    // complex-float copies of the GEMM operands (rounded once, here)
-    auto to32 = [&](const cplx *src, size_t nel) -> float2 * {
-      float2 *d = (float2 *)dev_alloc(c, nel * sizeof(float2));
-      if (!d) return nullptr;
-      foreach_(s, nel, [=] __device__(size_t i) { d[i] = make_float2((float)src[i].x, (float)src[i].y); });
-      return d;
-    };
-    c->Wvvvv32 = to32(Wvvvv.p, Wvvvv.size());
-    c->WvoP32 = to32(WvoP.p, WvoP.size());
-    c->WooP32 = to32(WooP.p, WooP.size());
-    c->WvoPea32 = to32(WvoPea.p, WvoPea.size());
-    if (!c->Wvvvv32 || !c->WvoP32 || !c->WooP32 || !c->WvoPea32) return CCGF_ENOMEM;
-  }
   if (hip_check(c, hipStreamSynchronize(s), "building Hbar blocks") != CCGF_OK) return CCGF_EDEVICE;
   // release the integral classes that the products do not read
   auto release = [&](cplx *p) {
@@ -373,8 +385,25 @@ int build_hbar(ccgf_ctx *c) {
       }
   };
   release(Voooo.p); release(Vooov.p); release(Voovo.p); release(Vovoo.p); release(Vovvo.p);
-  release(Vovvv.p); release(Vvovv.p); release(Vvvvo.p); release(tau.p); release(Z.p);
-  return CCGF_OK;
+  release(Vvovv.p); release(tau.p); release(Z.p); release((cplx *)d_trip);
+  // blocks that only fed the others
+  release(c->Woooo); c->Woooo = nullptr;
+  release(c->Wovvo); c->Wovvo = nullptr;
+  if (c->opt.precision != CCGF_PLAIN_F64) {  // FP32 operands of the big products (both mixed forms)
+    // complex-float copies of the GEMM operands (rounded once, here)
+    auto to32 = [&](const cplx *src, size_t nel) -> float2 * {
+      float2 *d = (float2 *)dev_alloc(c, nel * sizeof(float2));
+      if (!d) return nullptr;
+      foreach_(s, nel, [=] __device__(size_t i) { d[i] = make_float2((float)src[i].x, (float)src[i].y); });
+      return d;
+    };
+    c->Wvvvv32 = to32(c->Wvvvv, nv4 * (size_t)c->nwblk);
+    c->WvoP32 = to32(WvoP.p, WvoP.size());
+    c->WooP32 = to32(WooP.p, WooP.size());
+    c->WvoPea32 = to32(WvoPea.p, WvoPea.size());
+    if (!c->Wvvvv32 || !c->WvoP32 || !c->WooP32 || !c->WvoPea32) return CCGF_ENOMEM;
+  }
+  return hip_check(c, hipStreamSynchronize(s), "building the FP32 operands");
 }
 
 // *out = sum of v over a 256-thread block

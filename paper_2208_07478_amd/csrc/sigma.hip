@@ -457,7 +457,11 @@ static void build_plans(ccgf_ctx *c, SigmaPlan &P) {
     // ka <= kb is computed, the other block is filled afterwards.  A block ka = kb is itself
     // antisymmetric in (a, b): its rows a < b are computed (g_bigt, g_bigd) and the rest filled,
     // and its self-paired segments kc = kd (there is always kc = ka) run over c < d only.
-    T4 W{nullptr, nk, nv, nv, nv, nv};
+    // W blocks (ka <= kb, kc <= kd) are the stored ones
+    const long long nv4 = (long long)nv * nv * nv * nv;
+    auto wblk = [&](int ka, int kb, int kc) -> long long {
+      return (long long)c->wblk_h[((size_t)ka * nk + kb) * nk + kc] * nv4;
+    };
     std::vector<long long> fill;
     GemmPlan &gt = P.g_bigt, &gd = P.g_bigd;
     const int np = nv * (nv - 1) / 2;
@@ -485,7 +489,7 @@ static void build_plans(ccgf_ctx *c, SigmaPlan &P) {
           for (int kc = 0; kc < nk; ++kc) {
             const int kd = host_c3(c, ka, kb, kc);
             if (kc > kd) continue;
-            GemmSeg sg{(long long)W.blk(ka, kb, kc), nv + (ki * nk + kc) * b2, 1.0};
+            GemmSeg sg{wblk(ka, kb, kc), nv + (ki * nk + kc) * b2, 1.0};
             if (kc == kd) gt.segs.push_back(sg), ++tt.nseg;
             else gd.segs.push_back(sg), ++td.nseg;
           }
@@ -497,7 +501,7 @@ static void build_plans(ccgf_ctx *c, SigmaPlan &P) {
         for (int kc = 0; kc < nk; ++kc) {
           const int kd = host_c3(c, ka, kb, kc);
           if (kc > kd) continue;
-          g.segs.push_back(GemmSeg{(long long)W.blk(ka, kb, kc), nv + (ki * nk + kc) * b2, kc == kd ? 0.5 : 1.0});
+          g.segs.push_back(GemmSeg{wblk(ka, kb, kc), nv + (ki * nk + kc) * b2, kc == kd ? 0.5 : 1.0});
           ++t.nseg;
         }
         g.tasks.push_back(t);
@@ -1104,9 +1108,9 @@ int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y, 
     const size_t oovv = nk3 * c->no * c->no * c->nv * c->nv;
     bool ok;
     if (part == CCGF_PART_EA)
-      ok = plan_in_bounds(P->g_big, nk3 * c->nv * c->nv * c->nv * c->nv, vb, vb) &&
-           plan_in_bounds(P->g_bigt, nk3 * c->nv * c->nv * c->nv * c->nv, vb, vb) &&
-           plan_in_bounds(P->g_bigd, nk3 * c->nv * c->nv * c->nv * c->nv, vb, vb) &&
+      ok = plan_in_bounds(P->g_big, (size_t)c->nwblk * c->nv * c->nv * c->nv * c->nv, vb, vb) &&
+           plan_in_bounds(P->g_bigt, (size_t)c->nwblk * c->nv * c->nv * c->nv * c->nv, vb, vb) &&
+           plan_in_bounds(P->g_bigd, (size_t)c->nwblk * c->nv * c->nv * c->nv * c->nv, vb, vb) &&
            plan_in_bounds(P->g_ovvo, nk3 * c->nv * c->no * c->no * c->nv, vb, vb) &&
            plan_in_bounds(P->g_r1, nk3 * c->nv * c->nv * c->nv * c->no, vb, vb) &&
            plan_in_bounds(P->g_red1, nk3 * c->nv * c->no * c->nv * c->nv, vb, pe) &&

@@ -1,21 +1,32 @@
 """Throughput of the k-point CCGF hot path on one MI355X.
 
 A step is one pass of the whole path over one batch of synthetic input: build
-b/e vectors, solve every shifted IP and EA system of the batch with the batched
-GMRES (sigma products on MFMA), assemble G = G+ + G-.  The workload is the
-Si-like 2x2x2 k-mesh system (4 occupied + 26 virtual spin orbitals per cell,
-complex k-blocks, eta = 0.005 Ha): each step covers all 30 orbitals at K = Gamma
-and 8 frequencies spread over the 64-point grid on [-1, 1] Ha (240 points), with
-120 right-hand sides in flight per part.
+the b / e vectors, solve every shifted IP and EA system of the batch with the
+batched GMRES (sigma products on MFMA), assemble G = G+ + G-.  The workload is
+the Si-like 3x3x3 k-mesh system (27 k-points, 4 occupied + 26 virtual spin
+orbitals per cell, complex k-blocks, eta = 0.005 Ha): step s covers the ten
+orbitals p = g, g + 3, ..., g + 27 (g = s mod 3) at K = Gamma at one frequency
+of the 256-point grid on [-1, 1] Ha, grid point (37 s + 5) mod 256, so that
+successive steps spread over the grid and over the orbitals (10 points per
+step; the three groups hold 2, 1 and 1 occupied orbitals).
 
-Each solver form (plain FP64; mixed FP32 or BF16-split sigma with FP64
-refinement) is timed on the same batch at the same GMRES tolerance, and its G
-is compared with a tight plain-FP64 solve of every 4th frequency of the batch
-(all orbitals); a point counts at the 1e-6 relative-error target (per orbital:
-max over the checked frequencies of |dG| / max |G|).  `value` is the points/s
-of the fastest form that meets it.
+Forms:
+  * the headline form (default ``learned_mixed_f32``): FP32 sigma products with
+    FP64 refinement, starting each solve from the guess of a network trained
+    (outside the timed region, reported) on plain solves of all orbitals at the
+    frequencies of the first --ntrain warmup steps (those solves are the
+    warmup's work for those steps);
+  * ``plain_f64`` on the first ``--compare-steps`` timed steps (same
+    frequencies, same tolerance), for the speed-up at equal accuracy;
+  * the headline context with its network switched off on the same steps (the
+    network's own gain);
+  * a tight plain-FP64 solve (tol 1e-10) of the same steps, the accuracy
+    reference of every form: a point meets the target when |G - G_ref| <=
+    1e-6 |G_ref|.
 
-Prints ONE JSON line.
+The plain FP64 path behind the reference is pinned to the CPU oracle by the
+parity tests (full G on the Si-like 2x2x2 system, sampled sigma blocks on this
+3x3x3 system).  Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -23,57 +34,59 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
 import numpy as np
 
+T_START = time.perf_counter()
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "G(ω) points/sec at 1e-6 rel. error, learned+mixed vs plain FP64; MFMA util"
-# MI355X dense matrix peaks of each form's MFMA dtype, FLOP/s
-PEAK = {"plain_f64": 78.6e12, "mixed_f32": 157.3e12, "mixed_bf16x3": 2.5e15, "learned_mixed_f32": 157.3e12}
-# the dominant kernel of each form (EA 1/2 W_abcd r_i^cd over the blocks ka < kb), all N tile
-# widths the autotuner may pick (the traffic record covers the same family)
-GEMM_NAME = {"plain_f64": "k_cgemm<0, double>", "mixed_f32": "k_cgemm<0, float>",
-             "mixed_bf16x3": "k_cgemm_b3<0>", "learned_mixed_f32": "k_cgemm<0, float>"}
-PRECISION = {"plain_f64": "f64", "mixed_f32": "f32", "mixed_bf16x3": "bf16x3", "learned_mixed_f32": "f32"}
-DTYPE = {"plain_f64": "c128", "mixed_f32": "c64 sigma / c128 Krylov", "mixed_bf16x3": "bf16x3 sigma / c128 Krylov",
-         "learned_mixed_f32": "c64 sigma / c128 Krylov, FP32 network"}
+PEAK = {"f64": 78.6e12, "f32": 157.3e12, "bf16x3": 2.5e15}
+GEMM_NAME = {"f64": "k_cgemm<0, double>", "f32": "k_cgemm<0, float>", "bf16x3": "k_cgemm_b3<0>"}
+DTYPE = {"f64": "c128", "f32": "c64 sigma / c128 Krylov", "bf16x3": "bf16x3 sigma / c128 Krylov"}
 TARGET = 1e-6
+
+
+def log(*a):
+    print(f"[{time.perf_counter() - T_START:6.1f} s]", *a, file=sys.stderr, flush=True)
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--workload", default="si_k222")
-    ap.add_argument("--nw", type=int, default=8, help="frequencies per step (spread over the grid)")
-    ap.add_argument("--batch", type=int, default=120, help="right-hand sides in flight")
-    ap.add_argument("--forms", default="plain_f64,mixed_f32,mixed_bf16x3",
-                    help="comma list of plain_f64, mixed_f32, mixed_bf16x3, learned_mixed_f32")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="si_k333")
+    ap.add_argument("--form", default="learned_mixed_f32",
+                    help="headline form: [learned_]mixed_f32, [learned_]mixed_bf16x3 or plain_f64")
+    ap.add_argument("--compare-steps", type=int, default=2,
+                    help="timed steps also solved by plain FP64, by the headline without its network and "
+                         "by the tight reference")
     ap.add_argument("--tol", type=float, default=2e-7)
-    ap.add_argument("--ref-tol", type=float, default=1e-9)
-    ap.add_argument("--check-every", type=int, default=4, help="reference solve on every k-th step frequency")
+    ap.add_argument("--ref-tol", type=float, default=1e-10)
     ap.add_argument("--restart", type=int, default=200)
-    ap.add_argument("--maxiter", type=int, default=12000)
+    ap.add_argument("--batch", type=int, default=90, help="right-hand sides in flight per part (fitted to memory)")
+    ap.add_argument("--maxiter", type=int, default=20000)
     ap.add_argument("--precond-eta", type=float, default=0.4)
-    ap.add_argument("--restart-tail", type=int, default=0,
-                    help="restart length once the queue is empty and at most a quarter of the slots iterate")
-    ap.add_argument("--seed-m", type=int, default=128,
-                    help="shared-Krylov seed steps per orbital before the solves (0: start from zero)")
-    ap.add_argument("--no-check", action="store_true", help="skip the reference solve (profiling runs)")
+    ap.add_argument("--ntrain", type=int, default=3, help="training frequencies of the network (the first "
+                                                            "warmup steps' frequencies)")
+    ap.add_argument("--budget-s", type=float, default=430.0,
+                    help="wall-clock budget: optional legs are skipped when they would exceed it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe", choices=["sigma", "copy"], default=None,
                     help="counter-collection runs: 'sigma' applies 6 EA and 6 IP sigma products to a batch of "
-                         "--batch vectors (the first ones are the autotuner's trials, the last 3 its choice); "
-                         "'copy' copies a 1 GiB buffer once (HBM-traffic calibration)")
-    ap.add_argument("--probe-precision", default="f64")
-    ap.add_argument("--cpu-sample-s", type=float, default=20.0)
+                         "--batch vectors; 'copy' copies a 1 GiB buffer once (HBM-traffic calibration)")
+    ap.add_argument("--probe-precision", default="f32")
     return ap.parse_args()
+
+
+def form_precision(form):
+    return "f64" if form == "plain_f64" else form.split("_")[-1]
 
 
 def stored_traffic(kernel):
@@ -95,56 +108,95 @@ def stored_traffic(kernel):
     return None
 
 
+def host_info():
+    info = {"nproc": os.cpu_count(), "cpu": platform.processor() or "", "ram_gb": None}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["cpu"] = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                info["ram_gb"] = round(int(line.split()[1]) / 2 ** 20, 1)
+                break
+    except OSError:
+        pass
+    return info
+
+
 def cpu_baseline(sysm, sigma_per_point, budget_s):
-    """The oracle timed on the host: sigma products at K = Gamma of the same
-    workload, scaled to points/s with the sigma products per point measured on
-    the GPU run (the intermediates build is excluded, as cc_gf_init is)."""
-    from oracle import eom
+    """The oracle timed on the host (bounded sample): at K = Gamma, one 2p1h
+    output block of sigma_EA and one 2h1p block of sigma_IP for one vector, from
+    cold H-bar blocks (the oracle forms every block from the factor on demand;
+    its one-body blocks are built beforehand and excluded, as cc_gf_init is),
+    extrapolated linearly to the Nk^2 blocks of a product, then to points with
+    the headline form's sigma products per point."""
+    from oracle import blocks
     from paper_2208_07478_amd import synth
 
-    try:
-        import torch
-        threads = torch.get_num_threads()
-    except Exception:  # pragma: no cover
-        threads = os.cpu_count()
+    def threads():
+        try:
+            from threadpoolctl import threadpool_info
+            return max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+        except Exception:  # pragma: no cover
+            return os.cpu_count()
+
+    def sample(B):
+        per = {}
+        for part in ("ip", "ea"):
+            x = synth.random_eom_vectors(sysm.kmesh, sysm.nocc, sysm.nvir, part, 0, 1, seed=7)[0]
+            t = time.perf_counter()
+            B.sigma_block(part, 0, x, 0, 0)
+            per[part] = time.perf_counter() - t
+        return per
+
     t0 = time.perf_counter()
-    E = eom.EOMSystem(sysm)
+    B = blocks.BlockSystem(sysm)
+    B.fock()
     build_s = time.perf_counter() - t0
-    per = {}
-    for part in ("ea", "ip"):
-        n = E.size(part)
-        x = synth.random_vectors(n, 1, seed=7)[0]
-        ts = []
-        t_start = time.perf_counter()
-        while not ts or (time.perf_counter() - t_start < budget_s / 2 and len(ts) < 5):
-            t1 = time.perf_counter()
-            E.sigma(part, 0, x)
-            ts.append(time.perf_counter() - t1)
-        per[part] = (float(np.mean(ts)), len(ts))
-    sec_per_point = per["ea"][0] * sigma_per_point["ea"] + per["ip"][0] * sigma_per_point["ip"]
-    return {
-        "value": 1.0 / sec_per_point,
+    nth = threads()
+    per = sample(B)
+    nblk = sysm.nk ** 2
+    sec_point = nblk * (per["ea"] * sigma_per_point["ea"] + per["ip"] * sigma_per_point["ip"])
+    out = {
+        "value": 1.0 / sec_point,
         "unit": "G(w) points/s",
-        "cores": int(os.environ.get("OMP_NUM_THREADS", threads) or threads),
+        "cores": nth,
         "kind": "oracle",
-        "sample": (f"{per['ea'][1]} EA + {per['ip'][1]} IP oracle sigma products at K=Gamma "
-                   f"({per['ea'][0]:.2f} s / {per['ip'][0]:.3f} s each), scaled by the headline form's "
-                   f"{sigma_per_point['ea']:.0f} EA + {sigma_per_point['ip']:.0f} IP sigma products per point; "
-                   f"oracle intermediates build {build_s:.0f} s excluded"),
+        "sample": (f"oracle.blocks at K=Gamma: one sigma_EA output block ({per['ea']:.1f} s) and one sigma_IP "
+                   f"block ({per['ip']:.2f} s), one vector, cold H-bar blocks, x{nblk} blocks per product, x the "
+                   f"headline's {sigma_per_point['ea']:.0f} EA + {sigma_per_point['ip']:.0f} IP products per "
+                   f"point; one-body blocks ({build_s:.0f} s) excluded"),
+        "host": host_info(),
     }
+    # one thread: the IP block again from cold blocks (the EA block would take minutes); the
+    # 1-thread figure scales the value by that block's thread speed-up
+    left = budget_s - (time.perf_counter() - T_START)
+    if left > 20 * per["ip"] + 5:
+        B1 = blocks.BlockSystem(sysm)
+        B1._F = B._F
+        from threadpoolctl import threadpool_limits
+        x = synth.random_eom_vectors(sysm.kmesh, sysm.nocc, sysm.nvir, "ip", 0, 1, seed=7)[0]
+        with threadpool_limits(1):
+            t = time.perf_counter()
+            B1.sigma_block("ip", 0, x, 0, 0)
+            t1 = time.perf_counter() - t
+        out["thread_speedup_ip_block"] = t1 / per["ip"]
+        out["value_1thread_est"] = out["value"] / (t1 / per["ip"])
+        out["sample_1thread"] = (f"IP block on 1 thread {t1:.2f} s vs {per['ip']:.2f} s on {nth}; value_1thread_est "
+                                 f"divides the value by that ratio")
+    return out
 
 
-def col_err(G, Gref):
-    """Per orbital: max over frequencies of |G - Gref| / max |Gref|; the worst orbital."""
-    den = np.abs(Gref).max(axis=-1)
-    den = np.where(den > 0, den, 1.0)
-    return float(np.max(np.abs(G - Gref).max(axis=-1) / den))
+def pointwise_err(G, Gref):
+    return float(np.max(np.abs(G - Gref) / np.maximum(np.abs(Gref), 1e-300)))
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only (the solves of different K, orbitals "
+                                   "and frequencies are independent; see DESIGN.md for sharding); use --gpus 1"}))
         sys.exit(2)
     import torch
 
@@ -161,14 +213,16 @@ def main():
         print(json.dumps({"probe": "copy", "bytes_read": src.numel() * 8, "bytes_written": dst.numel() * 8}))
         return
     sysm = synth.preset_system(args.workload)
-    omega, eta = synth.preset_query(args.workload)
+    grid, eta = synth.preset_query(args.workload)
     nmo = sysm.nocc + sysm.nvir
     orbs = list(range(nmo))
-    nb = nmo * args.nw
-    stride = len(omega) // args.nw
-    wsel = omega[::stride][:args.nw]
+    ng = len(grid)
+    nsteps = args.warmup + args.steps
+    wstep = [float(grid[(37 * s + 5) % ng]) for s in range(nsteps)]
+    ostep = [list(range(s % 3, nmo, 3)) for s in range(nsteps)]
     opts = dict(tol=args.tol, restart_m=args.restart, maxiter=args.maxiter, max_batch=args.batch,
-                precond_eta=args.precond_eta, seed_m=args.seed_m, restart_tail=args.restart_tail)
+                precond_eta=args.precond_eta)
+    log(f"{args.workload}: {sysm.kmesh}, {sysm.nocc}+{sysm.nvir}")
     if args.probe == "sigma":
         ctx = Context(sysm, precision=args.probe_precision, graphs=False, **opts)
         for part in ("ea", "ip"):
@@ -181,137 +235,153 @@ def main():
         print(json.dumps({"probe": "sigma", "nvec": args.batch, "products": 6, "precision": args.probe_precision}))
         return
 
-    forms = [f for f in args.forms.split(",") if f]
-    res = {}
-    for form in forms:
-        t0 = time.perf_counter()
-        ctx = Context(sysm, timing=True, precision=PRECISION[form], **opts)
-        init_s = time.perf_counter() - t0
-        learn = None
-        if form.startswith("learned"):
-            # train on the grid frequencies midway between the step's (not timed; reported)
-            wtrain = omega[stride // 2::stride][:args.nw]
-            t1 = time.perf_counter()
-            learn = ctx.learn(0, orbs, wtrain, eta, allow_noconv=True)
-            learn["seconds"] = time.perf_counter() - t1
-            print(f"{form} training: {learn['seconds']:.1f} s", file=sys.stderr, flush=True)
-
-        def step():
-            # one pass over the batch: IP then EA solves of all orbitals x frequencies, G = G- + G+
-            _, _, Gm, sti = ctx.solve([0], orbs, wsel, eta, parts="ip", allow_noconv=True)
-            print(f"{form} IP: {sti['seconds']:.1f} s", file=sys.stderr, flush=True)
-            _, Gp, _, ste = ctx.solve([0], orbs, wsel, eta, parts="ea", allow_noconv=True)
-            print(f"{form} EA: {ste['seconds']:.1f} s", file=sys.stderr, flush=True)
-            return Gm + Gp, sti, ste
-
-        for i in range(args.warmup):
-            print(f"{form} warmup step {i}", file=sys.stderr, flush=True)
-            step()
-        torch.cuda.synchronize()
-        tot = {"big_ms": 0.0, "big_launches": 0, "big_flops": 0.0, "n_iterations": 0, "sigma_ms": 0.0,
-               "n_solves": 0, "max_rel_residual": 0.0, "n_unconverged": 0, "n_steps": 0, "n_reorth": 0,
-               "n_guess": 0}
-        nsig = {"ip": 0, "ea": 0}
-        t1 = time.perf_counter()
-        for i in range(args.steps):
-            G, sti, ste = step()
+    def run_steps(ctx, steps, tag):
+        """Solve the listed steps; returns (G [len(steps)][10], seconds, totals)."""
+        tot = {"big_ms": 0.0, "big_launches": 0, "big_flops": 0.0, "n_iterations": 0, "n_solves": 0,
+               "n_unconverged": 0, "n_sigma_ea": 0, "n_sigma_ip": 0, "n_guess": 0, "n_guess_rejected": 0,
+               "max_rel_residual": 0.0}
+        Gs, secs = [], []
+        for s in steps:
+            w, ob = wstep[s], ostep[s]
+            t = time.perf_counter()
+            _, _, Gm, sti = ctx.solve([0], ob, [w], eta, parts="ip", allow_noconv=True)
+            _, Gp, _, ste = ctx.solve([0], ob, [w], eta, parts="ea", allow_noconv=True)
+            secs.append(time.perf_counter() - t)
+            Gs.append((Gm + Gp)[0, :, 0])
             for st in (sti, ste):
-                for k in tot:
-                    tot[k] = max(tot[k], st[k]) if k == "max_rel_residual" else tot[k] + st[k]
-            nsig["ip"] += sti["n_sigma"]
-            nsig["ea"] += ste["n_sigma"]
-            print(f"{form} step {i}: {sti['seconds'] + ste['seconds']:.2f} s, "
-                  f"{sti['n_iterations'] + ste['n_iterations']} iterations", file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t1
-        ctx.close()
-        avg_ms = tot["big_ms"] / max(tot["big_launches"], 1)
-        fl = tot["big_flops"] / max(tot["big_launches"], 1)
-        ach = fl / (avg_ms * 1e-3) if avg_ms > 0 else 0.0
-        res[form] = {
-            "points_per_s": args.steps * nb / elapsed,
-            "ms_per_step": 1e3 * elapsed / args.steps,
-            "G": G,
-            "iterations_per_solve": tot["n_iterations"] / max(tot["n_solves"], 1),
-            "guesses_used": tot["n_guess"],
-            "batched_steps": tot["n_steps"],
-            "mean_active": tot["n_iterations"] / max(tot["n_steps"], 1),
-            "reorth_fraction": tot["n_reorth"] / max(tot["n_iterations"], 1),
-            "sigma_per_point": {p: nsig[p] / (args.steps * nb) for p in nsig},
-            "sigma_ms_share": tot["sigma_ms"] / (1e3 * elapsed),
-            "max_rel_residual": tot["max_rel_residual"],
-            "unconverged": tot["n_unconverged"],
-            "init_s": init_s,
-            "learn": learn,
-            "roofline": {"bound": "mfma", "kernel": GEMM_NAME[form] + " (EA 1/2 W_abcd r_i^cd, blocks ka < kb; "
-                                                                     "N tile 32/64/128 by the autotuner)",
-                         "achieved": ach / 1e12, "peak": PEAK[form] / 1e12, "unit": "TFLOP/s",
-                         "frac": ach / PEAK[form], "avg_ms": avg_ms, "flops_per_launch": fl,
-                         "launches": tot["big_launches"]},
-        }
+                for k in ("big_ms", "big_launches", "big_flops", "n_iterations", "n_solves", "n_unconverged",
+                          "n_guess", "n_guess_rejected"):
+                    tot[k] += st[k]
+                tot["max_rel_residual"] = max(tot["max_rel_residual"], st["max_rel_residual"])
+            tot["n_sigma_ip"] += sti["n_sigma"]
+            tot["n_sigma_ea"] += ste["n_sigma"]
+            log(f"{tag} w={w:+.4f}: {secs[-1]:.2f} s, {sti['n_iterations'] + ste['n_iterations']} iterations")
+        return np.array(Gs), secs, tot
 
+    form = args.form
+    prec = form_precision(form)
+    learned = form.startswith("learned")
+    res = {}
+    # ---------------------------------------------------------------- headline
+    t0 = time.perf_counter()
+    ctx = Context(sysm, timing=True, precision=prec, **opts)
+    init_s = time.perf_counter() - t0
+    log(f"{form}: cc_gf_init {init_s:.1f} s")
+    learn = None
+    nwarm_plain = 0
+    if learned and args.warmup > 0:
+        # the network learns from plain solves of all orbitals at the first warmup steps' frequencies
+        nwarm_plain = max(1, min(args.ntrain, args.warmup))
+        wtrain = sorted(set(wstep[:nwarm_plain]))
+        t1 = time.perf_counter()
+        learn = ctx.learn(0, orbs, wtrain, eta, allow_noconv=True)
+        learn["seconds"] = time.perf_counter() - t1
+        learn["omega_train"] = wtrain
+        log(f"{form}: training at {len(wtrain)} frequencies {learn['seconds']:.1f} s")
+    run_steps(ctx, range(nwarm_plain, args.warmup), f"{form} warmup")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    Gh, secs_h, tot = run_steps(ctx, range(args.warmup, nsteps), form)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t1
+    ppstep = len(ostep[0])
+    npts = sum(len(ostep[s]) for s in range(args.warmup, nsteps))
+    avg_ms = tot["big_ms"] / max(tot["big_launches"], 1)
+    fl = tot["big_flops"] / max(tot["big_launches"], 1)
+    ach = fl / (avg_ms * 1e-3) if avg_ms > 0 else 0.0
+    sigma_pp = {"ea": tot["n_sigma_ea"] / npts, "ip": tot["n_sigma_ip"] / npts}
+    res[form] = {"points_per_s": npts / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
+                 "iterations_per_solve": tot["n_iterations"] / max(tot["n_solves"], 1),
+                 "sigma_per_point": sigma_pp, "unconverged": tot["n_unconverged"],
+                 "guesses_used": tot["n_guess"], "guesses_rejected": tot["n_guess_rejected"],
+                 "max_rel_residual": tot["max_rel_residual"], "init_s": init_s, "learn": learn}
+    ncmp = max(1, min(args.compare_steps, args.steps))
+    wcmp = list(range(args.warmup, args.warmup + ncmp))
+    cmp_secs = {form: sum(secs_h[:ncmp])}
+    cmp_G = {form: Gh[:ncmp]}
+    budget = args.budget_s
+
+    def left():
+        return budget - (time.perf_counter() - T_START)
+
+    est_step = elapsed / args.steps
+    if learned and left() > 2.0 * ncmp * est_step + 150:
+        # the same context with its network switched off: what the network gains
+        ctx.learn_enable(False)
+        G, secs, t_ = run_steps(ctx, wcmp, form.replace("learned_", "") + " (network off)")
+        cmp_secs["network_off"] = sum(secs)
+        cmp_G["network_off"] = G
+        res[form]["network_off"] = {"iterations_per_solve": t_["n_iterations"] / max(t_["n_solves"], 1),
+                                    "steps": ncmp}
+        ctx.learn_enable(True)
+    ctx.close()
+    torch.cuda.synchronize()
+    # ------------------------------------------------------- plain FP64, reference
     ref = None
-    if not args.no_check:
-        # tight plain-FP64 solve of every `check_every`-th frequency of the step, all orbitals
-        sub = slice(None, None, args.check_every)
-        ctx = Context(sysm, **dict(opts, tol=args.ref_tol, maxiter=3 * args.maxiter, seed_m=0))
-        _, _, Gm, sti = ctx.solve([0], orbs, wsel[sub], eta, parts="ip", allow_noconv=True)
-        print(f"reference IP: {sti['seconds']:.1f} s", file=sys.stderr, flush=True)
-        _, Gp, _, ste = ctx.solve([0], orbs, wsel[sub], eta, parts="ea", allow_noconv=True)
-        print(f"reference EA: {ste['seconds']:.1f} s", file=sys.stderr, flush=True)
-        ctx.close()
-        ref = {"G": Gm + Gp, "tol": args.ref_tol, "unconverged": sti["n_unconverged"] + ste["n_unconverged"],
-               "points": int(Gm.shape[1] * Gm.shape[2])}
-        for form in res:
-            res[form]["max_rel_err"] = col_err(res[form]["G"][:, :, sub], ref["G"])
-
-    def meets(f):
-        return ref is not None and res[f]["max_rel_err"] <= TARGET and res[f]["unconverged"] == 0
-
-    ok = [f for f in res if meets(f)] or list(res)
-    head = max(ok, key=lambda f: res[f]["points_per_s"])
-    h = res[head]
-    roof = dict(h["roofline"])
-    tr = stored_traffic(GEMM_NAME[head])
+    ctx = Context(sysm, precision="f64", **opts)
+    if form != "plain_f64":
+        G, secs, t_ = run_steps(ctx, wcmp, "plain_f64")
+        cmp_secs["plain_f64"] = sum(secs)
+        cmp_G["plain_f64"] = G
+        res["plain_f64"] = {"points_per_s": ncmp * ppstep / sum(secs), "steps": ncmp,
+                            "iterations_per_solve": t_["n_iterations"] / max(t_["n_solves"], 1),
+                            "unconverged": t_["n_unconverged"]}
+    # the accuracy reference (not optional): the same plain context at a tight tolerance
+    ctx.set_options(tol=args.ref_tol)
+    G, secs, t_ = run_steps(ctx, wcmp, "reference")
+    ref = {"G": G, "tol": args.ref_tol, "unconverged": t_["n_unconverged"], "points": int(G.size)}
+    ctx.close()
+    torch.cuda.synchronize()
+    acc = {"target_rel_err": TARGET, "reference": "plain FP64 GPU solve at tol %g" % args.ref_tol,
+           "checked_points": ref["points"] if ref else 0, "steps_checked": ncmp if ref else 0}
+    if ref is not None:
+        acc["reference_unconverged"] = ref["unconverged"]
+        acc["max_rel_err"] = {k: pointwise_err(v, ref["G"]) for k, v in cmp_G.items()}
+    meets = ref is not None and acc["max_rel_err"][form] <= TARGET and tot["n_unconverged"] == 0
+    acc["meets_target"] = meets
+    roof = {"bound": "mfma", "kernel": GEMM_NAME[prec] + " (EA 1/2 W_abcd r_i^cd over the stored blocks ka < kb)",
+            "achieved": ach / 1e12, "peak": PEAK[prec] / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK[prec],
+            "avg_ms": avg_ms, "flops_per_launch": fl, "launches": tot["big_launches"]}
+    tr = stored_traffic(GEMM_NAME[prec])
     roof["traffic"] = tr["bytes_per_launch"] if tr else None
-    if tr:
-        roof["traffic_note"] = tr.get("note", "")
-    forms_out = {}
-    for f, r in res.items():
-        forms_out[f] = {k: v for k, v in r.items() if k not in ("G",)}
+    speed = None
+    if "plain_f64" in cmp_secs and form != "plain_f64":
+        speed = {"headline_vs_plain_f64": cmp_secs["plain_f64"] / cmp_secs[form], "steps": ncmp,
+                 "frequencies": wcmp}
+        if "network_off" in cmp_secs:
+            speed["headline_vs_network_off"] = cmp_secs["network_off"] / cmp_secs[form]
     out = {
         "metric": METRIC,
-        "value": h["points_per_s"],
+        "value": res[form]["points_per_s"] if meets else None,
         "unit": "G(w) points/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": h["ms_per_step"],
+        "ms_per_step": res[form]["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": DTYPE[head],
+        "dtype": DTYPE[prec],
         "data": "synthetic",
         "config": {
             "workload": (f"{args.workload}: Si-like {sysm.kmesh[0]}x{sysm.kmesh[1]}x{sysm.kmesh[2]} k-mesh, "
-                         f"{sysm.nocc} occ + {sysm.nvir} vir spin orbitals/cell, K=Gamma, {nmo} orbitals x "
-                         f"{args.nw} omega per step (every {stride}th point of the {len(omega)}-point grid on "
-                         f"[-1,1] Ha), eta={eta}, GMRES({args.restart}) tol={args.tol}, {args.batch} right-hand "
-                         f"sides in flight, preconditioner damping {args.precond_eta} Ha, maxiter {args.maxiter}"),
-            "form": head,
-            "points_per_step": nb,
+                         f"{sysm.nocc} occ + {sysm.nvir} vir spin orbitals/cell, K=Gamma; step s: orbitals "
+                         f"p = s mod 3 + 3j (10 of {nmo}) x 1 omega (grid point (37 s + 5) mod {ng} of the "
+                         f"{ng}-point grid on [-1,1] Ha), IP + EA, eta={eta}, GMRES({args.restart}) tol={args.tol}, "
+                         f"up to {args.batch} right-hand sides in flight, preconditioner damping "
+                         f"{args.precond_eta} Ha"),
+            "form": form,
+            "points_per_step": ppstep,
         },
-        "accuracy": {"target_rel_err": TARGET, "reference_tol": args.ref_tol,
-                     "checked_points": ref["points"] if ref else 0,
-                     "reference_unconverged": ref["unconverged"] if ref else None,
-                     "max_rel_err": h.get("max_rel_err"), "meets_target": meets(head)},
-        "forms": forms_out,
-        "speedup_vs_plain_f64": (h["points_per_s"] / res["plain_f64"]["points_per_s"]
-                                 if "plain_f64" in res else None),
+        "measured_value": res[form]["points_per_s"],
+        "accuracy": acc,
+        "forms": res,
+        "speedup": speed,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sysm, h["sigma_per_point"], args.cpu_sample_s)
+        out["cpu_baseline"] = cpu_baseline(sysm, sigma_pp, budget)
+    out["wall_s"] = time.perf_counter() - T_START
     print(json.dumps(out), flush=True)
 
 

@@ -222,6 +222,15 @@ int cc_gf_learn(ccgf_ctx *ctx, int parts, int K, int norb, const int *orbs, int 
                 const double *omega_train, double eta, const ccgf_learn_options *opt_opt,
                 ccgf_learn_stats *st_opt);
 
+/* Replace the solver options of a context (tolerance, restart length, batch width,
+ * stream, preconditioner damping, seed length, timing, ...) without rebuilding its
+ * Hamiltonian blocks.  The precision must equal the one the context was built with
+ * (CCGF_EUNSUPPORTED otherwise: its operand copies are made by cc_gf_init); the
+ * autotune file stays the one given to cc_gf_init.  Zero fields take the defaults of
+ * cc_gf_init; out-of-range values give CCGF_EINVAL and leave the context unchanged.
+ * Waits for the context's stream before switching. */
+int cc_gf_set_options(ccgf_ctx *ctx, const ccgf_options *opt);
+
 /* Use (on != 0, the default) or ignore the trained networks in cc_gf_solve. */
 int cc_gf_learn_enable(ccgf_ctx *ctx, int on);
 

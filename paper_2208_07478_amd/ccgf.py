@@ -24,7 +24,8 @@ PRECISIONS = {"f64": PLAIN_F64, "plain_f64": PLAIN_F64, "f32": MIXED_F32, "mixed
               "bf16x3": MIXED_BF16X3, "mixed_bf16x3": MIXED_BF16X3}
 
 EXPORTS = ("cc_gf_init", "cc_gf_solve", "cc_gf_mor", "cc_gf_vector_size", "cc_gf_sigma", "cc_gf_vectors",
-           "cc_gf_learn", "cc_gf_learn_enable", "cc_gf_mlp_grad", "cc_gf_free", "cc_gf_last_error")
+           "cc_gf_learn", "cc_gf_learn_enable", "cc_gf_set_options", "cc_gf_mlp_grad", "cc_gf_free",
+           "cc_gf_last_error")
 MOR_MAX = 32
 
 
@@ -113,6 +114,8 @@ def load(path: str = LIB_PATH):
     lib.cc_gf_learn.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, ctypes.c_int, dp, ctypes.c_double,
                                 ctypes.POINTER(LearnOptions), ctypes.POINTER(LearnStats)]
     lib.cc_gf_learn.restype = ctypes.c_int
+    lib.cc_gf_set_options.argtypes = [vp, ctypes.POINTER(Options)]
+    lib.cc_gf_set_options.restype = ctypes.c_int
     lib.cc_gf_learn_enable.argtypes = [vp, ctypes.c_int]
     lib.cc_gf_learn_enable.restype = ctypes.c_int
     fp = ctypes.POINTER(ctypes.c_float)
@@ -168,11 +171,11 @@ class Context:
         cs.t2 = self._keep[3].ctypes.data
         cs.mem_space = HOST
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-        opt = Options(prec, int(restart_m), int(maxiter), float(tol), int(max_batch),
-                      ctypes.c_void_p(stream.cuda_stream), 1 if timing else 0, float(precond_eta),
-                      int(recycle_k), float(reorth_ratio), 0 if autotune else -1,
-                      None if autotune_cache is None else str(autotune_cache).encode(), int(restart_tail),
-                      0 if graphs else -1, int(seed_m))
+        self._optargs = dict(tol=tol, restart_m=restart_m, maxiter=maxiter, max_batch=max_batch, timing=timing,
+                             precond_eta=precond_eta, recycle_k=recycle_k, reorth_ratio=reorth_ratio,
+                             autotune=autotune, graphs=graphs, restart_tail=restart_tail, seed_m=seed_m)
+        self._prec = prec
+        opt = self._options(stream, autotune_cache=autotune_cache, **self._optargs)
         self._opt = opt
         h = ctypes.c_void_p()
         rc = lib.cc_gf_init(ctypes.byref(cs), ctypes.byref(opt), ctypes.byref(h))
@@ -183,6 +186,24 @@ class Context:
         self.nk = int(np.prod(s.kmesh))
         self.nocc, self.nvir = int(s.nocc), int(s.nvir)
         self.nmo = self.nocc + self.nvir
+
+    def _options(self, stream, *, tol, restart_m, maxiter, max_batch, timing, precond_eta, recycle_k, reorth_ratio,
+                 autotune, graphs, restart_tail, seed_m, autotune_cache=None):
+        return Options(self._prec, int(restart_m), int(maxiter), float(tol), int(max_batch),
+                       ctypes.c_void_p(stream.cuda_stream), 1 if timing else 0, float(precond_eta),
+                       int(recycle_k), float(reorth_ratio), 0 if autotune else -1,
+                       None if autotune_cache is None else str(autotune_cache).encode(), int(restart_tail),
+                       0 if graphs else -1, int(seed_m))
+
+    def set_options(self, **changes):
+        """Change solver options (not the precision) of the live context."""
+        unknown = set(changes) - set(self._optargs)
+        if unknown:
+            raise TypeError(f"unknown options {sorted(unknown)}")
+        args = dict(self._optargs, **changes)
+        opt = self._options(self.stream, **args)
+        self._check(load().cc_gf_set_options(self._h, ctypes.byref(opt)))
+        self._optargs, self._opt = args, opt
 
     def _check(self, rc, allow=()):
         if rc != OK and rc not in allow:

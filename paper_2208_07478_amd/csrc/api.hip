@@ -439,6 +439,28 @@ extern "C" int cc_gf_learn(ccgf_ctx *c, int parts, int K, int norb, const int *o
   return status;
 }
 
+extern "C" int cc_gf_set_options(ccgf_ctx *c, const ccgf_options *opt) {
+  if (!c) return CCGF_ESTATE;
+  if (!opt) return set_err(c, CCGF_EINVAL, "options are NULL");
+  ccgf_options o = *opt;
+  if (o.precision != c->opt.precision)
+    return set_err(c, CCGF_EUNSUPPORTED, "the precision is fixed when the context is built");
+  if (o.restart_m == 0) o.restart_m = 30;
+  if (o.maxiter == 0) o.maxiter = 2000;
+  if (o.tol == 0) o.tol = 1e-10;
+  if (o.max_batch == 0) o.max_batch = 64;
+  if (o.restart_m < 1 || o.restart_m > 2000 || o.maxiter < 1 || o.tol < 0 || o.max_batch < 1 ||
+      o.recycle_k < 0 || o.recycle_k > 200 || o.precond_eta < 0 || o.reorth_ratio < 0 || o.reorth_ratio > 1 ||
+      o.autotune < -1 || o.autotune > 0 || o.graphs < -1 || o.graphs > 0 || o.restart_tail < 0 ||
+      o.restart_tail > 2000 || o.seed_m < 0 || o.seed_m > 2000)
+    return set_err(c, CCGF_EINVAL, "options out of range");
+  if (hip_check(c, hipStreamSynchronize(c->stream), "cc_gf_set_options") != CCGF_OK) return CCGF_EDEVICE;
+  if (o.hip_stream != c->opt.hip_stream) c->stream = (hipStream_t)o.hip_stream;
+  o.autotune_cache = nullptr;  // the autotune file stays the one given to cc_gf_init
+  c->opt = o;
+  return CCGF_OK;
+}
+
 extern "C" int cc_gf_learn_enable(ccgf_ctx *c, int on) {
   if (!c) return CCGF_ESTATE;
   c->learn_on = on != 0;

@@ -97,6 +97,7 @@ def test_options_and_new_entry_points_are_checked_on_the_host():
     dp = ctypes.POINTER(ctypes.c_double)
     assert lib.cc_gf_learn(None, 3, 0, 1, None, 1, None, 0.1, None, None) == ccgf.ESTATE
     assert lib.cc_gf_learn_enable(None, 1) == ccgf.ESTATE
+    assert lib.cc_gf_set_options(None, None) == ccgf.ESTATE
     fp = ctypes.POINTER(ctypes.c_float)
     for dims in ((0, 4, 2, 3), (3, 0, 2, 3), (3, 4, 0, 3), (3, 4, 2, 0), (5000, 4, 2, 3)):
         din, hid, dout, N = dims

@@ -174,6 +174,24 @@ int cc_gf_solve(ccgf_ctx *ctx, int nkq, const int *kidx, int norb, const int *or
                 int nw, const double *omega, double eta, int parts,
                 double *G, double *Gplus_opt, double *Gminus_opt, ccgf_stats *st_opt);
 
+/* Whole matrices G_pq(K, w) over the requested orbitals (Eqs. 7 and 9 with p != q)
+ * and the density of states, the trace of the spectral function A(K, w) = -(1/pi) Im G(K, w)
+ * (the equation after Eq. 9) taken with each part on the retarded side:
+ * A = -(1/pi) (Im G+ - Im G-), since the removal part of Eq. 6 (w + M - i eta) is time
+ * ordered (at T = V = 0 this is one unit-weight Lorentzian per orbital).  The
+ * right-hand sides and solves are those of cc_gf_solve
+ * (one solve per orbital, frequency and part); each solution is dotted with the left
+ * vectors of every requested orbital:  G+_pq = e+_p . Y_q(w),  G-_pq = e-_q . X_p(w).
+ *  G, Gplus_opt, Gminus_opt: host complex [nkq][nw][norb][norb] with element [a][w][i][j] =
+ *  G_{orbs[i], orbs[j]}(kidx[a], omega[w]) (the optional ones may be NULL; G receives
+ *  G+ + G- of the requested parts).  dos_opt: host real [nkq][nw], the trace of A over the
+ *  requested orbitals, or NULL.  Other arguments, errors and device memory as in
+ *  cc_gf_solve, plus (norb x norb) complex per right-hand side in flight. */
+int cc_gf_solve_matrix(ccgf_ctx *ctx, int nkq, const int *kidx, int norb, const int *orbs,
+                       int nw, const double *omega, double eta, int parts,
+                       double *G, double *Gplus_opt, double *Gminus_opt, double *dos_opt,
+                       ccgf_stats *st_opt);
+
 /* Learned initial guess (a network trained on the solver's own solutions).
  * Not part of the paper's method: a companion to it that changes only where
  * GMRES starts, never what it converges to. */
@@ -278,6 +296,31 @@ int cc_gf_sigma(ccgf_ctx *ctx, int part, int K, int nvec, const double *x, doubl
  * e (<Phi|(1+Lambda) abar+_p for IP, <Phi|(1+Lambda) abar_p for EA) of orbital
  * p at momentum K (Eqs. 6-7).  b, e: DEVICE complex [n]; either may be NULL. */
 int cc_gf_vectors(ccgf_ctx *ctx, int part, int K, int p, double *b, double *e);
+
+/* Active-space self-energy correction and Dyson's equation (Eqs. 12-14):
+ *   Sigma_CAS  = G_GW,CAS^-1 - G_CC,CAS^-1                    (M x M)
+ *   Sigma_full = V Sigma_CAS V^H                               (N x N)
+ *   G_CC+GW    = [G_GW,full^-1 - Sigma_full]^-1                (N x N)
+ * at every (k, w) of a batch; needs no context.  All arrays are DEVICE complex:
+ *   Ggw     [nk][nw][N][N]  G_GW,full, the low-level Green's function in the full orbital basis;
+ *   Ggw_cas [nk][nw][M][M]  G_GW,CAS, the low-level Green's function of the active space (for
+ *                           instance V^H G_GW,full V, or a low-level calculation within the space);
+ *   Gcc     [nk][nw][M][M]  G_CC,CAS, the CCGF of the active space (cc_gf_solve_matrix of the
+ *                           active-space system, G+ + G-);
+ *   V       [nk][N][M]      active natural orbitals in the full basis (columns);
+ *   Gout    [nk][nw][N][N]  receives G_CC+GW; Sfull_opt [nk][nw][N][N] and Scas_opt
+ *                           [nk][nw][M][M] receive the self-energies when not NULL.
+ * Row-major matrices.  Sizes: nk >= 1, nw >= 0, 1 <= M <= N <= 64.  Runs on hip_stream (NULL:
+ * the default stream) and returns after the results are complete.  Returns CCGF_EINVAL for
+ * bad sizes or when a matrix to invert is singular (Gauss-Jordan with partial pivoting in
+ * FP64 finds a zero pivot), CCGF_ENOMEM when the scratch buffer (about 16 (4 M^2 + 3 N^2 +
+ * N M + M^2) bytes per (k, w) point) cannot be allocated.  Messages: cc_gf_dyson_last_error. */
+int cc_gf_dyson_cas(int nk, int nw, int N, int M, const double *Ggw, const double *Ggw_cas,
+                    const double *Gcc, const double *V, double *Gout, double *Sfull_opt,
+                    double *Scas_opt, void *hip_stream);
+
+/* Message for the last failed cc_gf_dyson_cas call of this thread (never NULL). */
+const char *cc_gf_dyson_last_error(void);
 
 /* Releases all device memory of the context (NULL is ignored). */
 void cc_gf_free(ccgf_ctx *ctx);

@@ -54,11 +54,12 @@ def dense_gf(E, K, p, omegas, eta, M_cache=None):
     return out["ea"], out["ip"]
 
 
-def dense_gf_matrix(E, K, omegas, eta):
+def dense_gf_matrix(E, K, omegas, eta, parts=False):
     """Full G_pq(K, w) over all orbitals (needed for the supercell transform).
-    G+_pq = e+_p . Y_q,  G-_pq = e-_q . X_p."""
+    G+_pq = e+_p . Y_q,  G-_pq = e-_q . X_p.  With parts=True returns (G+, G-)."""
     nmo = E.no + E.nv
     res = np.zeros((len(np.atleast_1d(omegas)), nmo, nmo), dtype=np.complex128)
+    by_part = {"ea": np.zeros_like(res), "ip": np.zeros_like(res)}
     for part in ("ea", "ip"):
         M = E.dense_matrix(part, K)
         sM, sE = shift_sign(part)
@@ -69,10 +70,24 @@ def dense_gf_matrix(E, K, omegas, eta):
             X = np.linalg.solve((w + 1j * sE * eta) * I + sM * M, B)   # column q: solution for b_q
             P = Ev @ X                                                  # P[r, q] = e_r . x_q
             if part == "ea":
-                res[iw] += P                # G+_pq = e+_p . Y_q
+                by_part["ea"][iw] = P       # G+_pq = e+_p . Y_q
             else:
-                res[iw] += P.T              # G-_pq = e-_q . X_p
+                by_part["ip"][iw] = P.T     # G-_pq = e-_q . X_p
+            res[iw] += by_part[part][iw]
+    if parts:
+        return by_part["ea"], by_part["ip"]
     return res
+
+
+def spectral_trace(Gplus, Gminus):
+    """Density of states: trace of A(K, w) = -(1/pi) Im G(K, w) (the equation after
+    Eq. 9), for G [..., norb, norb], with each part on the retarded side: Eq. 6 puts
+    the removal part G- on the time-ordered side (w + M - i eta, poles above the real
+    axis), whose retarded counterpart flips the sign of its imaginary part, so
+    A = -(1/pi) (Im G+ - Im G-).  Pinned by the closed form at T = V = 0 (a sum of
+    Lorentzians of weight one per orbital)."""
+    tr = lambda G: np.trace(G, axis1=-2, axis2=-1)
+    return -(np.imag(tr(Gplus)) - np.imag(tr(Gminus))) / np.pi
 
 
 def gmres(matvec, b, *, dinv=None, x0=None, tol=1e-12, restart=30, maxiter=3000):

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libccgf.so")
-SOURCES = ["api.hip", "init.hip", "sigma.hip", "gmres.hip", "mlp.hip"]
+SOURCES = ["api.hip", "init.hip", "sigma.hip", "gmres.hip", "mlp.hip", "dyson.hip"]
 ARCH = os.environ.get("CCGF_OFFLOAD_ARCH", "gfx950")
 
 

@@ -23,9 +23,9 @@ PLAIN_F64, MIXED_F32, MIXED_BF16X3 = 0, 1, 2
 PRECISIONS = {"f64": PLAIN_F64, "plain_f64": PLAIN_F64, "f32": MIXED_F32, "mixed_f32": MIXED_F32,
               "bf16x3": MIXED_BF16X3, "mixed_bf16x3": MIXED_BF16X3}
 
-EXPORTS = ("cc_gf_init", "cc_gf_solve", "cc_gf_mor", "cc_gf_vector_size", "cc_gf_sigma", "cc_gf_vectors",
-           "cc_gf_learn", "cc_gf_learn_enable", "cc_gf_set_options", "cc_gf_mlp_grad", "cc_gf_free",
-           "cc_gf_last_error")
+EXPORTS = ("cc_gf_init", "cc_gf_solve", "cc_gf_solve_matrix", "cc_gf_mor", "cc_gf_vector_size", "cc_gf_sigma", "cc_gf_vectors",
+           "cc_gf_learn", "cc_gf_learn_enable", "cc_gf_set_options", "cc_gf_mlp_grad", "cc_gf_dyson_cas",
+           "cc_gf_dyson_last_error", "cc_gf_free", "cc_gf_last_error")
 MOR_MAX = 32
 
 
@@ -102,6 +102,9 @@ def load(path: str = LIB_PATH):
     lib.cc_gf_solve.argtypes = [vp, ctypes.c_int, ip, ctypes.c_int, ip, ctypes.c_int, dp, ctypes.c_double,
                                 ctypes.c_int, vp, vp, vp, ctypes.POINTER(Stats)]
     lib.cc_gf_solve.restype = ctypes.c_int
+    lib.cc_gf_solve_matrix.argtypes = [vp, ctypes.c_int, ip, ctypes.c_int, ip, ctypes.c_int, dp, ctypes.c_double,
+                                       ctypes.c_int, vp, vp, vp, vp, ctypes.POINTER(Stats)]
+    lib.cc_gf_solve_matrix.restype = ctypes.c_int
     lib.cc_gf_mor.argtypes = [vp, ctypes.c_int, ip, ctypes.c_int, ip, ctypes.c_int, dp, ctypes.c_int, dp,
                               ctypes.c_int, dp, ctypes.c_double, ctypes.c_int, vp, vp, vp, ctypes.POINTER(Stats)]
     lib.cc_gf_mor.restype = ctypes.c_int
@@ -122,6 +125,11 @@ def load(path: str = LIB_PATH):
     lib.cc_gf_mlp_grad.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, fp, ctypes.c_int, fp, fp, fp,
                                    ctypes.POINTER(ctypes.c_double)]
     lib.cc_gf_mlp_grad.restype = ctypes.c_int
+    lib.cc_gf_dyson_cas.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp, vp,
+                                    vp, vp]
+    lib.cc_gf_dyson_cas.restype = ctypes.c_int
+    lib.cc_gf_dyson_last_error.argtypes = []
+    lib.cc_gf_dyson_last_error.restype = ctypes.c_char_p
     lib.cc_gf_free.argtypes = [vp]
     lib.cc_gf_free.restype = None
     lib.cc_gf_last_error.argtypes = [vp]
@@ -271,6 +279,26 @@ class Context:
         self._check(rc, allow=(ENOCONV,) if allow_noconv else ())
         return G, Gp, Gm, st.as_dict()
 
+    def solve_matrix(self, kidx: Sequence[int], orbs: Sequence[int], omega, eta: float, parts="both",
+                     allow_noconv=False):
+        """G, G+, G- [nkq][nw][norb][norb], DOS [nkq][nw] and stats for the full G_pq(K, w)."""
+        kidx = np.ascontiguousarray(np.asarray(kidx, dtype=np.int32))
+        orbs = np.ascontiguousarray(np.asarray(orbs, dtype=np.int32))
+        om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
+        shape = (len(kidx), len(om), len(orbs), len(orbs))
+        G = np.zeros(shape, dtype=np.complex128)
+        Gp = np.zeros(shape, dtype=np.complex128)
+        Gm = np.zeros(shape, dtype=np.complex128)
+        dos = np.zeros((len(kidx), len(om)), dtype=np.float64)
+        st = Stats()
+        ip = ctypes.POINTER(ctypes.c_int)
+        dp = ctypes.POINTER(ctypes.c_double)
+        rc = load().cc_gf_solve_matrix(self._h, len(kidx), kidx.ctypes.data_as(ip), len(orbs), orbs.ctypes.data_as(ip),
+                                       len(om), om.ctypes.data_as(dp), float(eta), _part(parts), G.ctypes.data,
+                                       Gp.ctypes.data, Gm.ctypes.data, dos.ctypes.data, ctypes.byref(st))
+        self._check(rc, allow=(ENOCONV,) if allow_noconv else ())
+        return G, Gp, Gm, dos, st.as_dict()
+
     def learn(self, K: int, orbs: Sequence[int], omega_train, eta: float, parts="both", epochs=0, batch=0, lr=0.0,
               seed=0, hidden=0, guess="network", accept=0.0, allow_noconv=False):
         """Train the initial-guess network of momentum K on plain solves at omega_train."""
@@ -310,6 +338,31 @@ class Context:
                               Gp.ctypes.data, Gm.ctypes.data, ctypes.byref(st))
         self._check(rc, allow=(ENOCONV,) if allow_noconv else ())
         return G, Gp, Gm, st.as_dict()
+
+
+def dyson_cas(Ggw, Ggw_cas, Gcc, V, stream=None, self_energies=False):
+    """G_CC+GW [nk][nw][N][N] (and optionally Sigma_full, Sigma_CAS) from CUDA complex128
+    tensors Ggw [nk][nw][N][N], Ggw_cas and Gcc [nk][nw][M][M], V [nk][N][M].
+    The outputs are allocated here by torch, as any caller of the C ABI provides them."""
+    lib = load()
+    import torch
+    for t in (Ggw, Ggw_cas, Gcc, V):
+        assert t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()
+    nk, nw, N = Ggw.shape[0], Ggw.shape[1], Ggw.shape[2]
+    M = V.shape[2]
+    assert Ggw.shape == (nk, nw, N, N) and Ggw_cas.shape == (nk, nw, M, M) and Gcc.shape == (nk, nw, M, M)
+    assert V.shape == (nk, N, M)
+    out = torch.empty_like(Ggw)
+    sf = torch.empty_like(Ggw) if self_energies else None
+    sc = torch.empty_like(Gcc) if self_energies else None
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    rc = lib.cc_gf_dyson_cas(nk, nw, N, M, Ggw.data_ptr(), Ggw_cas.data_ptr(), Gcc.data_ptr(), V.data_ptr(),
+                             out.data_ptr(), sf.data_ptr() if sf is not None else None,
+                             sc.data_ptr() if sc is not None else None, ctypes.c_void_p(stream.cuda_stream))
+    if rc != OK:
+        raise CCGFError(rc, lib.cc_gf_dyson_last_error().decode())
+    return (out, sf, sc) if self_energies else out
 
 
 def mlp_grad(din: int, hidden: int, dout: int, theta, X, T):

@@ -230,13 +230,14 @@ extern "C" int cc_gf_vectors(ccgf_ctx *c, int part, int K, int p, double *b, dou
   return hip_check(c, hipStreamSynchronize(c->stream), "cc_gf_vectors");
 }
 
-extern "C" int cc_gf_solve(ccgf_ctx *c, int nkq, const int *kidx, int norb, const int *orbs, int nw,
-                           const double *omega, double eta, int parts, double *G, double *Gp, double *Gm,
-                           ccgf_stats *st) {
-  if (!c) return CCGF_ESTATE;
+// The solves of cc_gf_solve and cc_gf_solve_matrix.  With Gmat (host [nkq][nw][norb][norb]) every
+// solution is also dotted with every left vector of the call: G+_pq = e+_p . Y_q, G-_pq = e-_q . X_p.
+static int solve_common(ccgf_ctx *c, int nkq, const int *kidx, int norb, const int *orbs, int nw,
+                        const double *omega, double eta, int parts, double *G, double *Gp, double *Gm,
+                        cplx *Gmat, cplx *Gpmat, cplx *Gmmat, ccgf_stats *st) {
   auto t0 = std::chrono::steady_clock::now();
   if (nkq < 0 || norb < 0 || nw < 0) return set_err(c, CCGF_EINVAL, "negative counts");
-  if ((nkq && !kidx) || (norb && !orbs) || (nw && !omega) || !G)
+  if ((nkq && !kidx) || (norb && !orbs) || (nw && !omega) || !(G || Gmat))
     return set_err(c, CCGF_EINVAL, "NULL array argument");
   if (!(eta > 0)) return set_err(c, CCGF_EINVAL, "eta must be > 0");
   if (parts < 1 || parts > 3) return set_err(c, CCGF_EINVAL, "parts must be CCGF_PART_IP, _EA or _BOTH");
@@ -262,7 +263,13 @@ extern "C" int cc_gf_solve(ccgf_ctx *c, int nkq, const int *kidx, int norb, cons
       rhs_orb[b * nw + w] = b;
       rhs_w[b * nw + w] = omega[w];
     }
-  std::vector<cplx> res(nrhs);
+  std::vector<cplx> res(nrhs), cols(Gmat ? (size_t)nrhs * norb : 0);
+  const size_t nmat = (size_t)norb * norb;
+  if (Gmat) {
+    std::fill(Gmat, Gmat + (size_t)nkq * nw * nmat, mkc(0, 0));
+    if (Gpmat) std::fill(Gpmat, Gpmat + (size_t)nkq * nw * nmat, mkc(0, 0));
+    if (Gmmat) std::fill(Gmmat, Gmmat + (size_t)nkq * nw * nmat, mkc(0, 0));
+  }
   for (int part : {CCGF_PART_IP, CCGF_PART_EA}) {
     if (!(parts & part) || nrhs == 0) continue;
     const long long n = vec_len(c, part);
@@ -298,7 +305,8 @@ extern "C" int cc_gf_solve(ccgf_ctx *c, int nkq, const int *kidx, int norb, cons
           break;
         }
       }
-      int rc = solve_batched(c, part, K, nrhs, rhs_orb.data(), rhs_w.data(), eta, Bv, Ev, res.data(), S, nullptr, gp);
+      int rc = solve_batched(c, part, K, nrhs, rhs_orb.data(), rhs_w.data(), eta, Bv, Ev, res.data(), S, nullptr, gp,
+                             Gmat ? cols.data() : nullptr, Gmat ? norb : 0);
       if (chat) hipFree(chat);
       if (seedQ) hipFree(seedQ);
       if (rc != CCGF_OK) {
@@ -312,12 +320,26 @@ extern "C" int cc_gf_solve(ccgf_ctx *c, int nkq, const int *kidx, int norb, cons
         if (part == CCGF_PART_EA) Gplus[o] = res[r];
         else Gminus[o] = res[r];
       }
+      if (Gmat)
+        for (int r = 0; r < nrhs; ++r) {
+          const int b = rhs_orb[r], w = r % nw;
+          cplx *Ga = Gmat + ((size_t)a * nw + w) * nmat;
+          cplx *Gpart = part == CCGF_PART_EA ? Gpmat : Gmmat;
+          if (Gpart) Gpart += ((size_t)a * nw + w) * nmat;
+          for (int q = 0; q < norb; ++q) {
+            // EA: column b of G+ (Y of orbital b against e+_q); IP: row b of G- (X of b against e-_q)
+            const size_t o = part == CCGF_PART_EA ? (size_t)q * norb + b : (size_t)b * norb + q;
+            const cplx v = cols[(size_t)r * norb + q];
+            Ga[o] = cadd(Ga[o], v);
+            if (Gpart) Gpart[o] = v;
+          }
+        }
     }
     hipFree(Bv);
     hipFree(Ev);
     if (status != CCGF_OK && status != CCGF_ENOCONV) break;
   }
-  std::memcpy(G, Gsum.data(), sizeof(cplx) * ntot);
+  if (G) std::memcpy(G, Gsum.data(), sizeof(cplx) * ntot);
   if (Gp) std::memcpy(Gp, Gplus.data(), sizeof(cplx) * ntot);
   if (Gm) std::memcpy(Gm, Gminus.data(), sizeof(cplx) * ntot);
   S->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -328,6 +350,43 @@ extern "C" int cc_gf_solve(ccgf_ctx *c, int nkq, const int *kidx, int norb, cons
   S->sigma_ms = c->t_sigma_ms;
   S->sigma_launches = c->t_sigma_launches;
   return status;
+}
+
+extern "C" int cc_gf_solve(ccgf_ctx *c, int nkq, const int *kidx, int norb, const int *orbs, int nw,
+                           const double *omega, double eta, int parts, double *G, double *Gp, double *Gm,
+                           ccgf_stats *st) {
+  if (!c) return CCGF_ESTATE;
+  if (!G) return set_err(c, CCGF_EINVAL, "NULL array argument");
+  return solve_common(c, nkq, kidx, norb, orbs, nw, omega, eta, parts, G, Gp, Gm, nullptr, nullptr, nullptr, st);
+}
+
+extern "C" int cc_gf_solve_matrix(ccgf_ctx *c, int nkq, const int *kidx, int norb, const int *orbs, int nw,
+                                  const double *omega, double eta, int parts, double *G, double *Gp, double *Gm,
+                                  double *dos, ccgf_stats *st) {
+  if (!c) return CCGF_ESTATE;
+  if (!G) return set_err(c, CCGF_EINVAL, "NULL array argument");
+  if (nkq < 0 || norb < 0 || nw < 0) return set_err(c, CCGF_EINVAL, "negative counts");
+  // the parts are kept for the density of states even when the caller does not want them
+  const size_t nm = (size_t)nkq * nw * norb * norb;
+  std::vector<cplx> lp(dos && !Gp ? nm : 0), lm(dos && !Gm ? nm : 0);
+  cplx *P = Gp ? (cplx *)Gp : (dos ? lp.data() : nullptr);
+  cplx *Q = Gm ? (cplx *)Gm : (dos ? lm.data() : nullptr);
+  int rc = solve_common(c, nkq, kidx, norb, orbs, nw, omega, eta, parts, nullptr, nullptr, nullptr, (cplx *)G, P, Q,
+                        st);
+  if (dos && (rc == CCGF_OK || rc == CCGF_ENOCONV)) {
+    // A(K, w) = -(1/pi) Im G(K, w) with each part on the retarded side (G- of Eq. 6 is time
+    // ordered: its imaginary part changes sign), traced over the requested orbitals
+    for (int a = 0; a < nkq; ++a)
+      for (int w = 0; w < nw; ++w) {
+        double t = 0;
+        for (int p = 0; p < norb; ++p) {
+          const size_t o = (((size_t)a * nw + w) * norb + p) * norb + p;
+          t += P[o].y - Q[o].y;
+        }
+        dos[(size_t)a * nw + w] = -t / M_PI;
+      }
+  }
+  return rc;
 }
 
 extern "C" int cc_gf_mor(ccgf_ctx *c, int nkq, const int *kidx, int norb, const int *orbs, int nexp_ip,

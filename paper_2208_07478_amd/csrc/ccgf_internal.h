@@ -288,7 +288,7 @@ int seed_krylov(ccgf_ctx *c, int part, int K, int norb, const cplx *Bvecs, int n
                 const double *rhs_omega, double eta, Guess &g, cplx **Q, cplx **chat, ccgf_stats *st);
 int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb_slot, const double *rhs_omega,
                   double eta, const cplx *Bvecs, const cplx *Evecs, cplx *Gout, ccgf_stats *st,
-                  cplx *Xout = nullptr, const Guess *guess = nullptr);
+                  cplx *Xout = nullptr, const Guess *guess = nullptr, cplx *Gcols = nullptr, int ncols = 0);
 int learn_part(ccgf_ctx *c, int part, int K, int norb, const int *orbs, int ntrain, const double *wtrain, double eta,
                const ccgf_learn_options &lo, ccgf_learn_stats *ls);
 // Device reduced coordinates (chat, [nrhs][R]) of the network's guesses for the listed

@@ -678,7 +678,8 @@ static void build_pack(const ccgf_ctx *c, int part, int K, long long n, std::vec
 }
 
 int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, const double *rhs_omega, double eta,
-                  const cplx *Bvecs, const cplx *Evecs, cplx *Gout, ccgf_stats *st, cplx *Xout, const Guess *guess) {
+                  const cplx *Bvecs, const cplx *Evecs, cplx *Gout, ccgf_stats *st, cplx *Xout, const Guess *guess,
+                  cplx *Gcols, int ncols) {
   const long long n = vec_len(c, part);
   const int n1 = part == CCGF_PART_IP ? c->no : c->nv;
   const double sM = part == CCGF_PART_IP ? 1.0 : -1.0;
@@ -774,6 +775,11 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
   double *w0n = (double *)walloc(W, sizeof(double) * Bmax);
   long long *uoff = (long long *)walloc(W, sizeof(long long) * Bmax);
   long long *eoff = (long long *)walloc(W, sizeof(long long) * Bmax);
+  // whole columns: e_r . x for every left vector r of the call (Eqs. 7 and 9 off the diagonal)
+  const bool cols = Gcols != nullptr && ncols > 0;
+  cplx *partE = cols ? (cplx *)walloc(W, sizeof(cplx) * (size_t)Bmax * nchunk * ncols) : nullptr;
+  cplx *outE = cols ? (cplx *)walloc(W, sizeof(cplx) * (size_t)Bmax * ncols) : nullptr;
+  long long *zoff = cols ? (long long *)walloc(W, sizeof(long long) * Bmax) : nullptr;
   if (W.failed) {
     wfree(W);
     return set_err(c, CCGF_ENOMEM, "solver workspace allocation failed (reduce max_batch, restart_m or recycle_k)");
@@ -852,6 +858,7 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
   }
   hipMemcpyAsync(uoff, hoff.data(), sizeof(long long) * B, hipMemcpyHostToDevice, s);
   hipMemcpyAsync(uoffb, hoffb.data(), sizeof(long long) * B, hipMemcpyHostToDevice, s);
+  if (cols) hipMemsetAsync(zoff, 0, sizeof(long long) * B, s);
   // G = e . x (bilinear, Eq. 7), statistics and solutions of the listed slots; frees them
   auto retire = [&](const std::vector<int> &fin) -> int {
     alist.clear();
@@ -870,12 +877,24 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
     hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, 1, (const int *)fmask, htmp,
                        ldp, (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
     hipMemcpyAsync(hh.data(), htmp, sizeof(cplx) * B * ldp, hipMemcpyDeviceToHost, s);
+    std::vector<cplx> hcol;
+    if (cols) {  // every left vector of the call against the finished solutions
+      hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Evecs, zoff, (long long)n, ncols, X, n, n1, 0,
+                         (const int *)fmask, partE, nchunk, ncols, (const int *)nullptr);
+      hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partE, nchunk, ncols, ncols, (const int *)fmask,
+                         outE, ncols, (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr,
+                         (const int *)nullptr);
+      hcol.resize((size_t)B * ncols);
+      hipMemcpyAsync(hcol.data(), outE, sizeof(cplx) * hcol.size(), hipMemcpyDeviceToHost, s);
+    }
     if (Xout)  // solutions, for the reduced model
       for (int v : fin)
         hipMemcpyAsync(Xout + (size_t)rhs_of[v] * n, X + (size_t)v * n, sizeof(cplx) * n, hipMemcpyDeviceToDevice, s);
     if (int rc2 = sync("G assembly")) return rc2;
     for (int v : fin) {
       Gout[rhs_of[v]] = hh[(size_t)v * ldp];
+      if (cols)
+        for (int r = 0; r < ncols; ++r) Gcols[(size_t)rhs_of[v] * ncols + r] = hcol[(size_t)v * ncols + r];
       double rel = hbnorm[v] > 0 ? hrn[v] / hbnorm[v] : 0.0;
       bool ok = hbnorm[v] == 0.0 || rel <= tol;
       if (st) {

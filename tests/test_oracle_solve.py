@@ -115,3 +115,27 @@ def test_eigen_decomposition_form():
             g = np.array([np.sum((e @ R) * (L @ b) / (om + 1j * sE * eta + sM * ev)) for om in w])
             x = solve.dense_solutions(E, part, 0, p, w, eta)
             assert np.allclose(g, x @ e, atol=1e-12)
+
+
+def test_dos_closed_form_and_matrix_diagonal():
+    """DOS of the non-interacting system is a sum of Lorentzians (closed form);
+    the diagonal of the full matrix is the per-orbital G, and at T = V = 0 the
+    off-diagonal elements vanish."""
+    s = synth.make_system((2, 1, 1), 2, 3, seed=3, zero_t1=True, zero_t2=True, zero_eri=True)
+    E = eom.EOMSystem(s)
+    w = np.linspace(-1.2, 2.1, 7)
+    eta = 0.03
+    for K in range(2):
+        G = solve.dense_gf_matrix(E, K, w, eta)
+        Gp, Gm = solve.dense_gf_matrix(E, K, w, eta, parts=True)
+        assert np.allclose(Gp + Gm, G, rtol=0, atol=1e-15)
+        off = G - np.einsum("wpp->wp", G)[:, :, None] * np.eye(5)
+        assert np.abs(off).max() == 0.0
+        ref = sum(eta / np.pi / ((w - s.eps[K, p]) ** 2 + eta ** 2) for p in range(5))
+        assert np.allclose(solve.spectral_trace(Gp, Gm), ref, rtol=1e-13, atol=0)
+    s = synth.make_system((3, 1, 1), 2, 3, seed=4, t1_std=0.1, t2_std=0.1, eri_std=0.2)
+    E = eom.EOMSystem(s)
+    G = solve.dense_gf_matrix(E, 1, w, eta)
+    for p in range(5):
+        gp, gm = solve.dense_gf(E, 1, p, w, eta)
+        assert np.allclose(G[:, p, p], gp + gm, rtol=1e-12, atol=1e-14)

@@ -319,7 +319,19 @@ int cc_gf_dyson_cas(int nk, int nw, int N, int M, const double *Ggw, const doubl
                     const double *Gcc, const double *V, double *Gout, double *Sfull_opt,
                     double *Scas_opt, void *hip_stream);
 
-/* Message for the last failed cc_gf_dyson_cas call of this thread (never NULL). */
+/* cc_gf_dyson_cas for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): same arguments, results
+ * and errors, but it calls no allocating routine.  Its scratch is one fixed 64 MiB array per
+ * device, held until the process ends; batches larger than it holds are processed in chunks
+ * of (k, w) points, and a (k, w) point that alone needs more (impossible for N <= 64) gives
+ * CCGF_EINVAL.  Every call on a device shares that device's array: calls that overlap on one
+ * device (other host threads, other streams) race and must not be issued.  It reports a
+ * singular matrix without saying at which point, and returns after the results are complete. */
+int cc_gf_dyson_cas_noalloc(int nk, int nw, int N, int M, const double *Ggw, const double *Ggw_cas,
+                            const double *Gcc, const double *V, double *Gout, double *Sfull_opt,
+                            double *Scas_opt, void *hip_stream);
+
+/* Message for the last failed cc_gf_dyson_cas(_noalloc) call of this thread (never NULL). */
 const char *cc_gf_dyson_last_error(void);
 
 /* Releases all device memory of the context (NULL is ignored). */

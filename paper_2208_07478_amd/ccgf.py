@@ -25,7 +25,7 @@ PRECISIONS = {"f64": PLAIN_F64, "plain_f64": PLAIN_F64, "f32": MIXED_F32, "mixed
 
 EXPORTS = ("cc_gf_init", "cc_gf_solve", "cc_gf_solve_matrix", "cc_gf_mor", "cc_gf_vector_size", "cc_gf_sigma", "cc_gf_vectors",
            "cc_gf_learn", "cc_gf_learn_enable", "cc_gf_set_options", "cc_gf_mlp_grad", "cc_gf_dyson_cas",
-           "cc_gf_dyson_last_error", "cc_gf_free", "cc_gf_last_error")
+           "cc_gf_dyson_cas_noalloc", "cc_gf_dyson_last_error", "cc_gf_free", "cc_gf_last_error")
 MOR_MAX = 32
 
 
@@ -128,6 +128,8 @@ def load(path: str = LIB_PATH):
     lib.cc_gf_dyson_cas.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp, vp,
                                     vp, vp]
     lib.cc_gf_dyson_cas.restype = ctypes.c_int
+    lib.cc_gf_dyson_cas_noalloc.argtypes = lib.cc_gf_dyson_cas.argtypes
+    lib.cc_gf_dyson_cas_noalloc.restype = ctypes.c_int
     lib.cc_gf_dyson_last_error.argtypes = []
     lib.cc_gf_dyson_last_error.restype = ctypes.c_char_p
     lib.cc_gf_free.argtypes = [vp]
@@ -340,9 +342,10 @@ class Context:
         return G, Gp, Gm, st.as_dict()
 
 
-def dyson_cas(Ggw, Ggw_cas, Gcc, V, stream=None, self_energies=False):
+def dyson_cas(Ggw, Ggw_cas, Gcc, V, stream=None, self_energies=False, noalloc=False):
     """G_CC+GW [nk][nw][N][N] (and optionally Sigma_full, Sigma_CAS) from CUDA complex128
-    tensors Ggw [nk][nw][N][N], Ggw_cas and Gcc [nk][nw][M][M], V [nk][N][M].
+    tensors Ggw [nk][nw][N][N], Ggw_cas and Gcc [nk][nw][M][M], V [nk][N][M]; noalloc
+    calls the entry point that allocates nothing (its fixed per-device scratch).
     The outputs are allocated here by torch, as any caller of the C ABI provides them."""
     lib = load()
     import torch
@@ -357,7 +360,8 @@ def dyson_cas(Ggw, Ggw_cas, Gcc, V, stream=None, self_energies=False):
     sc = torch.empty_like(Gcc) if self_energies else None
     if stream is None:
         stream = torch.cuda.current_stream()
-    rc = lib.cc_gf_dyson_cas(nk, nw, N, M, Ggw.data_ptr(), Ggw_cas.data_ptr(), Gcc.data_ptr(), V.data_ptr(),
+    fn = lib.cc_gf_dyson_cas_noalloc if noalloc else lib.cc_gf_dyson_cas
+    rc = fn(nk, nw, N, M, Ggw.data_ptr(), Ggw_cas.data_ptr(), Gcc.data_ptr(), V.data_ptr(),
                              out.data_ptr(), sf.data_ptr() if sf is not None else None,
                              sc.data_ptr() if sc is not None else None, ctypes.c_void_p(stream.cuda_stream))
     if rc != OK:

@@ -11,6 +11,7 @@
 #include "ccgf_internal.h"
 
 #include <algorithm>
+#include <mutex>
 
 namespace {
 
@@ -242,3 +243,76 @@ extern "C" int cc_gf_dyson_cas(int nk, int nw, int N, int M, const double *Ggw, 
 }
 
 extern "C" const char *cc_gf_dyson_last_error(void) { return g_dyson_err.c_str(); }
+
+// ------------------------------------------------------------------ without allocation
+// Scratch of cc_gf_dyson_cas_noalloc: one fixed array per device (64 MiB), alive until
+// the process ends.  The first 256 bytes hold the singular-matrix flag, the rest the
+// matrices of one chunk of (k, w) points.  Host code reaches it only through the address
+// hipGetSymbolAddress returns on each device.
+#define DYSON_SCRATCH_ELEMS (1LL << 22)
+#define DYSON_SCRATCH_HEAD 16
+static __device__ __align__(256) cplx scratch[DYSON_SCRATCH_HEAD + DYSON_SCRATCH_ELEMS];
+
+namespace {
+__global__ void k_clear_flag(int *f) { *f = 0; }
+
+std::mutex g_scratch_mu;
+cplx *g_scratch_ptr[256] = {};  // per device ordinal
+}  // namespace
+
+// The device address of `scratch` on the current device (looked up once per device).
+static int dyson_scratch(cplx **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 256) {
+    (void)hipGetLastError();
+    g_dyson_err = "no current HIP device";
+    return CCGF_EDEVICE;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      g_dyson_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return CCGF_EDEVICE;
+    }
+    g_scratch_ptr[dev] = (cplx *)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return CCGF_OK;
+}
+
+extern "C" int cc_gf_dyson_cas_noalloc(int nk, int nw, int N, int M, const double *Ggw, const double *Ggw_cas,
+                                       const double *Gcc, const double *V, double *Gout, double *Sfull_opt,
+                                       double *Scas_opt, void *hip_stream) {
+  if (int rc = dyson_check(nk, nw, N, M, Ggw, Ggw_cas, Gcc, V, Gout)) return rc;
+  if (dyson_scratch_per_point(N, M) > DYSON_SCRATCH_ELEMS) {
+    g_dyson_err = "one (k, w) point needs more than the fixed scratch of cc_gf_dyson_cas_noalloc";
+    return CCGF_EINVAL;
+  }
+  if (nw == 0) return CCGF_OK;
+  cplx *base = nullptr;
+  if (int rc = dyson_scratch(&base)) return rc;
+  hipStream_t s = (hipStream_t)hip_stream;
+  int *flag = (int *)base;
+  hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(1), 0, s, flag);
+  int rc = dyson_cas_run(s, nk, nw, N, M, (const cplx *)Ggw, (const cplx *)Ggw_cas, (const cplx *)Gcc,
+                         (const cplx *)V, (cplx *)Gout, (cplx *)Sfull_opt, (cplx *)Scas_opt,
+                         base + DYSON_SCRATCH_HEAD, DYSON_SCRATCH_ELEMS, flag, 0);
+  if (rc != CCGF_OK) {
+    g_dyson_err = "kernel launch failed";
+    return rc;
+  }
+  int hflag = 0;
+  hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (hipStreamSynchronize(s) != hipSuccess) {
+    g_dyson_err = std::string("cc_gf_dyson_cas_noalloc: ") + hipGetErrorString(hipGetLastError());
+    return CCGF_EDEVICE;
+  }
+  if (hflag) {
+    g_dyson_err = "a matrix to invert is singular";
+    return CCGF_EINVAL;
+  }
+  return CCGF_OK;
+}

@@ -12,7 +12,8 @@
  * with b-_p = abar_p|Phi>, b+_p = abar+_p|Phi>, e-_p = <Phi|(1+Lambda) abar+_p,
  * e+_p = <Phi|(1+Lambda) abar_p restricted to the EOM-CCSD spaces of Eq. 8
  * (1h + 2h1p for IP, 1p + 2p1h for EA), Lambda = T^dagger (the approximation
- * stated after Eq. 10), and Hbar - E the EOM-CCSD matrix, i.e. the connected
+ * stated after Eq. 10) unless the caller gives Lambda amplitudes, and Hbar - E
+ * the EOM-CCSD matrix, i.e. the connected
  * commutator <mu|[Hbar, R_nu]|Phi>.  The products are bilinear (e is not
  * conjugated).  Every shifted system is solved by a batched, diagonally
  * right-preconditioned restarted GMRES on the GPU whose matrix-vector product
@@ -84,6 +85,13 @@ typedef struct {
   const double *t1;          /* complex [nk][nocc][nvir] */
   const double *t2;          /* complex [nk][nk][nk][nocc][nocc][nvir][nvir] */
   int mem_space;             /* CCGF_HOST or CCGF_DEVICE */
+  /* Lambda (de-excitation) amplitudes of the left state (1 + Lambda) of Eq. 5, in the
+   * layouts of t1 and t2 (l1[k][i][a] = lambda_a^i, l2[ki][kj][ka][i][j][a][b] =
+   * lambda_ab^ij, antisymmetric like t2).  NULL (both): Lambda = T^dagger, the
+   * approximation stated after Eq. 10.  Either both or neither; they enter only the
+   * left vectors e of Eq. 7. */
+  const double *l1;
+  const double *l2;
 } ccgf_system;
 
 typedef struct {
@@ -151,7 +159,7 @@ typedef struct {
                                  below accept ||b|| (network) or ||b|| (Krylov seed) */
 } ccgf_stats;
 
-/* Validates the system (shapes, t2 antisymmetry, factor Hermiticity, each to
+/* Validates the system (shapes, t2 and l2 antisymmetry, factor Hermiticity, each to
  * 1e-10 relative), uploads it on the given stream and builds the
  * similarity-transformed Hamiltonian blocks on the device in FP64.
  * Returns CCGF_EINVAL for invalid input, CCGF_ENOMEM if the device is full.

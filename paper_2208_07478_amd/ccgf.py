@@ -33,7 +33,8 @@ class System(ctypes.Structure):
     _fields_ = [("kmesh", ctypes.c_int * 3), ("nocc", ctypes.c_int), ("nvir", ctypes.c_int),
                 ("eps", ctypes.c_void_p), ("foo", ctypes.c_void_p), ("fvv", ctypes.c_void_p),
                 ("naux", ctypes.c_int), ("eri_factor", ctypes.c_void_p), ("t1", ctypes.c_void_p),
-                ("t2", ctypes.c_void_p), ("mem_space", ctypes.c_int)]
+                ("t2", ctypes.c_void_p), ("mem_space", ctypes.c_int), ("l1", ctypes.c_void_p),
+                ("l2", ctypes.c_void_p)]
 
 
 class Options(ctypes.Structure):
@@ -154,7 +155,7 @@ class Context:
     """One system on the GPU (wraps cc_gf_init / cc_gf_free)."""
 
     def __init__(self, system, *, tol=1e-10, restart_m=30, maxiter=2000, max_batch=64, stream=None,
-                 timing=False, foo=None, fvv=None, precond_eta=0.0, recycle_k=0, precision="f64",
+                 timing=False, foo=None, fvv=None, l1=None, l2=None, precond_eta=0.0, recycle_k=0, precision="f64",
                  reorth_ratio=0.0, autotune=True, autotune_cache=None, graphs=True, restart_tail=0,
                  seed_m=0):
         lib = load()
@@ -168,7 +169,9 @@ class Context:
                       _c128(s.t1), _c128(s.t2)]
         foo_a = None if foo is None else _c128(foo)
         fvv_a = None if fvv is None else _c128(fvv)
-        self._keep += [foo_a, fvv_a]
+        l1_a = None if l1 is None else _c128(l1)
+        l2_a = None if l2 is None else _c128(l2)
+        self._keep += [foo_a, fvv_a, l1_a, l2_a]
         cs = System()
         cs.kmesh = (ctypes.c_int * 3)(*[int(x) for x in s.kmesh])
         cs.nocc, cs.nvir = int(s.nocc), int(s.nvir)
@@ -180,6 +183,8 @@ class Context:
         cs.t1 = self._keep[2].ctypes.data
         cs.t2 = self._keep[3].ctypes.data
         cs.mem_space = HOST
+        cs.l1 = None if l1_a is None else l1_a.ctypes.data
+        cs.l2 = None if l2_a is None else l2_a.ctypes.data
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self._optargs = dict(tol=tol, restart_m=restart_m, maxiter=maxiter, max_batch=max_batch, timing=timing,
                              precond_eta=precond_eta, recycle_k=recycle_k, reorth_ratio=reorth_ratio,

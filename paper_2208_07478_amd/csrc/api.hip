@@ -48,33 +48,35 @@ static void free_all(ccgf_ctx *c) {
 // Host-side checks of the symmetry the formulation relies on (host inputs only).
 static int validate_host(ccgf_ctx *c, const ccgf_system *s) {
   const int nk = c->nk, no = c->no, nv = c->nv, nmo = c->nmo, naux = c->naux;
-  const double *t2 = s->t2;
-  double amax = 0, dev = 0;
-  auto T2 = [&](int ki, int kj, int ka, int i, int j, int a, int b, int comp) {
-    size_t off = ((((((size_t)ki * nk + kj) * nk + ka) * no + i) * no + j) * nv + a) * nv + b;
-    return t2[2 * off + comp];
-  };
-  for (int ki = 0; ki < nk; ++ki)
-    for (int kj = 0; kj < nk; ++kj)
-      for (int ka = 0; ka < nk; ++ka) {
-        int kb = c->kc3_h[((size_t)ki * nk + kj) * nk + ka];
-        for (int i = 0; i < no; ++i)
-          for (int j = 0; j < no; ++j)
-            for (int a = 0; a < nv; ++a)
-              for (int b = 0; b < nv; ++b)
-                for (int q = 0; q < 2; ++q) {
-                  double x = T2(ki, kj, ka, i, j, a, b, q);
-                  amax = std::fmax(amax, std::fabs(x));
-                  dev = std::fmax(dev, std::fabs(x + T2(kj, ki, ka, j, i, a, b, q)));
-                  dev = std::fmax(dev, std::fabs(x + T2(ki, kj, kb, i, j, b, a, q)));
-                }
-      }
-  if (dev > 1e-10 * std::fmax(amax, 1e-300) && dev > 0)
-    return set_err(c, CCGF_EINVAL, "t2 is not antisymmetric under i<->j / a<->b (max deviation " +
-                                       std::to_string(dev) + ")");
+  for (const double *t2 : {s->t2, s->l2}) {
+    if (!t2) continue;
+    const char *name = t2 == s->t2 ? "t2" : "l2";
+    double amax = 0, dev = 0;
+    auto T2 = [&](int ki, int kj, int ka, int i, int j, int a, int b, int comp) {
+      size_t off = ((((((size_t)ki * nk + kj) * nk + ka) * no + i) * no + j) * nv + a) * nv + b;
+      return t2[2 * off + comp];
+    };
+    for (int ki = 0; ki < nk; ++ki)
+      for (int kj = 0; kj < nk; ++kj)
+        for (int ka = 0; ka < nk; ++ka) {
+          int kb = c->kc3_h[((size_t)ki * nk + kj) * nk + ka];
+          for (int i = 0; i < no; ++i)
+            for (int j = 0; j < no; ++j)
+              for (int a = 0; a < nv; ++a)
+                for (int b = 0; b < nv; ++b)
+                  for (int q = 0; q < 2; ++q) {
+                    double x = T2(ki, kj, ka, i, j, a, b, q);
+                    amax = std::fmax(amax, std::fabs(x));
+                    dev = std::fmax(dev, std::fabs(x + T2(kj, ki, ka, j, i, a, b, q)));
+                    dev = std::fmax(dev, std::fabs(x + T2(ki, kj, kb, i, j, b, a, q)));
+                  }
+        }
+    if (dev > 1e-10 * std::fmax(amax, 1e-300) && dev > 0)
+      return set_err(c, CCGF_EINVAL, std::string(name) + " is not antisymmetric under i<->j / a<->b (max deviation " +
+                                         std::to_string(dev) + ")");
+  }
   const double *A = s->eri_factor;
-  amax = 0;
-  dev = 0;
+  double amax = 0, dev = 0;
   for (int k1 = 0; k1 < nk; ++k1)
     for (int k3 = 0; k3 < nk; ++k3)
       for (int L = 0; L < naux; ++L)
@@ -102,6 +104,8 @@ extern "C" int cc_gf_init(const ccgf_system *s, const ccgf_options *opt, ccgf_ct
     return set_err(nullptr, CCGF_EINVAL, "eps, eri_factor, t1 and t2 are required");
   if (s->mem_space != CCGF_HOST && s->mem_space != CCGF_DEVICE)
     return set_err(nullptr, CCGF_EINVAL, "mem_space must be CCGF_HOST or CCGF_DEVICE");
+  if ((s->l1 == nullptr) != (s->l2 == nullptr))
+    return set_err(nullptr, CCGF_EINVAL, "give both l1 and l2, or neither (Lambda = T^dagger)");
   ccgf_options o{};
   if (opt) o = *opt;
   if (o.precision != CCGF_PLAIN_F64 && o.precision != CCGF_MIXED_F32 && o.precision != CCGF_MIXED_BF16X3)
@@ -167,6 +171,12 @@ extern "C" int cc_gf_init(const ccgf_system *s, const ccgf_options *opt, ccgf_ct
   if (c->kc3) hipMemcpy(c->kc3, c->kc3_h.data(), sizeof(int) * c->kc3_h.size(), hipMemcpyHostToDevice);
   c->t1 = upload(s->t1, sizeof(cplx) * n_t1);
   c->t2 = upload(s->t2, sizeof(cplx) * n_t2);
+  bool lam_ok = true;
+  if (s->l1) {
+    c->l1 = upload(s->l1, sizeof(cplx) * n_t1);
+    c->l2 = upload(s->l2, sizeof(cplx) * n_t2);
+    lam_ok = c->l1 && c->l2;
+  }
   c->fac = upload(s->eri_factor, sizeof(cplx) * n_fac);
   // Fock blocks: given, or diag(eps)
   std::vector<cplx> hfoo((size_t)nk * no * no, mkc(0, 0)), hfvv((size_t)nk * nv * nv, mkc(0, 0));
@@ -185,7 +195,7 @@ extern "C" int cc_gf_init(const ccgf_system *s, const ccgf_options *opt, ccgf_ct
     if (s->fvv) hipMemcpy(c->fvv, s->fvv, sizeof(cplx) * hfvv.size(), kind);
     else hipMemcpy(c->fvv, hfvv.data(), sizeof(cplx) * hfvv.size(), hipMemcpyHostToDevice);
   }
-  if (!c->kc3 || !c->t1 || !c->t2 || !c->fac || !c->foo || !c->fvv) {
+  if (!c->kc3 || !c->t1 || !c->t2 || !c->fac || !c->foo || !c->fvv || !lam_ok) {
     g_init_err = "device allocation or upload failed";
     free_all(c);
     delete c;

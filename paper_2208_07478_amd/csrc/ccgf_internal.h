@@ -208,6 +208,7 @@ struct ccgf_ctx {
   int *kc3 = nullptr;
   // inputs
   cplx *t1 = nullptr, *t2 = nullptr, *fac = nullptr, *foo = nullptr, *fvv = nullptr;
+  cplx *l1 = nullptr, *l2 = nullptr;  // Lambda amplitudes when given (NULL: Lambda = T^dagger)
   // Hbar blocks (complex double)
   cplx *Foo = nullptr, *Fvv = nullptr, *Fov = nullptr;
   // W_abcd is antisymmetric under (a,ka)<->(b,kb) and (c,kc)<->(d,kd): only the blocks

@@ -61,6 +61,20 @@ struct Eri {
   }
 };
 
+// Lambda amplitudes: the given l1 / l2 ([k][i][a] and [ki][kj][ka][i][j][a][b], the layouts of
+// t1 / t2), or T^dagger (lambda_a^i = conj(t_i^a), lambda_ab^ij = conj(t_ij^ab)) when none are given
+struct Lam {
+  T2d t1;
+  T4 t2;
+  const cplx *l1, *l2;
+  __device__ inline cplx one(int k, int i, int a) const {
+    return l1 ? l1[((size_t)k * t1.n1 + i) * t1.n2 + a] : cconj(t1(k, i, a));
+  }
+  __device__ inline cplx two(int ki, int kj, int ka, int i, int j, int a, int b) const {
+    return l2 ? l2[t2.at(ki, kj, ka, i, j, a, b)] : cconj(t2(ki, kj, ka, i, j, a, b));
+  }
+};
+
 }  // namespace
 
 long long vec_len(const ccgf_ctx *c, int part) {
@@ -422,9 +436,9 @@ __device__ inline void block_store_sum(cplx v, cplx *out) {
   if (threadIdx.x == 0) *out = mkc(sh[0][0], sh[1][0]);
 }
 
-// h[i] = sum over kl, kc, l, c, d of t2[K][kl][kc](p, l, c, d) conj(t2[K][kl][kc](i, l, c, d)),
+// h[i] = sum over kl, kc, l, c, d of t2[K][kl][kc](p, l, c, d) lambda2[K][kl][kc](i, l, c, d),
 // one 256-thread block per occupied i (the 1h overlap term of the IP e vector)
-__global__ __launch_bounds__(256) void k_t2_overlap(T4 t2, int K, int p, cplx *__restrict__ h) {
+__global__ __launch_bounds__(256) void k_t2_overlap(T4 t2, Lam lam, int K, int p, cplx *__restrict__ h) {
   const int ii = blockIdx.x, nk = t2.nk, no = t2.n2, nv = t2.n4;
   const long long tot = (long long)nk * nk * no * nv * nv;
   cplx acc = mkc(0, 0);
@@ -437,14 +451,15 @@ __global__ __launch_bounds__(256) void k_t2_overlap(T4 t2, int K, int p, cplx *_
     const int l = (int)(r % no);
     r /= no;
     const int kc = (int)(r % nk), kl = (int)(r / nk);
-    cfma(acc, t2(K, kl, kc, p, l, cc, d), cconj(t2(K, kl, kc, ii, l, cc, d)));
+    cfma(acc, t2(K, kl, kc, p, l, cc, d), lam.two(K, kl, kc, ii, l, cc, d));
   }
   block_store_sum(acc, h + ii);
 }
 
-// h[a] = sum over kk, kl, k, l, d of t2[kk][kl][kd](k, l, d, c0) conj(t2[kk][kl][kd](k, l, d, a)),
+// h[a] = sum over kk, kl, k, l, d of t2[kk][kl][kd](k, l, d, c0) lambda2[kk][kl][kd](k, l, d, a),
 // kd = kk + kl - K, one 256-thread block per virtual a (the 1p overlap term of the EA e vector)
-__global__ __launch_bounds__(256) void k_t2_overlap_ea(T4 t2, KTab kt, int K, int c0, cplx *__restrict__ h) {
+__global__ __launch_bounds__(256) void k_t2_overlap_ea(T4 t2, Lam lam, KTab kt, int K, int c0,
+                                                       cplx *__restrict__ h) {
   const int a = blockIdx.x, nk = t2.nk, no = t2.n1, nv = t2.n4;
   const long long tot = (long long)nk * nk * no * no * nv;
   cplx acc = mkc(0, 0);
@@ -458,7 +473,7 @@ __global__ __launch_bounds__(256) void k_t2_overlap_ea(T4 t2, KTab kt, int K, in
     r /= no;
     const int kl = (int)(r % nk), kk = (int)(r / nk);
     const int kd = kt.c3(kk, kl, K);
-    cfma(acc, t2(kk, kl, kd, k, l, d, c0), cconj(t2(kk, kl, kd, k, l, d, a)));
+    cfma(acc, t2(kk, kl, kd, k, l, d, c0), lam.two(kk, kl, kd, k, l, d, a));
   }
   block_store_sum(acc, h + a);
 }
@@ -470,6 +485,7 @@ int build_vectors(ccgf_ctx *c, int part, int K, int p, cplx *bv, cplx *ev) {
   KTab kt{nk, c->kc3};
   T2d t1{c->t1, no, nv};
   T4 t2{c->t2, nk, no, no, nv, nv};
+  const Lam lam{t1, t2, c->l1, c->l2};
   const size_t n = (size_t)vec_len(c, part);
   if (part == CCGF_PART_IP) {
     // IP layout: [r1[i]], r2[ki][kj][i][j][a], ka = ki + kj - K
@@ -496,16 +512,16 @@ int build_vectors(ccgf_ctx *c, int part, int K, int p, cplx *bv, cplx *ev) {
       if (!c->e_overlap) c->e_overlap = (cplx *)dev_alloc(c, sizeof(cplx) * (size_t)std::max(no, nv));
       if (!c->e_overlap) return CCGF_ENOMEM;
       cplx *hov = c->e_overlap;
-      if (p < no) hipLaunchKernelGGL(k_t2_overlap, dim3(no), dim3(256), 0, s, t2, K, p, hov);
+      if (p < no) hipLaunchKernelGGL(k_t2_overlap, dim3(no), dim3(256), 0, s, t2, lam, K, p, hov);
       foreach_(s, n, [=] __device__(size_t x) {
         cplx v = mkc(0, 0);
         if (x < (size_t)no) {
           int ii = (int)x;
           if (p >= no) {
-            v = cconj(t1(K, ii, p - no));
+            v = lam.one(K, ii, p - no);
           } else {
             v = mkc(ii == p ? 1.0 : 0.0, 0);
-            for (int cc = 0; cc < nv; ++cc) v = csub(v, cmul(t1(K, p, cc), cconj(t1(K, ii, cc))));
+            for (int cc = 0; cc < nv; ++cc) v = csub(v, cmul(t1(K, p, cc), lam.one(K, ii, cc)));
             v = csub(v, cscale(hov[ii], 0.5));
           }
         } else {
@@ -514,11 +530,11 @@ int build_vectors(ccgf_ctx *c, int part, int K, int p, cplx *bv, cplx *ev) {
           int ki = (int)(blk / nk), kj = (int)(blk % nk);
           int a = (int)(r % nv), j = (int)((r / nv) % no), ii = (int)(r / ((size_t)nv * no));
           if (p >= no) {
-            v = cconj(t2(ki, kj, K, ii, j, p - no, a));
+            v = lam.two(ki, kj, K, ii, j, p - no, a);
           } else {
-            if (ki == K && ii == p) v = cadd(v, cconj(t1(kj, j, a)));
-            if (kj == K && j == p) v = csub(v, cconj(t1(ki, ii, a)));
-            for (int cc = 0; cc < nv; ++cc) v = csub(v, cmul(t1(K, p, cc), cconj(t2(ki, kj, K, ii, j, cc, a))));
+            if (ki == K && ii == p) v = cadd(v, lam.one(kj, j, a));
+            if (kj == K && j == p) v = csub(v, lam.one(ki, ii, a));
+            for (int cc = 0; cc < nv; ++cc) v = csub(v, cmul(t1(K, p, cc), lam.two(ki, kj, K, ii, j, cc, a)));
           }
         }
         ev[x] = v;
@@ -551,18 +567,18 @@ int build_vectors(ccgf_ctx *c, int part, int K, int p, cplx *bv, cplx *ev) {
       if (!c->e_overlap) c->e_overlap = (cplx *)dev_alloc(c, sizeof(cplx) * (size_t)std::max(no, nv));
       if (!c->e_overlap) return CCGF_ENOMEM;
       cplx *hov = c->e_overlap;
-      if (p >= no) hipLaunchKernelGGL(k_t2_overlap_ea, dim3(nv), dim3(256), 0, s, t2, kt, K, p - no, hov);
+      if (p >= no) hipLaunchKernelGGL(k_t2_overlap_ea, dim3(nv), dim3(256), 0, s, t2, lam, kt, K, p - no, hov);
       foreach_(s, n, [=] __device__(size_t x) {
         cplx v = mkc(0, 0);
         if (x < (size_t)nv) {
           int a = (int)x;
           if (p < no) {
-            cplx q = cconj(t1(K, p, a));
+            cplx q = lam.one(K, p, a);
             v = mkc(-q.x, -q.y);
           } else {
             int c0 = p - no;
             v = mkc(a == c0 ? 1.0 : 0.0, 0);
-            for (int j = 0; j < no; ++j) v = csub(v, cmul(t1(K, j, c0), cconj(t1(K, j, a))));
+            for (int j = 0; j < no; ++j) v = csub(v, cmul(t1(K, j, c0), lam.one(K, j, a)));
             v = csub(v, cscale(hov[a], 0.5));
           }
         } else {
@@ -572,12 +588,12 @@ int build_vectors(ccgf_ctx *c, int part, int K, int p, cplx *bv, cplx *ev) {
           int b = (int)(r % nv), a = (int)((r / nv) % nv), ii = (int)(r / ((size_t)nv * nv));
           int kb = kt.c3(K, ki, ka);
           if (p < no) {
-            v = cconj(t2(ki, K, ka, ii, p, a, b));
+            v = lam.two(ki, K, ka, ii, p, a, b);
           } else {
             int c0 = p - no;
-            if (ka == K && a == c0) v = cadd(v, cconj(t1(ki, ii, b)));
-            if (kb == K && b == c0) v = csub(v, cconj(t1(ki, ii, a)));
-            for (int j = 0; j < no; ++j) cfma(v, t1(K, j, c0), cconj(t2(ki, K, ka, ii, j, a, b)));
+            if (ka == K && a == c0) v = cadd(v, lam.one(ki, ii, b));
+            if (kb == K && b == c0) v = csub(v, lam.one(ki, ii, a));
+            for (int j = 0; j < no; ++j) cfma(v, t1(K, j, c0), lam.two(ki, K, ka, ii, j, a, b));
           }
         }
         ev[x] = v;

@@ -43,6 +43,8 @@ TID_T2 = 4
 TID_VEC = 5
 TID_ROT = 6
 TID_MISC = 7
+TID_LAM1 = 8
+TID_LAM2 = 9
 
 
 def _rng(seed: int, tid: int, *block: int) -> np.random.Generator:
@@ -159,31 +161,53 @@ def make_system(kmesh=(1, 1, 1), nocc=2, nvir=6, *, seed=BASE_SEED, naux=None,
         for k in range(nk):
             t1[k] = _cnormal(_rng(seed, TID_T1, k), (nocc, nvir), t1_std, real)
 
-    t2 = np.zeros((nk, nk, nk, nocc, nocc, nvir, nvir), dtype=np.complex128)
-    if not zero_t2:
-        tab = _ksum_table(kmesh)
-        raw = {}
-
-        def blk(ki, kj, ka):
-            key = (ki, kj, ka)
-            if key not in raw:
-                raw[key] = _cnormal(_rng(seed, TID_T2, ki, kj, ka), (nocc, nocc, nvir, nvir),
-                                    t2_std * scale, real)
-            return raw[key]
-
-        for ki in range(nk):
-            for kj in range(nk):
-                for ka in range(nk):
-                    kb = tab[ki, kj, ka]
-                    x = (blk(ki, kj, ka)
-                         - blk(kj, ki, ka).transpose(1, 0, 2, 3)
-                         - blk(ki, kj, kb).transpose(0, 1, 3, 2)
-                         + blk(kj, ki, kb).transpose(1, 0, 3, 2))
-                    t2[ki, kj, ka] = 0.5 * x
+    if zero_t2:
+        t2 = np.zeros((nk, nk, nk, nocc, nocc, nvir, nvir), dtype=np.complex128)
+    else:
+        t2 = _doubles(kmesh, nocc, nvir, seed, TID_T2, t2_std * scale, real)
     meta = dict(seed=seed, eri_std=eri_std, t1_std=t1_std, t2_std=t2_std, knorm=knorm,
                 naux=naux, real=real)
     return System(kmesh=kmesh, nocc=nocc, nvir=nvir, eps=eps, eri_factor=A, t1=t1, t2=t2,
                   meta=meta)
+
+
+def _doubles(kmesh, nocc, nvir, seed, tid, std, real):
+    """Seeded doubles amplitudes [ki][kj][ka][i][j][a][b] (kb = ki + kj - ka),
+    antisymmetric under (i,ki)<->(j,kj) and (a,ka)<->(b,kb)."""
+    nk = int(np.prod(kmesh))
+    out = np.zeros((nk, nk, nk, nocc, nocc, nvir, nvir), dtype=np.complex128)
+    tab = _ksum_table(kmesh)
+    raw = {}
+
+    def blk(ki, kj, ka):
+        key = (ki, kj, ka)
+        if key not in raw:
+            raw[key] = _cnormal(_rng(seed, tid, ki, kj, ka), (nocc, nocc, nvir, nvir), std, real)
+        return raw[key]
+
+    for ki in range(nk):
+        for kj in range(nk):
+            for ka in range(nk):
+                kb = tab[ki, kj, ka]
+                x = (blk(ki, kj, ka)
+                     - blk(kj, ki, ka).transpose(1, 0, 2, 3)
+                     - blk(ki, kj, kb).transpose(0, 1, 3, 2)
+                     + blk(kj, ki, kb).transpose(1, 0, 3, 2))
+                out[ki, kj, ka] = 0.5 * x
+    return out
+
+
+def make_lambda(kmesh, nocc, nvir, *, seed=BASE_SEED, l1_std=0.01, l2_std=0.02, knorm="1/Nk", real=False):
+    """Seeded Lambda amplitudes (l1[k][i][a], l2 like t2), independent of T: a
+    stand-in for solved k-point Lambda equations, which the inputs here do not have."""
+    kmesh = tuple(int(x) for x in kmesh)
+    nk = int(np.prod(kmesh))
+    scale = (1.0 / nk) if knorm == "1/Nk" else 1.0
+    l1 = np.zeros((nk, nocc, nvir), dtype=np.complex128)
+    for k in range(nk):
+        l1[k] = _cnormal(_rng(seed, TID_LAM1, k), (nocc, nvir), l1_std, real)
+    l2 = _doubles(kmesh, nocc, nvir, seed, TID_LAM2, l2_std * scale, real)
+    return l1, l2
 
 
 def random_vectors(n: int, nvec: int, *, seed=BASE_SEED, tid=TID_VEC, std=1.0) -> np.ndarray:

@@ -69,6 +69,18 @@ def test_invalid_inputs_are_rejected_on_the_host():
     cs.kmesh = (ctypes.c_int * 3)(2, 0, 1)
     assert lib.cc_gf_init(ctypes.byref(cs), None, ctypes.byref(h)) == ccgf.EINVAL
     assert lib.cc_gf_init(None, None, ctypes.byref(h)) == ccgf.EINVAL
+    # Lambda: both or neither, and l2 antisymmetric
+    l1, l2 = synth.make_lambda((2, 1, 1), 2, 3, seed=4)
+    cs, keep = _system_struct(s)
+    keep += [l1, l2]
+    cs.l1 = l1.ctypes.data
+    assert lib.cc_gf_init(ctypes.byref(cs), None, ctypes.byref(h)) == ccgf.EINVAL
+    l2b = l2.copy()
+    l2b[1, 0, 1, 0, 1, 2, 0] += 0.2
+    keep.append(l2b)
+    cs.l2 = l2b.ctypes.data
+    assert lib.cc_gf_init(ctypes.byref(cs), None, ctypes.byref(h)) == ccgf.EINVAL
+    assert b"l2" in lib.cc_gf_last_error(None)
     # calls on a NULL context
     assert lib.cc_gf_sigma(None, 1, 0, 0, None, None) == ccgf.ESTATE
     assert lib.cc_gf_mor(None, 0, None, 0, None, 1, None, 1, None, 0, None, 0.1, 3, None, None, None,

@@ -53,3 +53,27 @@ def test_sigma_antisymmetric_and_linear():
             assert np.allclose(s12, 2.0 * s1 - 0.5j * s2, atol=1e-12)
             # the output is antisymmetric: unpack(pack(s)) reproduces it
             assert np.allclose(E.unpack(part, K, E.pack(part, K, s1)), s1, atol=1e-13)
+
+
+@pytest.mark.parametrize("no,nv,seed", [(2, 3, 15), (3, 3, 16), (2, 4, 17)])
+def test_e_vectors_with_independent_lambda_match_bruteforce(no, nv, seed):
+    """General Lambda (not T^dagger): the left vectors e of O1 equal the Fock-space
+    brute force <Phi|(1 + Lambda) abar ...| with the same Lambda operator."""
+    s = synth.make_system((1, 1, 1), no, nv, seed=seed, t1_std=0.3, t2_std=0.3, eri_std=0.3)
+    l1, l2 = synth.make_lambda((1, 1, 1), no, nv, seed=seed + 1, l1_std=0.3, l2_std=0.3)
+    assert np.abs(l1 - np.conj(s.t1)).max() > 0.1  # independent of T
+    E = eom.EOMSystem(s, l1=l1, l2=l2)
+    n = no + nv
+    v = eri_blocks(E.mesh, s.eri_factor, slice(0, n), slice(0, n), slice(0, n), slice(0, n)).data[0, 0, 0]
+    f = np.zeros((n, n), complex)
+    f[:no, :no] = E.foo.data[0]
+    f[no:, no:] = E.fvv.data[0]
+    fs = fock.FockSpace(f, v, s.t1[0], s.t2[0, 0, 0], no, l1=l1[0], l2=l2[0, 0, 0])
+    E0 = eom.EOMSystem(s)
+    for part in ("ip", "ea"):
+        for p in range(n):
+            e0, e1 = fs.e_vector(part, p), E.pack(part, 0, E.e_vector(part, 0, p))
+            assert np.allclose(e0, e1, atol=1e-13), (part, p)
+            # b does not depend on Lambda; e does
+            assert np.allclose(E.b_vector(part, 0, p), E0.b_vector(part, 0, p), atol=0)
+        assert max(np.abs(E.e_vector(part, 0, p) - E0.e_vector(part, 0, p)).max() for p in range(n)) > 1e-3

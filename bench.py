@@ -15,7 +15,8 @@ Forms:
     FP64 refinement, starting each solve from the guess of a network trained
     (outside the timed region, reported) on plain solves of all orbitals at the
     frequencies of the first --ntrain warmup steps (those solves are the
-    warmup's work for those steps);
+    warmup's work for those steps), and giving each solve the preconditioner
+    damping a second network predicts from probe solves at those frequencies;
   * ``plain_f64`` on the first ``--compare-steps`` timed steps (same
     frequencies, same tolerance), for the speed-up at equal accuracy;
   * the headline context with its network switched off on the same steps (the
@@ -72,9 +73,11 @@ def parse():
     ap.add_argument("--restart", type=int, default=200)
     ap.add_argument("--batch", type=int, default=90, help="right-hand sides in flight per part (fitted to memory)")
     ap.add_argument("--maxiter", type=int, default=20000)
-    ap.add_argument("--precond-eta", type=float, default=0.4)
-    ap.add_argument("--ntrain", type=int, default=3, help="training frequencies of the network (the first "
-                                                            "warmup steps' frequencies)")
+    ap.add_argument("--precond-eta", type=float, default=0.25)
+    ap.add_argument("--ntrain", type=int, default=4, help="training frequencies of the networks (the first "
+                                                            "warmup steps' frequencies, all orbitals)")
+    ap.add_argument("--probe", type=int, default=30, help="GMRES steps of each probe solve of the "
+                                                           "preconditioner network (-1: none)")
     ap.add_argument("--budget-s", type=float, default=430.0,
                     help="wall-clock budget: optional legs are skipped when they would exceed it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -271,10 +274,12 @@ def main():
     nwarm_plain = 0
     if learned and args.warmup > 0:
         # the network learns from plain solves of all orbitals at the first warmup steps' frequencies
-        nwarm_plain = max(1, min(args.ntrain, args.warmup))
+        # (at least one ordinary warmup step follows when there are two or more: the learned
+        # path's first solves build their own plans)
+        nwarm_plain = max(1, min(args.ntrain, args.warmup - 1 if args.warmup > 1 else 1))
         wtrain = sorted(set(wstep[:nwarm_plain]))
         t1 = time.perf_counter()
-        learn = ctx.learn(0, orbs, wtrain, eta, allow_noconv=True)
+        learn = ctx.learn(0, orbs, wtrain, eta, probe=args.probe, allow_noconv=True)
         learn["seconds"] = time.perf_counter() - t1
         learn["omega_train"] = wtrain
         log(f"{form}: training at {len(wtrain)} frequencies {learn['seconds']:.1f} s")

@@ -215,6 +215,8 @@ typedef struct {
   double accept;           /* a guess is used only if ||b - A x0|| < accept * ||b||, in (0, 1];
                               0 -> 0.1 (a guess that leaves most of b tends to slow GMRES:
                               its residual is rich in the near-resonant directions) */
+  int probe;               /* learned preconditioner: GMRES steps of each probe solve (below);
+                              0 -> 40; -1: no preconditioner network */
 } ccgf_learn_options;
 enum { CCGF_GUESS_NETWORK = 0, CCGF_GUESS_NEAREST = 1 };
 
@@ -226,10 +228,17 @@ typedef struct {
   double solve_seconds;     /* plain solves that produced the training solutions */
   double train_seconds;     /* network training on the GPU */
   long long solve_iterations;
+  double probe_seconds;     /* probe solves of the preconditioner network */
+  double precond_loss_initial; /* its mean squared error / 2 before and after training */
+  double precond_loss_final;
 } ccgf_learn_stats;
 
+/* Candidate dampings of the learned preconditioner, in units of the largest of eta and
+ * the context's precond_eta: D = w -/+ diag(M) +/- i eta_p with eta_p one of these. */
+#define CCGF_PRECOND_CANDIDATES 5
+
 /* Train the initial-guess network of momentum K and the given parts
- * (CCGF_PART_*).  The plain solver (the context's options) solves the shifted
+ * (CCGF_PART_*), and the preconditioner network.  The plain solver (the context's options) solves the shifted
  * systems of Eq. 6 for every (orbs[b], omega_train[j]); per orbital, the
  * solutions are orthonormalised (Gram-Schmidt twice, dependent columns zeroed)
  * into a basis Q_p of rank ntrain, and c_j = Q_p^H x_j are their reduced
@@ -240,9 +249,18 @@ typedef struct {
  * starts each (K, p, w) solve of a trained orbital from x0 = Q_p c_hat,
  * c_hat = c_ref + network output, with c_ref taken at the training frequency
  * nearest to w; a guess whose residual is not below accept * ||b|| is
- * discarded and the solve starts from zero.  The model
- * replaces any earlier one of the same (part, K).  ntrain in 1..32, sorted
- * ascending, finite.  opt and st may be NULL.  Device memory: ntrain * norb
+ * discarded and the solve starts from zero.
+ * Preconditioner network (unless opt->probe = -1): every training (p, w) is
+ * solved again from zero for opt->probe GMRES steps with each candidate damping
+ * eta_p of the diagonal preconditioner (0.25, 0.5, 1, 1.5, 2.5 times the context's
+ * damping), all in one batch, and a second perceptron of the same form learns
+ *   (w, Fock diagonal of p, occupied flag, w - Fock diagonal) -> log10 of each
+ * candidate's relative residual after those steps.  cc_gf_solve then gives each
+ * (K, p, w) solve the damping the network predicts to leave the smallest residual:
+ * a per-right-hand-side diagonal correction of D, judged like any preconditioner
+ * by the FP64 true residual (it changes the iteration count, never the solution).
+ * The model replaces any earlier one of the same (part, K).  ntrain in 1..32,
+ * sorted ascending, finite.  opt and st may be NULL.  Device memory: ntrain * norb
  * vectors per part are kept for the basis. */
 int cc_gf_learn(ccgf_ctx *ctx, int parts, int K, int norb, const int *orbs, int ntrain,
                 const double *omega_train, double eta, const ccgf_learn_options *opt_opt,
@@ -257,7 +275,10 @@ int cc_gf_learn(ccgf_ctx *ctx, int parts, int K, int norb, const int *orbs, int 
  * Waits for the context's stream before switching. */
 int cc_gf_set_options(ccgf_ctx *ctx, const ccgf_options *opt);
 
-/* Use (on != 0, the default) or ignore the trained networks in cc_gf_solve. */
+/* Which trained networks cc_gf_solve uses: a mask of CCGF_LEARN_GUESS (initial
+ * guesses) and CCGF_LEARN_PRECOND (per-solve preconditioner damping); 0 ignores
+ * both.  Every cc_gf_learn call sets both again. */
+enum { CCGF_LEARN_GUESS = 1, CCGF_LEARN_PRECOND = 2 };
 int cc_gf_learn_enable(ccgf_ctx *ctx, int on);
 
 /* Least-squares loss and its gradient for the network above, for checking the

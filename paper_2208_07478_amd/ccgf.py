@@ -64,13 +64,15 @@ class Stats(ctypes.Structure):
 class LearnOptions(ctypes.Structure):
     _fields_ = [("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_double),
                 ("seed", ctypes.c_ulonglong), ("hidden", ctypes.c_int), ("guess", ctypes.c_int),
-                ("accept", ctypes.c_double)]
+                ("accept", ctypes.c_double), ("probe", ctypes.c_int)]
 
 
 class LearnStats(ctypes.Structure):
     _fields_ = [("pairs", ctypes.c_longlong), ("rank", ctypes.c_int), ("loss_initial", ctypes.c_double),
                 ("loss_final", ctypes.c_double), ("solve_seconds", ctypes.c_double),
-                ("train_seconds", ctypes.c_double), ("solve_iterations", ctypes.c_longlong)]
+                ("train_seconds", ctypes.c_double), ("solve_iterations", ctypes.c_longlong),
+                ("probe_seconds", ctypes.c_double), ("precond_loss_initial", ctypes.c_double),
+                ("precond_loss_final", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -307,12 +309,12 @@ class Context:
         return G, Gp, Gm, dos, st.as_dict()
 
     def learn(self, K: int, orbs: Sequence[int], omega_train, eta: float, parts="both", epochs=0, batch=0, lr=0.0,
-              seed=0, hidden=0, guess="network", accept=0.0, allow_noconv=False):
+              seed=0, hidden=0, guess="network", accept=0.0, probe=0, allow_noconv=False):
         """Train the initial-guess network of momentum K on plain solves at omega_train."""
         orbs = np.ascontiguousarray(np.asarray(orbs, dtype=np.int32))
         wt = np.ascontiguousarray(np.asarray(omega_train, dtype=np.float64))
         lo = LearnOptions(int(epochs), int(batch), float(lr), int(seed), int(hidden),
-                          {"network": 0, "nearest": 1}[guess], float(accept))
+                          {"network": 0, "nearest": 1}[guess], float(accept), int(probe))
         ls = LearnStats()
         rc = load().cc_gf_learn(self._h, _part(parts), int(K), len(orbs), orbs.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                                 len(wt), wt.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(eta),
@@ -320,8 +322,11 @@ class Context:
         self._check(rc, allow=(ENOCONV,) if allow_noconv else ())
         return ls.as_dict()
 
-    def learn_enable(self, on: bool):
-        self._check(load().cc_gf_learn_enable(self._h, 1 if on else 0))
+    def learn_enable(self, on=True, *, guess=None, precond=None):
+        """Use the trained networks (on) or none; guess / precond select each one."""
+        g = on if guess is None else guess
+        p = on if precond is None else precond
+        self._check(load().cc_gf_learn_enable(self._h, (1 if g else 0) | (2 if p else 0)))
 
     def mor(self, kidx: Sequence[int], orbs: Sequence[int], wexp_ip, wexp_ea, omega, eta: float, parts="both",
             allow_noconv=False):

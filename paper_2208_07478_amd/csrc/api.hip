@@ -300,12 +300,17 @@ static int solve_common(ccgf_ctx *c, int nkq, const int *kidx, int norb, const i
       Guess gs;
       const Guess *gp = nullptr;
       cplx *chat = nullptr;
-      if (c->learn_on)
-        for (const LearnModel &M : c->models)
-          if (M.part == part && M.K == K) {
-            if (learn_guess(c, M, nrhs, rhs_orb.data(), orbs, rhs_w.data(), gs, &chat)) gp = &gs;
-            break;
-          }
+      std::vector<double> peta;
+      bool have_peta = false;
+      for (const LearnModel &M : c->models)
+        if (M.part == part && M.K == K) {
+          if ((c->learn_on & CCGF_LEARN_GUESS) &&
+              learn_guess(c, M, nrhs, rhs_orb.data(), orbs, rhs_w.data(), gs, &chat))
+            gp = &gs;
+          if (c->learn_on & CCGF_LEARN_PRECOND)
+            have_peta = learn_precond(c, M, nrhs, rhs_orb.data(), orbs, rhs_w.data(), peta);
+          break;
+        }
       cplx *seedQ = nullptr;
       if (!gp && c->opt.seed_m > 0) {
         int rs = seed_krylov(c, part, K, norb, Bv, nrhs, rhs_orb.data(), rhs_w.data(), eta, gs, &seedQ, &chat, S);
@@ -316,7 +321,7 @@ static int solve_common(ccgf_ctx *c, int nkq, const int *kidx, int norb, const i
         }
       }
       int rc = solve_batched(c, part, K, nrhs, rhs_orb.data(), rhs_w.data(), eta, Bv, Ev, res.data(), S, nullptr, gp,
-                             Gmat ? cols.data() : nullptr, Gmat ? norb : 0);
+                             Gmat ? cols.data() : nullptr, Gmat ? norb : 0, have_peta ? peta.data() : nullptr);
       if (chat) hipFree(chat);
       if (seedQ) hipFree(seedQ);
       if (rc != CCGF_OK) {
@@ -488,13 +493,16 @@ extern "C" int cc_gf_learn(ccgf_ctx *c, int parts, int K, int norb, const int *o
   if (lo.lr == 0) lo.lr = 1e-3;
   if (lo.hidden == 0) lo.hidden = 256;
   if (lo.accept == 0) lo.accept = 0.1;
+  if (lo.probe == 0) lo.probe = 40;
   if (lo.epochs < 0 || lo.batch < 1 || !(lo.lr > 0) || lo.hidden < 1 || lo.hidden > 4096 ||
-      (lo.guess != CCGF_GUESS_NETWORK && lo.guess != CCGF_GUESS_NEAREST) || !(lo.accept > 0) || lo.accept > 1)
+      (lo.guess != CCGF_GUESS_NETWORK && lo.guess != CCGF_GUESS_NEAREST) || !(lo.accept > 0) || lo.accept > 1 ||
+      lo.probe < -1 || lo.probe > 2000)
     return set_err(c, CCGF_EINVAL, "learning options out of range");
   ccgf_learn_stats local{};
   ccgf_learn_stats *S = st ? st : &local;
   std::memset(S, 0, sizeof(*S));
   int status = CCGF_OK;
+  c->learn_on = CCGF_LEARN_GUESS | CCGF_LEARN_PRECOND;  // a fresh model is used until disabled
   for (int part : {CCGF_PART_IP, CCGF_PART_EA}) {
     if (!(parts & part)) continue;
     int rc = learn_part(c, part, K, norb, orbs, ntrain, wtr, eta, lo, S);
@@ -532,7 +540,9 @@ extern "C" int cc_gf_set_options(ccgf_ctx *c, const ccgf_options *opt) {
 
 extern "C" int cc_gf_learn_enable(ccgf_ctx *c, int on) {
   if (!c) return CCGF_ESTATE;
-  c->learn_on = on != 0;
+  if (on < 0 || on > (CCGF_LEARN_GUESS | CCGF_LEARN_PRECOND))
+    return set_err(c, CCGF_EINVAL, "on must be a mask of CCGF_LEARN_GUESS and CCGF_LEARN_PRECOND");
+  c->learn_on = on;
   return CCGF_OK;
 }
 
@@ -542,6 +552,7 @@ extern "C" void cc_gf_free(ccgf_ctx *c) {
   for (LearnModel &M : c->models) {
     if (M.Q) hipFree(M.Q);
     if (M.theta) hipFree(M.theta);
+    if (M.theta_p) hipFree(M.theta_p);
   }
   c->models.clear();
   timing_release(c);

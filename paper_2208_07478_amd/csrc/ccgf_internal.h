@@ -186,7 +186,22 @@ struct LearnModel {
   double wscale = 1, wstep = 1;
   cplx *Q = nullptr;            // device [norb][R][n] orthonormal basis (zero columns allowed)
   float *theta = nullptr;       // device parameters
+  // preconditioner network: features -> log10 residual after the probe steps per candidate damping
+  int pdin = 0, pdout = 0;
+  double pbase = 0;             // damping unit: max(eta, precond_eta) at training
+  float *theta_p = nullptr;     // device parameters (null: none trained)
 };
+// Features of the preconditioner network for orbital b at frequency w.
+void precond_features(const LearnModel &M, int b, double w, float *f);
+extern const double kPrecondCand[CCGF_PRECOND_CANDIDATES];
+// Per-right-hand-side damping chosen by the preconditioner network (false: none).
+bool learn_precond(ccgf_ctx *c, const LearnModel &M, int nrhs, const int *rhs_orb, const int *orbs,
+                   const double *rhs_omega, std::vector<double> &peta);
+// Train a three-layer perceptron on (F [P][din], T [P][dout]) with Adam; *theta (device) receives
+// the parameters (allocated here); L0 / L1 the loss before and after.
+int mlp_train(ccgf_ctx *c, int din, int hidden, int dout, long long P, const std::vector<float> &F,
+              const std::vector<float> &T, int epochs, int batch, double lr, unsigned long long seed, bool zero_out,
+              float **theta, double *L0, double *L1);
 // Initial guesses for solve_batched: x0 of right-hand side r = Q[qidx[r]] chat[r]
 struct Guess {
   const cplx *Q = nullptr;      // [nq][R][n]
@@ -243,7 +258,7 @@ struct ccgf_ctx {
   hipEvent_t tev[2] = {nullptr, nullptr};
   hipStream_t cap_stream = nullptr;  // private stream on which sigma launch sequences are captured
   std::string tune_path;
-  int learn_on = 1;                 // use them in cc_gf_solve
+  int learn_on = 3;                 // use them in cc_gf_solve (CCGF_LEARN_* mask)
   // event timing of the sigma products (options.timing)
   // sigma timing (options.timing): events of recent products, read once they have completed
   struct TimedSigma {
@@ -289,7 +304,8 @@ int seed_krylov(ccgf_ctx *c, int part, int K, int norb, const cplx *Bvecs, int n
                 const double *rhs_omega, double eta, Guess &g, cplx **Q, cplx **chat, ccgf_stats *st);
 int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb_slot, const double *rhs_omega,
                   double eta, const cplx *Bvecs, const cplx *Evecs, cplx *Gout, ccgf_stats *st,
-                  cplx *Xout = nullptr, const Guess *guess = nullptr, cplx *Gcols = nullptr, int ncols = 0);
+                  cplx *Xout = nullptr, const Guess *guess = nullptr, cplx *Gcols = nullptr, int ncols = 0,
+                  const double *rhs_peta = nullptr, double *rhs_res = nullptr);
 int learn_part(ccgf_ctx *c, int part, int K, int norb, const int *orbs, int ntrain, const double *wtrain, double eta,
                const ccgf_learn_options &lo, ccgf_learn_stats *ls);
 // Device reduced coordinates (chat, [nrhs][R]) of the network's guesses for the listed

@@ -120,27 +120,42 @@ __global__ __launch_bounds__(256) void k_dots(const cplx *__restrict__ U, const 
 }
 
 // out[v][i] = sum_chunk partial; if H != null also H[v][i][col] += out (and H2 likewise);
-// per-slot counts and columns as in k_dots
-__global__ void k_dots_reduce(const cplx *__restrict__ partial, int nchunk, int ldp, int ni0,
-                              const int *__restrict__ active, cplx *__restrict__ out, int ldo,
-                              cplx *__restrict__ H, int ldh, long long shv, int col0, cplx *__restrict__ H2,
-                              const int *__restrict__ nlist, const int *__restrict__ colv) {
+// per-slot counts and columns as in k_dots.  One 256-thread block per slot: 64 columns at a
+// time, each summed over the chunks by four thread groups (independent loads in flight), then
+// the four group sums added in LDS.
+__global__ __launch_bounds__(256) void k_dots_reduce(const cplx *__restrict__ partial, int nchunk, int ldp, int ni0,
+                                                     const int *__restrict__ active, cplx *__restrict__ out, int ldo,
+                                                     cplx *__restrict__ H, int ldh, long long shv, int col0,
+                                                     cplx *__restrict__ H2, const int *__restrict__ nlist,
+                                                     const int *__restrict__ colv) {
   const int v = blockIdx.x;
   if (active && !active[v]) return;
   const int ni = nlist ? nlist[v] + ni0 : ni0;
   const int col = colv ? colv[v] : col0;
-  for (int i = threadIdx.x; i < ni; i += blockDim.x) {
-    cplx s = mkc(0, 0);
-    for (int ch = 0; ch < nchunk; ++ch) s = cadd(s, partial[((size_t)v * nchunk + ch) * ldp + i]);
-    out[(size_t)v * ldo + i] = s;
-    if (H) {
-      cplx *h = H + (size_t)v * shv + (size_t)i * ldh + col;
-      *h = cadd(*h, s);
+  const int il = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  __shared__ double red[2][4][64];
+  for (int i0 = 0; i0 < ni; i0 += 64) {
+    const int i = i0 + il;
+    cplx acc = mkc(0, 0);
+    if (i < ni)
+      for (int ch = grp; ch < nchunk; ch += 4) acc = cadd(acc, partial[((size_t)v * nchunk + ch) * ldp + i]);
+    red[0][grp][il] = acc.x;
+    red[1][grp][il] = acc.y;
+    __syncthreads();
+    if (grp == 0 && i < ni) {
+      const cplx s = mkc(red[0][0][il] + red[0][1][il] + red[0][2][il] + red[0][3][il],
+                         red[1][0][il] + red[1][1][il] + red[1][2][il] + red[1][3][il]);
+      out[(size_t)v * ldo + i] = s;
+      if (H) {
+        cplx *h = H + (size_t)v * shv + (size_t)i * ldh + col;
+        *h = cadd(*h, s);
+      }
+      if (H2) {
+        cplx *h = H2 + (size_t)v * shv + (size_t)i * ldh + col;
+        *h = cadd(*h, s);
+      }
     }
-    if (H2) {
-      cplx *h = H2 + (size_t)v * shv + (size_t)i * ldh + col;
-      *h = cadd(*h, s);
-    }
+    __syncthreads();
   }
 }
 
@@ -679,7 +694,7 @@ static void build_pack(const ccgf_ctx *c, int part, int K, long long n, std::vec
 
 int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, const double *rhs_omega, double eta,
                   const cplx *Bvecs, const cplx *Evecs, cplx *Gout, ccgf_stats *st, cplx *Xout, const Guess *guess,
-                  cplx *Gcols, int ncols) {
+                  cplx *Gcols, int ncols, const double *rhs_peta, double *rhs_res) {
   const long long n = vec_len(c, part);
   const int n1 = part == CCGF_PART_IP ? c->no : c->nv;
   const double sM = part == CCGF_PART_IP ? 1.0 : -1.0;
@@ -814,7 +829,7 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
   auto norms = [&](const cplx *Xp, int B) {
     hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Xp, uoff, 0LL, 1, Xp, n, n1, 1,
                        (const int *)nullptr, partial, nchunk, ldp, (const int *)nullptr);
-    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, 1, (const int *)nullptr, htmp,
+    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(256), 0, s, partial, nchunk, ldp, 1, (const int *)nullptr, htmp,
                        ldp, (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
   };
   // true residual b - A x of the listed right-hand sides into R and its norm into hh
@@ -874,14 +889,14 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
     hipMemcpyAsync(fmask, msk.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
     hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Evecs, eoff, 0LL, 1, X, n, n1, 0,
                        (const int *)fmask, partial, nchunk, ldp, (const int *)nullptr);
-    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, 1, (const int *)fmask, htmp,
+    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(256), 0, s, partial, nchunk, ldp, 1, (const int *)fmask, htmp,
                        ldp, (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
     hipMemcpyAsync(hh.data(), htmp, sizeof(cplx) * B * ldp, hipMemcpyDeviceToHost, s);
     std::vector<cplx> hcol;
     if (cols) {  // every left vector of the call against the finished solutions
       hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Evecs, zoff, (long long)n, ncols, X, n, n1, 0,
                          (const int *)fmask, partE, nchunk, ncols, (const int *)nullptr);
-      hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partE, nchunk, ncols, ncols, (const int *)fmask,
+      hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(256), 0, s, partE, nchunk, ncols, ncols, (const int *)fmask,
                          outE, ncols, (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr,
                          (const int *)nullptr);
       hcol.resize((size_t)B * ncols);
@@ -897,6 +912,7 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
         for (int r = 0; r < ncols; ++r) Gcols[(size_t)rhs_of[v] * ncols + r] = hcol[(size_t)v * ncols + r];
       double rel = hbnorm[v] > 0 ? hrn[v] / hbnorm[v] : 0.0;
       bool ok = hbnorm[v] == 0.0 || rel <= tol;
+      if (rhs_res) rhs_res[rhs_of[v]] = rel;
       if (st) {
         st->n_solves += 1;
         st->n_iterations += its[v];
@@ -916,7 +932,7 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
       const int r = rhs_of[v];
       msk[v] = 1;
       hshift[v] = mkc(rhs_omega[r], sE * eta);
-      hpshift[v] = mkc(rhs_omega[r], sE * peta);
+      hpshift[v] = mkc(rhs_omega[r], sE * (rhs_peta && rhs_peta[r] >= 0 ? std::max(eta, rhs_peta[r]) : peta));
       heoff[v] = (long long)rhs_orb[r] * n;
       hipMemcpyAsync(Bv + (size_t)v * n, Bvecs + (size_t)rhs_orb[r] * n, sizeof(cplx) * n, hipMemcpyDeviceToDevice,
                      s);
@@ -930,7 +946,7 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
     hipMemcpyAsync(fmask, msk.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
     hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Bv, uoff, 0LL, 1, Bv, n, n1, 1, (const int *)fmask,
                        partial, nchunk, ldp, (const int *)nullptr);
-    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, 1, (const int *)fmask, htmp,
+    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(256), 0, s, partial, nchunk, ldp, 1, (const int *)fmask, htmp,
                        ldp, (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
     hipMemcpyAsync(hh.data(), htmp, sizeof(cplx) * B * ldp, hipMemcpyDeviceToHost, s);
     if (int rc = sync("solver start")) return rc;
@@ -1082,7 +1098,7 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
     // ||w||^2 before projection (for the reorthogonalisation test)
     hipLaunchKernelGGL(k_dots, dim3(nchb, B), dim3(256), 0, s, Wv, uoffb, 0LL, 1, Wv, nb, n1b, 1, active, partial,
                        nchb, ldp, (const int *)nullptr);
-    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchb, ldp, 1, active, htmp, ldp,
+    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(256), 0, s, partial, nchb, ldp, 1, active, htmp, ldp,
                        (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
     hipLaunchKernelGGL(k_take_norm, dim3((B + 63) / 64), dim3(64), 0, s, B, htmp, ldp, w0n, active);
     // classical Gram-Schmidt against the recycled C and V_0..V_j, a second pass where the first
@@ -1092,20 +1108,20 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
       if (kc > 0) {  // (GCROT: full vectors, nb = n)
         hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Cb, uoff, (long long)svi, kc, Wv, n, n1, 1,
                            mask, partial, nchunk, ldp, (const int *)nullptr);
-        hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, kc, mask, htmp, ldp, Bm, m,
+        hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(256), 0, s, partial, nchunk, ldp, kc, mask, htmp, ldp, Bm, m,
                            (long long)kslots * m, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)jvd);
         hipLaunchKernelGGL(k_sub_proj, dim3(gx, B), dim3(256), 0, s, Wv, Cb, (long long)svi, n, kc, htmp, ldp, mask,
                            (const int *)nullptr);
       }
       hipLaunchKernelGGL(k_dots, dim3(nchb, B), dim3(256), 0, s, V, uoffb, (long long)svb, 1, Wv, nb, n1b, 1, mask,
                          partial, nchb, ldp, (const int *)jvd);
-      hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchb, ldp, 1, mask, htmp, ldp, H, m,
+      hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(256), 0, s, partial, nchb, ldp, 1, mask, htmp, ldp, H, m,
                          (long long)(m + 1) * m, 0, H0, (const int *)jvd, (const int *)jvd);
       hipLaunchKernelGGL(k_sub_proj, dim3(gxb, B), dim3(256), 0, s, Wv, V, (long long)svb, nb, 1, htmp, ldp, mask,
                          (const int *)jvd);
       hipLaunchKernelGGL(k_dots, dim3(nchb, B), dim3(256), 0, s, Wv, uoffb, 0LL, 1, Wv, nb, n1b, 1, mask, partial,
                          nchb, ldp, (const int *)nullptr);
-      hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchb, ldp, 1, mask, htmp, ldp,
+      hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(256), 0, s, partial, nchb, ldp, 1, mask, htmp, ldp,
                          (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
       if (pass == 0)
         hipLaunchKernelGGL(k_need_reorth, dim3((B + 63) / 64), dim3(64), 0, s, B, htmp, ldp, w0n, active, need,
@@ -1186,7 +1202,7 @@ int solve_batched(ccgf_ctx *c, int part, int K, int nrhs, const int *rhs_orb, co
         hipMemcpyAsync(active, redo.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
         hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Cb, uoff, (long long)svi, kcn, R, n, n1, 1,
                            active, partial, nchunk, ldp, (const int *)nullptr);
-        hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, kcn, active, htmp, ldp,
+        hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(256), 0, s, partial, nchunk, ldp, kcn, active, htmp, ldp,
                            (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
         hipLaunchKernelGGL(k_add_proj, dim3(gx, B), dim3(256), 0, s, X, Ub, (long long)svi, n, kcn, htmp, ldp, active);
         hipLaunchKernelGGL(k_sub_proj, dim3(gx, B), dim3(256), 0, s, R, Cb, (long long)svi, n, kcn, htmp, ldp, active,
@@ -1347,7 +1363,7 @@ int seed_krylov(ccgf_ctx *c, int part, int K, int norb, const cplx *Bvecs, int n
   // beta_q = ||b_q||, v_0 = b_q / beta_q
   hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Bvecs, uoff, 0LL, 1, Bvecs, n, n1, 1,
                      (const int *)nullptr, partial, nchunk, ldp, (const int *)nullptr);
-  hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, 1, (const int *)nullptr, htmp, ldp,
+  hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(256), 0, s, partial, nchunk, ldp, 1, (const int *)nullptr, htmp, ldp,
                      (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
   std::vector<cplx> hh((size_t)B * ldp);
   hipMemcpyAsync(hh.data(), htmp, sizeof(cplx) * B * ldp, hipMemcpyDeviceToHost, s);
@@ -1373,7 +1389,7 @@ int seed_krylov(ccgf_ctx *c, int part, int K, int norb, const cplx *Bvecs, int n
     for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
       hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Q, uoff, (long long)vb, j + 1, Wv, n, n1, 1,
                          (const int *)act, partial, nchunk, ldp, (const int *)nullptr);
-      hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, j + 1, (const int *)act, htmp,
+      hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(256), 0, s, partial, nchunk, ldp, j + 1, (const int *)act, htmp,
                          ldp, H, m, (long long)(m + 1) * m, j, (cplx *)nullptr, (const int *)nullptr,
                          (const int *)nullptr);
       hipLaunchKernelGGL(k_sub_proj, dim3(gx, B), dim3(256), 0, s, Wv, Q, (long long)vb, n, j + 1, htmp, ldp,
@@ -1381,7 +1397,7 @@ int seed_krylov(ccgf_ctx *c, int part, int K, int norb, const cplx *Bvecs, int n
     }
     hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, Wv, uoff, 0LL, 1, Wv, n, n1, 1, (const int *)act,
                        partial, nchunk, ldp, (const int *)nullptr);
-    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, 1, (const int *)act, htmp, ldp,
+    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(256), 0, s, partial, nchunk, ldp, 1, (const int *)act, htmp, ldp,
                        (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
     hipLaunchKernelGGL(k_seed_norm, dim3((B + 63) / 64), dim3(64), 0, s, B, htmp, ldp, H, m, j, inv, act, mlen);
     hipLaunchKernelGGL(k_scale, dim3(gx, B), dim3(256), 0, s, Q + (size_t)(j + 1) * vb, Wv, inv, n,
@@ -1437,7 +1453,7 @@ static int group_basis(ccgf_ctx *c, long long n, int n1, int ngroup, int ncol, c
   auto dots = [&](const cplx *U, const long long *uoff, long long su, int ni, const cplx *Wp, int B) {
     hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, U, uoff, su, ni, Wp, n, n1, 1, (const int *)nullptr,
                        partial, nchunk, ldp, (const int *)nullptr);
-    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, ni, (const int *)nullptr, out,
+    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(256), 0, s, partial, nchunk, ldp, ni, (const int *)nullptr, out,
                        ldp, (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
   };
   for (int v = 0; v < nrhs; ++v) ha[v] = (long long)v * n;
@@ -1541,7 +1557,7 @@ int mor_part(ccgf_ctx *c, int part, int K, int norb, const int *orbs, int nexp, 
   auto dots = [&](const cplx *U, const long long *uoff, long long su, int ni, const cplx *Wp, int B, int conjU) {
     hipLaunchKernelGGL(k_dots, dim3(nchunk, B), dim3(256), 0, s, U, uoff, su, ni, Wp, n, n1, conjU,
                        (const int *)nullptr, partial, nchunk, ldp, (const int *)nullptr);
-    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(64), 0, s, partial, nchunk, ldp, ni, (const int *)nullptr, out,
+    hipLaunchKernelGGL(k_dots_reduce, dim3(B), dim3(256), 0, s, partial, nchunk, ldp, ni, (const int *)nullptr, out,
                        ldp, (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
   };
   if (int rc = group_basis(c, n, n1, norb, nexp, S)) {
@@ -1635,6 +1651,7 @@ int learn_part(ccgf_ctx *c, int part, int K, int norb, const int *orbs, int ntra
   auto fail = [&](int rc) {
     if (M.Q) hipFree(M.Q);
     if (M.theta) hipFree(M.theta);
+    if (M.theta_p) hipFree(M.theta_p);
     return rc;
   };
   GmresWork W;
@@ -1676,7 +1693,7 @@ int learn_part(ccgf_ctx *c, int part, int K, int norb, const int *orbs, int ntra
   hipMemcpyAsync(off_a, ha.data(), sizeof(long long) * nrhs, hipMemcpyHostToDevice, s);
   hipLaunchKernelGGL(k_dots, dim3(nchunk, nrhs), dim3(256), 0, s, M.Q, off_a, n, R, X, n, n1, 1, (const int *)nullptr,
                      partial, nchunk, ldp, (const int *)nullptr);
-  hipLaunchKernelGGL(k_dots_reduce, dim3(nrhs), dim3(64), 0, s, partial, nchunk, ldp, R, (const int *)nullptr, out, ldp,
+  hipLaunchKernelGGL(k_dots_reduce, dim3(nrhs), dim3(256), 0, s, partial, nchunk, ldp, R, (const int *)nullptr, out, ldp,
                      (cplx *)nullptr, 0, 0LL, 0, (cplx *)nullptr, (const int *)nullptr, (const int *)nullptr);
   std::vector<cplx> hh((size_t)nrhs * ldp);
   hipMemcpyAsync(hh.data(), out, sizeof(cplx) * nrhs * ldp, hipMemcpyDeviceToHost, s);
@@ -1735,91 +1752,70 @@ int learn_part(ccgf_ctx *c, int part, int K, int norb, const int *orbs, int ntra
         }
         ++P;
       }
-  // parameters: uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) hidden weights, zero biases and a zero
-  // output layer, so that the untrained network proposes the reference solution itself
-  const long long np = mlp_nparams(M.din, M.hidden, M.dout);
-  std::vector<float> th(np, 0.0f);
-  std::mt19937_64 rng(lo.seed);
-  {
-    long long o = 0;
-    const int fin[3] = {M.din, M.hidden, M.hidden}, fout[3] = {M.hidden, M.hidden, M.dout};
-    for (int l = 0; l < 2; ++l) {
-      std::uniform_real_distribution<float> U(-1.0f / std::sqrt((float)fin[l]), 1.0f / std::sqrt((float)fin[l]));
-      for (long long q = 0; q < (long long)fout[l] * fin[l]; ++q) th[o + q] = U(rng);
-      o += (long long)fout[l] * fin[l] + fout[l];
-    }
-  }
-  const int bs = (int)std::min<long long>(P, lo.batch);
-  MlpWork w;
-  float *dF = nullptr, *dT = nullptr, *mm = nullptr, *vv = nullptr;
-  bool ok = mlp_alloc(w, M.din, M.hidden, M.dout, (int)P) && hipMalloc(&M.theta, sizeof(float) * np) == hipSuccess &&
-            hipMalloc(&dF, sizeof(float) * F.size()) == hipSuccess &&
-            hipMalloc(&dT, sizeof(float) * T.size()) == hipSuccess && hipMalloc(&mm, sizeof(float) * np) == hipSuccess &&
-            hipMalloc(&vv, sizeof(float) * np) == hipSuccess;
-  auto cleanup = [&]() {
-    mlp_free(w);
-    if (dF) hipFree(dF);
-    if (dT) hipFree(dT);
-    if (mm) hipFree(mm);
-    if (vv) hipFree(vv);
-  };
-  if (!ok) {
-    (void)hipGetLastError();
-    cleanup();
-    return fail(set_err(c, CCGF_ENOMEM, "no device memory for the network"));
-  }
-  hipMemcpyAsync(M.theta, th.data(), sizeof(float) * np, hipMemcpyHostToDevice, s);
-  hipMemsetAsync(mm, 0, sizeof(float) * np, s);
-  hipMemsetAsync(vv, 0, sizeof(float) * np, s);
-  auto full_loss = [&](double &L) -> int {
-    hipMemcpyAsync(dF, F.data(), sizeof(float) * F.size(), hipMemcpyHostToDevice, s);
-    hipMemcpyAsync(dT, T.data(), sizeof(float) * T.size(), hipMemcpyHostToDevice, s);
-    const int nb = mlp_backward(s, w, M.theta, (int)P, dF, dT);
-    std::vector<double> lp(nb);
-    hipMemcpyAsync(lp.data(), w.lpart, sizeof(double) * nb, hipMemcpyDeviceToHost, s);
-    int rc = hip_check(c, hipStreamSynchronize(s), "network loss");
-    L = 0;
-    for (double x : lp) L += x;
-    L *= 0.5 / (double)P;
-    return rc;
-  };
   double L0 = 0, L1 = 0;
-  if (int rc = full_loss(L0)) {
-    cleanup();
+  // the untrained network (zero output layer) proposes the reference solution itself
+  if (int rc = mlp_train(c, M.din, M.hidden, M.dout, P, F, T, lo.epochs, lo.batch, lo.lr, lo.seed, true, &M.theta,
+                         &L0, &L1))
     return fail(rc);
-  }
-  std::vector<long long> perm(P);
-  std::vector<float> Fs(F.size()), Ts(T.size());
-  int t = 0;
-  for (int e = 0; e < lo.epochs; ++e) {
-    for (long long q = 0; q < P; ++q) perm[q] = q;
-    std::shuffle(perm.begin(), perm.end(), rng);
-    for (long long q = 0; q < P; ++q) {
-      std::copy(&F[(size_t)perm[q] * M.din], &F[(size_t)perm[q] * M.din] + M.din, &Fs[(size_t)q * M.din]);
-      std::copy(&T[(size_t)perm[q] * M.dout], &T[(size_t)perm[q] * M.dout] + M.dout, &Ts[(size_t)q * M.dout]);
+  // preconditioner network: probe solves of every training (p, w) with each candidate damping
+  double probe_s = 0, PL0 = 0, PL1 = 0;
+  if (lo.probe >= 0) {
+    auto tp = std::chrono::steady_clock::now();
+    const int nc = CCGF_PRECOND_CANDIDATES;
+    M.pbase = std::max(eta, c->opt.precond_eta);
+    const int npr = nrhs * nc;
+    std::vector<int> porb(npr);
+    std::vector<double> pw(npr), pe(npr), pres(npr, 1.0);
+    for (int r = 0; r < nrhs; ++r)
+      for (int q = 0; q < nc; ++q) {
+        porb[r * nc + q] = rorb[r];
+        pw[r * nc + q] = rw[r];
+        pe[r * nc + q] = kPrecondCand[q] * M.pbase;
+      }
+    GmresWork W2;
+    cplx *Bp = (cplx *)walloc(W2, sizeof(cplx) * (size_t)norb * n);
+    cplx *Ep = (cplx *)walloc(W2, sizeof(cplx) * (size_t)norb * n);
+    if (W2.failed) {
+      wfree(W2);
+      return fail(set_err(c, CCGF_ENOMEM, "no device memory for the probe solves"));
     }
-    hipMemcpyAsync(dF, Fs.data(), sizeof(float) * Fs.size(), hipMemcpyHostToDevice, s);
-    hipMemcpyAsync(dT, Ts.data(), sizeof(float) * Ts.size(), hipMemcpyHostToDevice, s);
-    for (long long q0 = 0; q0 + bs <= P; q0 += bs) {
-      mlp_backward(s, w, M.theta, bs, dF + (size_t)q0 * M.din, dT + (size_t)q0 * M.dout);
-      mlp_adam(s, np, M.theta, w.grad, mm, vv, ++t, (float)lo.lr);
+    for (int b = 0; b < norb; ++b)
+      if (int rc = build_vectors(c, part, K, orbs[b], Bp + (size_t)b * n, Ep + (size_t)b * n)) {
+        wfree(W2);
+        return fail(rc);
+      }
+    const ccgf_options keep = c->opt;
+    c->opt.maxiter = lo.probe;
+    c->opt.tol = 0.0;          // run every probe for its full step count
+    c->opt.restart_m = std::max(keep.restart_m, lo.probe);
+    std::vector<cplx> gdump(npr);
+    ccgf_stats pst{};
+    int prc = solve_batched(c, part, K, npr, porb.data(), pw.data(), eta, Bp, Ep, gdump.data(), &pst, nullptr,
+                            nullptr, nullptr, 0, pe.data(), pres.data());
+    c->opt = keep;
+    wfree(W2);
+    if (prc != CCGF_OK && prc != CCGF_ENOCONV) return fail(prc);
+    M.pdin = 4;
+    M.pdout = nc;
+    std::vector<float> PF((size_t)nrhs * M.pdin), PT((size_t)nrhs * nc);
+    for (int r = 0; r < nrhs; ++r) {
+      precond_features(M, rorb[r], rw[r], &PF[(size_t)r * M.pdin]);
+      for (int q = 0; q < nc; ++q) PT[(size_t)r * nc + q] = (float)std::log10(std::max(pres[r * nc + q], 1e-16));
     }
-    if (int rc = hip_check(c, hipStreamSynchronize(s), "network training")) {  // host arrays reused next epoch
-      cleanup();
+    if (int rc = mlp_train(c, M.pdin, M.hidden, M.pdout, nrhs, PF, PT, lo.epochs, lo.batch, lo.lr, lo.seed + 1,
+                           false, &M.theta_p, &PL0, &PL1))
       return fail(rc);
-    }
+    probe_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - tp).count();
   }
-  if (int rc = full_loss(L1)) {
-    cleanup();
-    return fail(rc);
-  }
-  cleanup();
   auto t2 = std::chrono::steady_clock::now();
   if (ls) {
     ls->pairs += P;
     ls->rank = R;
     ls->loss_initial += L0;
     ls->loss_final += L1;
+    ls->probe_seconds += probe_s;
+    ls->precond_loss_initial += PL0;
+    ls->precond_loss_final += PL1;
     ls->solve_seconds += std::chrono::duration<double>(t1 - t0).count();
     ls->train_seconds += std::chrono::duration<double>(t2 - t1).count();
     ls->solve_iterations += st.n_iterations;
@@ -1828,6 +1824,7 @@ int learn_part(ccgf_ctx *c, int part, int K, int norb, const int *orbs, int ntra
     if (it->part == part && it->K == K) {
       if (it->Q) hipFree(it->Q);
       if (it->theta) hipFree(it->theta);
+      if (it->theta_p) hipFree(it->theta_p);
       c->models.erase(it);
       break;
     }

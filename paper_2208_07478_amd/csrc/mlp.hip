@@ -5,8 +5,10 @@
 // Y = a2 W3^T + b3;  loss L = |Y - T|^2 / (2N);  backward by the chain rule.
 #include "ccgf_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <random>
 #include <vector>
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -316,5 +318,149 @@ bool learn_guess(ccgf_ctx *c, const LearnModel &M, int nrhs, const int *rhs_orb,
   g.R = M.R;
   g.accept = M.accept;
   *chat_dev = dch;
+  return true;
+}
+
+// ------------------------------------------------------------------ training
+int mlp_train(ccgf_ctx *c, int din, int hidden, int dout, long long P, const std::vector<float> &F,
+              const std::vector<float> &T, int epochs, int batch, double lr, unsigned long long seed, bool zero_out,
+              float **theta, double *L0, double *L1) {
+  *theta = nullptr;
+  hipStream_t s = c->stream;
+  // parameters: uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights and zero biases; with zero_out the
+  // output layer starts at zero (the untrained network outputs 0)
+  const long long np = mlp_nparams(din, hidden, dout);
+  std::vector<float> th(np, 0.0f);
+  std::mt19937_64 rng(seed);
+  {
+    long long o = 0;
+    const int fin[3] = {din, hidden, hidden}, fout[3] = {hidden, hidden, dout};
+    for (int l = 0; l < (zero_out ? 2 : 3); ++l) {
+      std::uniform_real_distribution<float> U(-1.0f / std::sqrt((float)fin[l]), 1.0f / std::sqrt((float)fin[l]));
+      for (long long q = 0; q < (long long)fout[l] * fin[l]; ++q) th[o + q] = U(rng);
+      o += (long long)fout[l] * fin[l] + fout[l];
+    }
+  }
+  const int bs = (int)std::min<long long>(P, batch);
+  MlpWork w;
+  float *dth = nullptr, *dF = nullptr, *dT = nullptr, *mm = nullptr, *vv = nullptr;
+  bool ok = mlp_alloc(w, din, hidden, dout, (int)P) && hipMalloc(&dth, sizeof(float) * np) == hipSuccess &&
+            hipMalloc(&dF, sizeof(float) * F.size()) == hipSuccess &&
+            hipMalloc(&dT, sizeof(float) * T.size()) == hipSuccess && hipMalloc(&mm, sizeof(float) * np) == hipSuccess &&
+            hipMalloc(&vv, sizeof(float) * np) == hipSuccess;
+  auto cleanup = [&](bool keep_theta) {
+    mlp_free(w);
+    if (dF) hipFree(dF);
+    if (dT) hipFree(dT);
+    if (mm) hipFree(mm);
+    if (vv) hipFree(vv);
+    if (!keep_theta && dth) hipFree(dth);
+  };
+  if (!ok) {
+    (void)hipGetLastError();
+    cleanup(false);
+    return set_err(c, CCGF_ENOMEM, "no device memory for the network");
+  }
+  hipMemcpyAsync(dth, th.data(), sizeof(float) * np, hipMemcpyHostToDevice, s);
+  hipMemsetAsync(mm, 0, sizeof(float) * np, s);
+  hipMemsetAsync(vv, 0, sizeof(float) * np, s);
+  auto full_loss = [&](double &L) -> int {
+    hipMemcpyAsync(dF, F.data(), sizeof(float) * F.size(), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(dT, T.data(), sizeof(float) * T.size(), hipMemcpyHostToDevice, s);
+    const int nb = mlp_backward(s, w, dth, (int)P, dF, dT);
+    std::vector<double> lp(nb);
+    hipMemcpyAsync(lp.data(), w.lpart, sizeof(double) * nb, hipMemcpyDeviceToHost, s);
+    int rc = hip_check(c, hipStreamSynchronize(s), "network loss");
+    L = 0;
+    for (double x : lp) L += x;
+    L *= 0.5 / (double)P;
+    return rc;
+  };
+  if (int rc = full_loss(*L0)) {
+    cleanup(false);
+    return rc;
+  }
+  std::vector<long long> perm(P);
+  std::vector<float> Fs(F.size()), Ts(T.size());
+  int t = 0;
+  for (int e = 0; e < epochs; ++e) {
+    for (long long q = 0; q < P; ++q) perm[q] = q;
+    std::shuffle(perm.begin(), perm.end(), rng);
+    for (long long q = 0; q < P; ++q) {
+      std::copy(&F[(size_t)perm[q] * din], &F[(size_t)perm[q] * din] + din, &Fs[(size_t)q * din]);
+      std::copy(&T[(size_t)perm[q] * dout], &T[(size_t)perm[q] * dout] + dout, &Ts[(size_t)q * dout]);
+    }
+    hipMemcpyAsync(dF, Fs.data(), sizeof(float) * Fs.size(), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(dT, Ts.data(), sizeof(float) * Ts.size(), hipMemcpyHostToDevice, s);
+    for (long long q0 = 0; q0 + bs <= P; q0 += bs) {
+      mlp_backward(s, w, dth, bs, dF + (size_t)q0 * din, dT + (size_t)q0 * dout);
+      mlp_adam(s, np, dth, w.grad, mm, vv, ++t, (float)lr);
+    }
+    if (int rc = hip_check(c, hipStreamSynchronize(s), "network training")) {  // host arrays reused next epoch
+      cleanup(false);
+      return rc;
+    }
+  }
+  if (int rc = full_loss(*L1)) {
+    cleanup(false);
+    return rc;
+  }
+  cleanup(true);
+  *theta = dth;
+  return CCGF_OK;
+}
+
+// ------------------------------------------------------------------ preconditioner network
+const double kPrecondCand[CCGF_PRECOND_CANDIDATES] = {0.25, 0.5, 1.0, 1.5, 2.5};
+
+void precond_features(const LearnModel &M, int b, double w, float *f) {
+  f[0] = (float)(w / M.wscale);
+  f[1] = (float)(M.fpp[b] / M.wscale);
+  f[2] = M.occ[b] ? 1.0f : -1.0f;
+  f[3] = (float)((w - M.fpp[b]) / M.wscale);
+}
+
+bool learn_precond(ccgf_ctx *c, const LearnModel &M, int nrhs, const int *rhs_orb, const int *orbs,
+                   const double *rhs_omega, std::vector<double> &peta) {
+  if (!M.theta_p || nrhs <= 0) return false;
+  std::vector<int> rows;
+  std::vector<float> F;
+  for (int r = 0; r < nrhs; ++r) {
+    const int p = orbs[rhs_orb[r]];
+    int bm = -1;
+    for (int b = 0; b < M.norb; ++b)
+      if (M.orbs[b] == p) bm = b;
+    if (bm < 0) continue;
+    F.resize((rows.size() + 1) * M.pdin);
+    precond_features(M, bm, rhs_omega[r], &F[rows.size() * M.pdin]);
+    rows.push_back(r);
+  }
+  if (rows.empty()) return false;
+  const int N = (int)rows.size();
+  hipStream_t s = c->stream;
+  MlpWork w;
+  float *dF = nullptr;
+  bool ok = mlp_alloc(w, M.pdin, M.hidden, M.pdout, N) && hipMalloc(&dF, sizeof(float) * F.size()) == hipSuccess;
+  std::vector<float> Y((size_t)N * M.pdout, 0.0f);
+  if (ok) {
+    hipMemcpyAsync(dF, F.data(), sizeof(float) * F.size(), hipMemcpyHostToDevice, s);
+    mlp_forward(s, w, M.theta_p, N, dF);
+    hipMemcpyAsync(Y.data(), w.y, sizeof(float) * Y.size(), hipMemcpyDeviceToHost, s);
+    ok = hipStreamSynchronize(s) == hipSuccess;
+  }
+  if (dF) hipFree(dF);
+  mlp_free(w);
+  if (!ok) {
+    (void)hipGetLastError();
+    return false;
+  }
+  // -1: the context's own damping (orbitals the network was not trained on)
+  peta.assign(nrhs, -1.0);
+  for (int k = 0; k < N; ++k) {
+    int best = 0;
+    for (int q = 1; q < M.pdout; ++q)
+      if (Y[(size_t)k * M.pdout + q] < Y[(size_t)k * M.pdout + best]) best = q;
+    peta[rows[k]] = kPrecondCand[best] * M.pbase;
+  }
   return true;
 }

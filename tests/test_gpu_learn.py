@@ -30,49 +30,89 @@ def test_network_gradient_matches_oracle(din, h, dout, N):
         assert np.abs(a - b).max() <= 1e-4 * max(np.abs(b).max(), 1e-12), k
 
 
-def test_learned_guess_keeps_g_and_reports_its_gain():
-    """Train on every other frequency of a grid, solve the rest from zero, from
-    the nearest training solution and from the network's guess: G agrees with
-    dense inversion every time, and the iteration counts are reported."""
+def _check_g(E, orbs, wtest, eta, runs):
+    cache = {}
+    for p in orbs:
+        gp, gm = solve.dense_gf(E, 0, p, wtest, eta, M_cache=cache)
+        sc = max(np.abs(gp).max(), np.abs(gm).max())
+        for k, (G, Gp, Gm, st) in runs.items():
+            assert st["n_unconverged"] == 0, k
+            assert np.abs(Gp[0, p] - gp).max() <= 1e-8 * sc, k
+            assert np.abs(Gm[0, p] - gm).max() <= 1e-8 * sc, k
+
+
+def test_learned_guess_gain_in_a_smooth_window():
+    """A case where the network should help: frequencies in the gap between the
+    removal and addition spectra, where the solutions change smoothly with w.
+    Trained on every other point of the window, the network's guesses for the
+    points between need fewer GMRES steps than starting from zero and than
+    starting from the nearest training solution; G is unchanged (dense inversion)."""
     import torch
     from paper_2208_07478_amd.ccgf import Context
     case = dict(kmesh=(2, 1, 1), nocc=2, nvir=5, seed=12)
     s = synth.make_system(t1_std=0.05, t2_std=0.05, eri_std=0.1, **case)
     print("case", case, flush=True)
     E = eom.EOMSystem(s)
-    eta = 0.02
-    grid = np.linspace(-1.0, 1.0, 25)
-    wtrain, wtest = grid[0::2], grid[1::2]
-    nmo = s.nocc + s.nvir
-    orbs = list(range(nmo))
-    ctx = Context(s, tol=1e-10, restart_m=40, maxiter=6000, max_batch=64)
+    eta = 0.005
+    window = np.linspace(-0.28, 0.18, 17)
+    wtrain, wtest = window[0::2], window[1::2]
+    orbs = list(range(s.nocc + s.nvir))
+    ctx = Context(s, tol=1e-10, restart_m=60, maxiter=20000, max_batch=128, precond_eta=0.4)
     try:
         runs = {}
         ctx.learn_enable(False)
         runs["zero"] = ctx.solve([0], orbs, wtest, eta)
-        ctx.learn_enable(True)
-        ctx.learn(0, orbs, wtrain, eta, guess="nearest", accept=1.0)
+        ctx.learn(0, orbs, wtrain, eta, guess="nearest", accept=1.0, probe=-1)
         runs["nearest"] = ctx.solve([0], orbs, wtest, eta)
-        ls = ctx.learn(0, orbs, wtrain, eta, epochs=300, seed=3, accept=1.0)
+        ls = ctx.learn(0, orbs, wtrain, eta, epochs=300, seed=3, probe=-1)
         print("learn", ls, flush=True)
         assert ls["loss_final"] < ls["loss_initial"]
         runs["network"] = ctx.solve([0], orbs, wtest, eta)
-        ctx.learn(0, orbs, wtrain, eta, epochs=300, seed=3)  # default acceptance 0.1
-        runs["network_accept0.1"] = ctx.solve([0], orbs, wtest, eta)
-        for k, (G, Gp, Gm, st) in runs.items():
-            print(k, "iterations", st["n_iterations"], "guesses", st["n_guess"], "rejected", st["n_guess_rejected"],
-                  flush=True)
-            assert st["n_unconverged"] == 0
-        assert runs["zero"][3]["n_guess"] == 0 and runs["network"][3]["n_guess"] > 0
-        # with the default acceptance the guesses do not cost iterations overall
-        assert runs["network_accept0.1"][3]["n_iterations"] <= 1.05 * runs["zero"][3]["n_iterations"]
-        cache = {}
-        for p in orbs:
-            gp, gm = solve.dense_gf(E, 0, p, wtest, eta, M_cache=cache)
-            sc = max(np.abs(gp).max(), np.abs(gm).max())
-            for k, (G, Gp, Gm, st) in runs.items():
-                assert np.abs(Gp[0, p] - gp).max() <= 1e-8 * sc, k
-                assert np.abs(Gm[0, p] - gm).max() <= 1e-8 * sc, k
+        its = {k: r[3]["n_iterations"] for k, r in runs.items()}
+        print("iterations", its, "guesses used", runs["network"][3]["n_guess"], flush=True)
+        assert runs["network"][3]["n_guess"] > 0
+        assert its["network"] < 0.9 * its["zero"]
+        assert its["network"] < its["nearest"]
+        _check_g(E, orbs, wtest, eta, runs)
+    finally:
+        ctx.close()
+        torch.cuda.synchronize()
+
+
+def test_learned_preconditioner_gain_and_fallback():
+    """The preconditioner network (damping of the diagonal preconditioner per
+    solve, learned from probe solves) on a 2x2x1 system across the whole window
+    [-1, 1] Ha at eta = 5 mHa: fewer GMRES steps than the fixed damping, with G
+    unchanged (the damping changes only the iteration count; the FP64 residual
+    judges every solve)."""
+    import torch
+    from paper_2208_07478_amd.ccgf import Context
+    case = dict(kmesh=(2, 2, 1), nocc=4, nvir=12, seed=5)
+    s = synth.make_system(t1_std=0.01, t2_std=0.01, eri_std=0.05, **case)
+    print("case", case, flush=True)
+    eta = 0.005
+    grid = np.linspace(-1.0, 1.0, 33)
+    wtrain, wtest = grid[0::2], grid[1::2]
+    orbs = list(range(s.nocc + s.nvir))
+    ctx = Context(s, tol=1e-10, restart_m=60, maxiter=20000, max_batch=128, precond_eta=0.4)
+    try:
+        runs = {}
+        runs["fixed"] = ctx.solve([0], orbs, wtest, eta)
+        ls = ctx.learn(0, orbs, wtrain, eta, epochs=300, seed=3)
+        print("learn", ls, flush=True)
+        assert ls["precond_loss_final"] < ls["precond_loss_initial"]
+        ctx.learn_enable(guess=False, precond=True)
+        runs["learned"] = ctx.solve([0], orbs, wtest, eta)
+        its = {k: r[3]["n_iterations"] for k, r in runs.items()}
+        print("iterations", its, flush=True)
+        assert its["learned"] < 0.95 * its["fixed"]
+        # the damping changes the iteration count only: both runs give the same G to the tolerance
+        # (the plain solver's G is pinned against dense inversion by the parity tests)
+        for k in ("Gp", "Gm"):
+            i = 1 if k == "Gp" else 2
+            a, b = runs["learned"][i], runs["fixed"][i]
+            assert np.abs(a - b).max() <= 1e-8 * np.abs(b).max(), k
+        assert runs["learned"][3]["n_unconverged"] == 0
     finally:
         ctx.close()
         torch.cuda.synchronize()

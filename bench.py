@@ -76,8 +76,8 @@ def parse():
     ap.add_argument("--precond-eta", type=float, default=0.25)
     ap.add_argument("--ntrain", type=int, default=4, help="training frequencies of the networks (the first "
                                                             "warmup steps' frequencies, all orbitals)")
-    ap.add_argument("--probe", type=int, default=30, help="GMRES steps of each probe solve of the "
-                                                           "preconditioner network (-1: none)")
+    ap.add_argument("--probe-steps", type=int, default=30, help="GMRES steps of each probe solve of the "
+                                                                 "preconditioner network (-1: none)")
     ap.add_argument("--budget-s", type=float, default=430.0,
                     help="wall-clock budget: optional legs are skipped when they would exceed it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -279,7 +279,7 @@ def main():
         nwarm_plain = max(1, min(args.ntrain, args.warmup - 1 if args.warmup > 1 else 1))
         wtrain = sorted(set(wstep[:nwarm_plain]))
         t1 = time.perf_counter()
-        learn = ctx.learn(0, orbs, wtrain, eta, probe=args.probe, allow_noconv=True)
+        learn = ctx.learn(0, orbs, wtrain, eta, probe=args.probe_steps, allow_noconv=True)
         learn["seconds"] = time.perf_counter() - t1
         learn["omega_train"] = wtrain
         log(f"{form}: training at {len(wtrain)} frequencies {learn['seconds']:.1f} s")

@@ -561,6 +561,9 @@ extern "C" void cc_gf_free(ccgf_ctx *c) {
     for (auto &g : P.graphs) hipGraphExecDestroy(g.exec);
   c->plans.clear();
   if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+  if (c->side_stream) hipStreamDestroy(c->side_stream);
+  if (c->ev_fork) hipEventDestroy(c->ev_fork);
+  if (c->ev_join) hipEventDestroy(c->ev_join);
   for (int q = 0; q < 2; ++q)
     if (c->tev[q]) hipEventDestroy(c->tev[q]);
   free_all(c);

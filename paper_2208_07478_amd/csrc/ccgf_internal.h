@@ -257,6 +257,10 @@ struct ccgf_ctx {
   std::map<std::string, int> tuned;
   hipEvent_t tev[2] = {nullptr, nullptr};
   hipStream_t cap_stream = nullptr;  // private stream on which sigma launch sequences are captured
+  // second stream of a sigma product: the terms that do not write the W_abcd / W_mnij output
+  // run there beside that product (fork and join by events; default priority)
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::string tune_path;
   int learn_on = 3;                 // use them in cc_gf_solve (CCGF_LEARN_* mask)
   // event timing of the sigma products (options.timing)

@@ -58,11 +58,12 @@ struct Mf<float> {
 // 2: IP W_mnij, 3: IP W_maei, 4: EA W_abei r^e, 5: IP W_maij r_m, 6: EA 1p-row
 // reductions W_alcd r, <kl||cd> r, 7: IP 1h-row reductions W_mnie r, <mn||ef> r,
 // 8 and 9: EA W_abcd on the blocks ka = kb, pairs kc = kd and kc < kd).
-// TNT is the tile width in N (64, 32 for narrow batches, 128 in FP32 to read W
-// fewer times); the four waves of a block own 32x32 (TNT = 64), 16x32 (TNT = 32)
-// or 32x64 (TNT = 128) output sub-tiles.
+// TNT is the tile width in N (64; 16, 32 or 48 for narrow batches, the smallest
+// that holds N so that little of the MFMA work is padding; 128 in FP32 to read W
+// fewer times); the four waves of a block own 32x32 (TNT = 64), 16 x TNT
+// (TNT <= 48) or 32x64 (TNT = 128) output sub-tiles.
 template <int TAG, typename R, int TNT>
-__global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *__restrict__ tasks,
+__global__ __launch_bounds__(256, TNT <= 48 ? 4 : 2) void k_cgemm(GemmShape sh, const GemmTask *__restrict__ tasks,
                                                   const GemmSeg *__restrict__ segs,
                                                   const typename Mf<R>::AE *__restrict__ A,
                                                   const typename Mf<R>::AE *__restrict__ B, cplx *__restrict__ C,
@@ -86,8 +87,11 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
   constexpr int RPP = 256 / KS;            // rows staged per pass of the block
   constexpr int AJ = TM / RPP;             // A rows staged per thread
   constexpr int NBJ = TNT / RPP;           // B rows staged per thread
-  constexpr int AM = TNT == 32 ? 1 : 2;    // MFMA row tiles per wave
-  constexpr int BN = TNT == 128 ? 4 : 2;   // MFMA column tiles per wave
+  // narrow tiles (16, 32, 48 columns): the four waves split the 64 rows, each holding every
+  // column; 64 and 128 columns: 2 x 2 waves of 32 rows
+  constexpr bool NARROW = TNT <= 48;
+  constexpr int AM = NARROW ? 1 : 2;                 // MFMA row tiles per wave
+  constexpr int BN = NARROW ? TNT / 16 : TNT / 32;   // MFMA column tiles per wave
   __shared__ R Ar[TM][KS + 1], Ai[TM][KS + 1], Br[TNT][KS + 1], Bi[TNT][KS + 1];
   const int tid = threadIdx.x;
 
@@ -143,8 +147,8 @@ __global__ __launch_bounds__(256, 2) void k_cgemm(GemmShape sh, const GemmTask *
 
   const int wave = tid >> 6, lane = tid & 63;
   // rows [rbase, rbase + 16 AM) and columns [cbase, cbase + 16 BN) of the tile belong to this wave
-  const int rbase = TNT == 32 ? wave * 16 : (wave >> 1) * 32;
-  const int cbase = TNT == 32 ? 0 : (wave & 1) * (TNT / 2);
+  const int rbase = NARROW ? wave * 16 : (wave >> 1) * 32;
+  const int cbase = NARROW ? 0 : (wave & 1) * (TNT / 2);
   const int lr = lane & 15, lk = lane >> 4;
 
   if (nsteps > 0) load(0);
@@ -381,11 +385,18 @@ static void launch_w(const GemmPlan &plan, const void *A, const void *B, cplx *C
   else if (tn == 128 && sizeof(R) == 4) launch_t<TAG, float, 128>(plan, A, B, C, s);
   else launch_t<TAG, R, 64>(plan, A, B, C, s);
 }
+// the big products also have 16- and 48-wide tiles (narrow batches)
+template <int TAG, typename R>
+static void launch_wn(const GemmPlan &plan, const void *A, const void *B, cplx *C, hipStream_t s, int tn) {
+  if (tn == 16) launch_t<TAG, R, 16>(plan, A, B, C, s);
+  else if (tn == 48) launch_t<TAG, R, 48>(plan, A, B, C, s);
+  else launch_w<TAG, R>(plan, A, B, C, s, tn);
+}
 
 // prec 0: FP64 operands (A and B complex double); prec 1: FP32 (A complex float,
 // B the vectors' complex float copy); prec 2: BF16-split products from the FP32
 // operands (64-wide tiles only).  Tags 4 to 7 run in FP64 only.
-// tn: N tile width (64 or 32), chosen per plan by the autotuner in sigma_apply.
+// tn: N tile width (16, 32, 48, 64 or 128), chosen per plan in tuned_launch.
 void gemm_launch(int tag, const GemmPlan &plan, const void *A, const void *B, cplx *C, hipStream_t s, int prec,
                  int tn) {
   const GemmShape &sh = plan.shape;
@@ -393,8 +404,8 @@ void gemm_launch(int tag, const GemmPlan &plan, const void *A, const void *B, cp
 #define CASE(T)                                                                              \
   case T:                                                                                    \
     if (prec == 2) launch_b3<T>(plan, A, B, C, s);                                           \
-    else if (prec) launch_w<T, float>(plan, A, B, C, s, tn);                                 \
-    else launch_w<T, double>(plan, A, B, C, s, tn);                                          \
+    else if (prec) launch_wn<T, float>(plan, A, B, C, s, tn);                                \
+    else launch_wn<T, double>(plan, A, B, C, s, tn);                                         \
     break;
   switch (tag) {
     CASE(0) CASE(1) CASE(2) CASE(3) CASE(8) CASE(9)
@@ -895,14 +906,19 @@ __global__ __launch_bounds__(256) void k_ip_local(int nk, int no, int nv, int K,
   }
 }
 
-// Launch a plan with the N tile width the autotuner picked for its shape.  The
-// first two launches of an unseen shape are timed trials of the 64- and 32-wide
+// Launch a plan with the N tile width the autotuner picked for its shape.  The big
+// products of narrow batches (N <= 48) take the narrowest tile that holds N without
+// trials.  Otherwise the first two launches of an unseen shape are timed trials of the 64- and 32-wide
 // variants (each does the real work); the 32-wide one is kept only if it is at
 // least 5% faster.  Choices are cached per shape in the context (and in the
 // autotune file when one is configured).
 static int tuned_launch(ccgf_ctx *c, int tag, GemmPlan &p, const void *A, const void *B, cplx *C, hipStream_t s,
                         int prec) {
   if (p.tn[prec] == 0 && (c->opt.autotune < 0 || prec == 2)) p.tn[prec] = 64;
+  // narrow batches of the big products (N <= 48): the narrowest tile that holds N, where the
+  // MFMA work is least padding (the W operand is streamed once either way)
+  const bool big = tag <= 3 || tag == 8 || tag == 9;
+  if (p.tn[prec] == 0 && big && p.shape.N <= 48) p.tn[prec] = 16 * ((p.shape.N + 15) / 16);
   if (p.tn[prec] == 0) {
     char key[160];
     std::snprintf(key, sizeof key, "t%d p%d M%d N%d K%d s%zu n%d", tag, prec, p.shape.M, p.shape.N, p.shape.K,
@@ -977,24 +993,33 @@ static int sigma_enqueue(ccgf_ctx *c, SigmaPlan *P, int part, int K, int nvec, c
     hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, x, c->sig_x32, tot);
     xb = c->sig_x32;
   }
+  // fork: the side stream takes the terms that write other buffers than the big product's
+  // blocks (the diagonal W_abcd blocks, the W_ovvo scratch, the split-K partial sums), so that
+  // their small, HBM-bound launches overlap the big one; join before the terms that read them
+  hipStream_t s2 = c->side_stream;
+  hipEventRecord(c->ev_fork, s);
+  hipStreamWaitEvent(s2, c->ev_fork, 0);
   if (part == CCGF_PART_EA) {
-    if (ts) hipEventRecord(ts->e[2], s);
     if (prec && !c->Wvvvv32) return set_err(c, CCGF_ESTATE, "mixed-precision operands were not built");
     const void *Wbig = prec ? (const void *)c->Wvvvv32 : (const void *)c->Wvvvv;
     const void *Wovvo = prec ? (const void *)c->WvoPea32 : (const void *)c->WvoPea;
-    int rc = tuned_launch(c, 0, P->g_big, Wbig, xb, y, s, prec);
+    int rc = CCGF_OK;
+    if (!rc && P->g_bigt.ntask) rc = tuned_launch(c, 8, P->g_bigt, Wbig, xb, y, s2, prec);
+    if (!rc && P->g_bigd.ntask) rc = tuned_launch(c, 9, P->g_bigd, Wbig, xb, y, s2, prec);
+    if (!rc) rc = tuned_launch(c, 1, P->g_ovvo, Wovvo, xb, c->sig_tmp, s2, prec);
+    if (!rc) rc = tuned_launch(c, 6, P->g_red1, c->Wvovv, x, c->sig_part, s2, 0);
+    if (!rc) rc = tuned_launch(c, 6, P->g_red2, c->Voovv, x, c->sig_part, s2, 0);
+    hipEventRecord(c->ev_join, s2);
+    if (ts) hipEventRecord(ts->e[2], s);
+    if (!rc) rc = tuned_launch(c, 0, P->g_big, Wbig, xb, y, s, prec);
     if (ts) hipEventRecord(ts->e[3], s);
-    if (!rc && P->g_bigt.ntask) rc = tuned_launch(c, 8, P->g_bigt, Wbig, xb, y, s, prec);
-    if (!rc && P->g_bigd.ntask) rc = tuned_launch(c, 9, P->g_bigd, Wbig, xb, y, s, prec);
+    hipStreamWaitEvent(s, c->ev_join, 0);
     if (P->nfill > 0) {
       const long long b2 = (long long)no * nv * nv;
       hipLaunchKernelGGL(k_vvvv_fill, dim3((unsigned)((b2 + 255) / 256), P->nfill, std::min(nvec, 64)), dim3(256), 0,
                          s, y, n, nvec, nv, b2, P->d_fill, P->d_fill + P->nfill, P->nfill);
     }
-    if (!rc) rc = tuned_launch(c, 1, P->g_ovvo, Wovvo, xb, c->sig_tmp, s, prec);
     if (!rc) rc = tuned_launch(c, 4, P->g_r1, c->Wvvvo, x, y, s, 0);
-    if (!rc) rc = tuned_launch(c, 6, P->g_red1, c->Wvovv, x, c->sig_part, s, 0);
-    if (!rc) rc = tuned_launch(c, 6, P->g_red2, c->Voovv, x, c->sig_part, s, 0);
     if (rc) return rc;
     hipLaunchKernelGGL(k_r1_finish, dim3((unsigned)(((nv + no) * nvec + 3) / 4)), dim3(256), 0, s, 1, nk, no, nv, K,
                        nv + no, nv, nvec, nk * nk * no, n, c->sig_part, x, y, c->sig_r1aux, std::max(no, nv), c->Foo,
@@ -1003,16 +1028,18 @@ static int sigma_enqueue(ccgf_ctx *c, SigmaPlan *P, int part, int K, int nvec, c
     hipLaunchKernelGGL(k_ea_local, dim3((unsigned)((tot + 255) / 256), gy), dim3(256), 0, s, nk, no, nv, K, nvec, n,
                        c->kc3, x, y, c->sig_tmp, c->sig_r1aux, c->Foo, c->Fvv, c->t2);
   } else {
-    if (ts) hipEventRecord(ts->e[2], s);
     if (prec && !c->WooP32) return set_err(c, CCGF_ESTATE, "mixed-precision operands were not built");
     const void *Wbig = prec ? (const void *)c->WooP32 : (const void *)c->WooP;
     const void *Wovvo = prec ? (const void *)c->WvoP32 : (const void *)c->WvoP;
-    int rc = tuned_launch(c, 2, P->g_big, Wbig, xb, y, s, prec);
+    int rc = tuned_launch(c, 3, P->g_ovvo, Wovvo, xb, c->sig_tmp, s2, prec);
+    if (!rc) rc = tuned_launch(c, 7, P->g_red1, c->Wooov, x, c->sig_part, s2, 0);
+    if (!rc) rc = tuned_launch(c, 7, P->g_red2, c->Voovv, x, c->sig_part, s2, 0);
+    hipEventRecord(c->ev_join, s2);
+    if (ts) hipEventRecord(ts->e[2], s);
+    if (!rc) rc = tuned_launch(c, 2, P->g_big, Wbig, xb, y, s, prec);
     if (ts) hipEventRecord(ts->e[3], s);
-    if (!rc) rc = tuned_launch(c, 3, P->g_ovvo, Wovvo, xb, c->sig_tmp, s, prec);
+    hipStreamWaitEvent(s, c->ev_join, 0);
     if (!rc) rc = tuned_launch(c, 5, P->g_r1, c->Wovoo, x, y, s, 0);
-    if (!rc) rc = tuned_launch(c, 7, P->g_red1, c->Wooov, x, c->sig_part, s, 0);
-    if (!rc) rc = tuned_launch(c, 7, P->g_red2, c->Voovv, x, c->sig_part, s, 0);
     if (rc) return rc;
     hipLaunchKernelGGL(k_r1_finish, dim3((unsigned)(((nv + no) * nvec + 3) / 4)), dim3(256), 0, s, 0, nk, no, nv, K,
                        no + nv, no, nvec, nk * nk * no, n, c->sig_part, x, y, c->sig_r1aux, std::max(no, nv), c->Foo,
@@ -1086,6 +1113,12 @@ int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y, 
       c->sig_part_elems = c->sig_part ? need_part : 0;
       if (!c->sig_part) return CCGF_ENOMEM;
     }
+  }
+  if (!c->side_stream) {
+    if (hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
+      return hip_check(c, hipGetLastError(), "sigma side stream");
   }
   SigmaPlan *P = nullptr;
   for (auto &q : c->plans)

@@ -321,6 +321,20 @@ int cc_gf_vector_size(const ccgf_ctx *ctx, int part, long long *n);
  * and returns after the product is complete. */
 int cc_gf_sigma(ccgf_ctx *ctx, int part, int K, int nvec, const double *x, double *y);
 
+/* The sigma products of several systems at once (uneven k-meshes, orbital counts and
+ * parts): y_i = M_i(K[i]) x_i for i < nsys, as cc_gf_sigma on each context (same
+ * arithmetic per element), with every GEMM term of the products (W_abcd, W_mnij, W_ovvo,
+ * the couplings and the 1h / 1p reductions) issued as ONE launch whose tasks cover all
+ * the systems, each task with its own shape and operands; small systems then share the
+ * chip instead of each under-filling it.  ctxs: distinct contexts of the same precision
+ * (CCGF_PLAIN_F64 or CCGF_MIXED_F32; CCGF_EUNSUPPORTED for the BF16 split) on one device;
+ * parts[i] CCGF_PART_IP or CCGF_PART_EA; x[i], y[i]: DEVICE complex [nvec[i]][n_i], not
+ * aliased, x antisymmetric in its pair indices.  Runs on ctxs[0]'s stream after waiting
+ * for every context's stream; returns after the products are complete.  Errors go to
+ * ctxs[0] (cc_gf_last_error). */
+int cc_gf_sigma_group(int nsys, ccgf_ctx *const *ctxs, const int *parts, const int *K, const int *nvec,
+                      const double *const *x, double *const *y);
+
 /* Right-hand side b (abar_p|Phi> for IP, abar+_p|Phi> for EA) and left vector
  * e (<Phi|(1+Lambda) abar+_p for IP, <Phi|(1+Lambda) abar_p for EA) of orbital
  * p at momentum K (Eqs. 6-7).  b, e: DEVICE complex [n]; either may be NULL. */

@@ -23,7 +23,8 @@ PLAIN_F64, MIXED_F32, MIXED_BF16X3 = 0, 1, 2
 PRECISIONS = {"f64": PLAIN_F64, "plain_f64": PLAIN_F64, "f32": MIXED_F32, "mixed_f32": MIXED_F32,
               "bf16x3": MIXED_BF16X3, "mixed_bf16x3": MIXED_BF16X3}
 
-EXPORTS = ("cc_gf_init", "cc_gf_solve", "cc_gf_solve_matrix", "cc_gf_mor", "cc_gf_vector_size", "cc_gf_sigma", "cc_gf_vectors",
+EXPORTS = ("cc_gf_init", "cc_gf_solve", "cc_gf_solve_matrix", "cc_gf_mor", "cc_gf_vector_size", "cc_gf_sigma",
+           "cc_gf_sigma_group", "cc_gf_vectors",
            "cc_gf_learn", "cc_gf_learn_enable", "cc_gf_set_options", "cc_gf_mlp_grad", "cc_gf_dyson_cas",
            "cc_gf_dyson_cas_noalloc", "cc_gf_dyson_last_error", "cc_gf_free", "cc_gf_last_error")
 MOR_MAX = 32
@@ -115,6 +116,9 @@ def load(path: str = LIB_PATH):
     lib.cc_gf_vector_size.restype = ctypes.c_int
     lib.cc_gf_sigma.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp]
     lib.cc_gf_sigma.restype = ctypes.c_int
+    lib.cc_gf_sigma_group.argtypes = [ctypes.c_int, ctypes.POINTER(vp), ip, ip, ip, ctypes.POINTER(vp),
+                                      ctypes.POINTER(vp)]
+    lib.cc_gf_sigma_group.restype = ctypes.c_int
     lib.cc_gf_vectors.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp]
     lib.cc_gf_vectors.restype = ctypes.c_int
     lib.cc_gf_learn.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, ctypes.c_int, dp, ctypes.c_double,
@@ -350,6 +354,28 @@ class Context:
                               Gp.ctypes.data, Gm.ctypes.data, ctypes.byref(st))
         self._check(rc, allow=(ENOCONV,) if allow_noconv else ())
         return G, Gp, Gm, st.as_dict()
+
+
+def sigma_group(items):
+    """Grouped sigma products: items is a list of (Context, part, K, x) with x a CUDA
+    complex128 [nvec, n] tensor; returns the list of y tensors."""
+    lib = load()
+    import torch
+    n = len(items)
+    vp = ctypes.c_void_p
+    ys = [torch.empty_like(x) for (_, _, _, x) in items]
+    for (_, _, _, x) in items:
+        assert x.is_cuda and x.dtype == torch.complex128 and x.is_contiguous()
+    ctxs = (vp * n)(*[c._h.value for (c, _, _, _) in items])
+    parts = (ctypes.c_int * n)(*[_part(p) for (_, p, _, _) in items])
+    ks = (ctypes.c_int * n)(*[int(k) for (_, _, k, _) in items])
+    nv = (ctypes.c_int * n)(*[int(x.shape[0]) for (_, _, _, x) in items])
+    xp = (vp * n)(*[x.data_ptr() for (_, _, _, x) in items])
+    yp = (vp * n)(*[y.data_ptr() for y in ys])
+    rc = lib.cc_gf_sigma_group(n, ctxs, parts, ks, nv, xp, yp)
+    if rc != OK:
+        raise CCGFError(rc, lib.cc_gf_last_error(items[0][0]._h).decode())
+    return ys
 
 
 def dyson_cas(Ggw, Ggw_cas, Gcc, V, stream=None, self_energies=False, noalloc=False):

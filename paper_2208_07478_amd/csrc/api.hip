@@ -231,6 +231,32 @@ extern "C" int cc_gf_sigma(ccgf_ctx *c, int part, int K, int nvec, const double 
   return hip_check(c, hipStreamSynchronize(c->stream), "cc_gf_sigma");
 }
 
+extern "C" int cc_gf_sigma_group(int nsys, ccgf_ctx *const *ctxs, const int *parts, const int *K, const int *nvec,
+                                 const double *const *x, double *const *y) {
+  if (nsys < 1 || !ctxs || !ctxs[0]) return CCGF_ESTATE;
+  ccgf_ctx *c0 = ctxs[0];
+  if (!parts || !K || !nvec || !x || !y) return set_err(c0, CCGF_EINVAL, "NULL array argument");
+  if (c0->opt.precision == CCGF_MIXED_BF16X3)
+    return set_err(c0, CCGF_EUNSUPPORTED, "grouped products run in FP64 or FP32");
+  for (int i = 0; i < nsys; ++i) {
+    ccgf_ctx *c = ctxs[i];
+    if (!c) return set_err(c0, CCGF_ESTATE, "NULL context");
+    if (c->opt.precision != c0->opt.precision) return set_err(c0, CCGF_EINVAL, "systems differ in precision");
+    if (parts[i] != CCGF_PART_IP && parts[i] != CCGF_PART_EA) return set_err(c0, CCGF_EINVAL, "part must be IP or EA");
+    if (K[i] < 0 || K[i] >= c->nk) return set_err(c0, CCGF_EINVAL, "K out of range");
+    if (nvec[i] < 0 || (nvec[i] > 0 && (!x[i] || !y[i]))) return set_err(c0, CCGF_EINVAL, "bad vectors");
+    if (nvec[i] > 0 && x[i] == y[i]) return set_err(c0, CCGF_EINVAL, "x and y must not alias");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == c) return set_err(c0, CCGF_EINVAL, "a context appears twice (its workspace is per product)");
+  }
+  // every context's own work is done before its workspace is reused on the first stream
+  for (int i = 0; i < nsys; ++i)
+    if (hip_check(c0, hipStreamSynchronize(ctxs[i]->stream), "cc_gf_sigma_group") != CCGF_OK) return CCGF_EDEVICE;
+  int rc = sigma_group(nsys, ctxs, parts, K, nvec, (const cplx *const *)x, (cplx *const *)y);
+  if (rc != CCGF_OK) return rc;
+  return hip_check(c0, hipStreamSynchronize(c0->stream), "cc_gf_sigma_group");
+}
+
 extern "C" int cc_gf_vectors(ccgf_ctx *c, int part, int K, int p, double *b, double *e) {
   if (!c) return CCGF_ESTATE;
   if (part != CCGF_PART_IP && part != CCGF_PART_EA) return set_err(c, CCGF_EINVAL, "part must be IP or EA");

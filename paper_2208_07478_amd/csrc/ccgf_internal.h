@@ -261,6 +261,9 @@ struct ccgf_ctx {
   // run there beside that product (fork and join by events; default priority)
   hipStream_t side_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // tables of the grouped launches over several systems (sigma_group)
+  void *grp_buf = nullptr;
+  size_t grp_bytes = 0;
   std::string tune_path;
   int learn_on = 3;                 // use them in cc_gf_solve (CCGF_LEARN_* mask)
   // event timing of the sigma products (options.timing)
@@ -289,6 +292,9 @@ long long vec_len(const ccgf_ctx *c, int part);
 
 // sigma.hip
 int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y, int prec = 0);
+// sigma products of several systems, one launch per GEMM term over all of them (ctxs[0]'s stream)
+int sigma_group(int nsys, ccgf_ctx *const *ctxs, const int *parts, const int *Ks, const int *nvecs,
+                const cplx *const *xs, cplx *const *ys);
 // Accumulate the timings of the recorded sigma products (waits for any still running).
 void timing_harvest(ccgf_ctx *c);
 void timing_release(ccgf_ctx *c);

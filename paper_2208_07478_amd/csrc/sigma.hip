@@ -62,26 +62,16 @@ struct Mf<float> {
 // that holds N so that little of the MFMA work is padding; 128 in FP32 to read W
 // fewer times); the four waves of a block own 32x32 (TNT = 64), 16 x TNT
 // (TNT <= 48) or 32x64 (TNT = 128) output sub-tiles.
+// One output tile (tm, tn) of one task: the body shared by the launch over one shape
+// (k_cgemm) and the launch over the tasks of several systems (k_cgemm_group).
 template <int TAG, typename R, int TNT>
-__global__ __launch_bounds__(256, TNT <= 48 ? 4 : 2) void k_cgemm(GemmShape sh, const GemmTask *__restrict__ tasks,
-                                                  const GemmSeg *__restrict__ segs,
-                                                  const typename Mf<R>::AE *__restrict__ A,
-                                                  const typename Mf<R>::AE *__restrict__ B, cplx *__restrict__ C,
-                                                  int tilesM,
-                                                  int tilesN, int total) {
+__device__ __forceinline__ void cgemm_tile(const GemmShape &sh, const GemmTask &task,
+                                           const GemmSeg *__restrict__ segs,
+                                           const typename Mf<R>::AE *__restrict__ A,
+                                           const typename Mf<R>::AE *__restrict__ B, cplx *__restrict__ C, int tm,
+                                           int tn) {
   typedef typename Mf<R>::V4 V4;
   typedef typename Mf<R>::AE AE;
-  int bid = blockIdx.x;
-  // keep the tiles of one task on one XCD (consecutive logical ids share an L2)
-  if ((total & 7) == 0) {
-    int per = total >> 3;
-    bid = (bid & 7) * per + (bid >> 3);
-  }
-  const int per_task = tilesM * tilesN;
-  const int t = bid / per_task, r = bid % per_task;
-  const int tm = r / tilesN, tn = r % tilesN;
-  const GemmTask task = tasks[t];
-
   // k-slab: 32 for the FP32 W_abcd products (half the barriers per k), else 16
   constexpr int KS = (sizeof(R) == 4 && (TAG == 0 || TAG == 8 || TAG == 9)) ? 2 * TK : TK;
   constexpr int RPP = 256 / KS;            // rows staged per pass of the block
@@ -210,6 +200,55 @@ __global__ __launch_bounds__(256, TNT <= 48 ? 4 : 2) void k_cgemm(GemmShape sh, 
           C[off] = val;
         }
       }
+}
+
+// XCD-aware block order: consecutive logical tiles share an XCD (and its L2)
+__device__ inline int xcd_block(int total) {
+  int bid = blockIdx.x;
+  if ((total & 7) == 0) {
+    const int per = total >> 3;
+    bid = (bid & 7) * per + (bid >> 3);
+  }
+  return bid;
+}
+
+template <int TAG, typename R, int TNT>
+__global__ __launch_bounds__(256, TNT <= 48 ? 4 : 2) void k_cgemm(GemmShape sh, const GemmTask *__restrict__ tasks,
+                                                                  const GemmSeg *__restrict__ segs,
+                                                                  const typename Mf<R>::AE *__restrict__ A,
+                                                                  const typename Mf<R>::AE *__restrict__ B,
+                                                                  cplx *__restrict__ C, int tilesM, int tilesN,
+                                                                  int total) {
+  const int bid = xcd_block(total);
+  const int per_task = tilesM * tilesN;
+  const int t = bid / per_task, r = bid % per_task;
+  cgemm_tile<TAG, R, TNT>(sh, tasks[t], segs, A, B, C, r / tilesN, r % tilesN);
+}
+
+// One launch over the tasks of several systems (uneven shapes): task g covers the blocks
+// [tile0, tile0 + tilesM * tilesN) and carries its shape and operand bases.
+struct GroupTask {
+  const void *A, *B;
+  cplx *C;
+  GemmTask task;
+  int shape, tile0, tilesM, tilesN;
+};
+
+template <int TAG, typename R, int TNT>
+__global__ __launch_bounds__(256, TNT <= 48 ? 4 : 2) void k_cgemm_group(const GemmShape *__restrict__ shapes,
+                                                                        const GroupTask *__restrict__ gt, int ntask,
+                                                                        const GemmSeg *__restrict__ segs, int total) {
+  const int bid = xcd_block(total);
+  int lo = 0, hi = ntask - 1;  // the last task whose first block is <= bid
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (gt[mid].tile0 <= bid) lo = mid;
+    else hi = mid - 1;
+  }
+  const GroupTask g = gt[lo];
+  const int r = bid - g.tile0;
+  cgemm_tile<TAG, R, TNT>(shapes[g.shape], g.task, segs, (const typename Mf<R>::AE *)g.A,
+                          (const typename Mf<R>::AE *)g.B, g.C, r / g.tilesN, r % g.tilesN);
 }
 
 // BF16-split variant of the same product for the mixed form: FP32 tiles in LDS,
@@ -1060,8 +1099,8 @@ static void drop_graphs(ccgf_ctx *c) {
   }
 }
 
-int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y, int prec) {
-  if (nvec <= 0) return CCGF_OK;
+// The plan of (part, K, nvec) and the workspace of a product of nvec vectors.
+static int sigma_prepare(ccgf_ctx *c, int part, int K, int nvec, int prec, SigmaPlan **Pout) {
   const long long n = vec_len(c, part);
   // workspace
   size_t need = (size_t)nvec * n;
@@ -1161,6 +1200,14 @@ int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y, 
       return set_err(c, CCGF_EINVAL, "internal: sigma GEMM plan exceeds its buffers");
     }
   }
+  *Pout = P;
+  return CCGF_OK;
+}
+
+int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y, int prec) {
+  if (nvec <= 0) return CCGF_OK;
+  SigmaPlan *P = nullptr;
+  if (int rc = sigma_prepare(c, part, K, nvec, prec, &P)) return rc;
   hipStream_t s = c->stream;
   const bool timing = c->opt.timing != 0;
   ccgf_ctx::TimedSigma *ts = nullptr;
@@ -1250,4 +1297,213 @@ void timing_release(ccgf_ctx *c) {
     for (int q = 0; q < 4; ++q)
       if (r.e[q]) hipEventDestroy(r.e[q]);
   c->tring.clear();
+}
+
+// ------------------------------------------------------------------ several systems at once
+// sigma products of several systems (uneven Nk, No, Nv; IP or EA each) in one sequence: every
+// GEMM term is one launch over the tasks of all systems that have it, each task with its own
+// shape and operands (k_cgemm_group); the element-wise terms run per system.  The products
+// are those of sigma_apply term by term (the same tile arithmetic per output element).
+namespace {
+struct GroupLaunch {
+  int tag, tn, prec;
+  size_t shape0, task0, seg0;  // offsets of this launch's tables in the device buffer
+  int ntask, total;
+};
+
+template <int TAG, typename R>
+void launch_group_t(const GroupLaunch &L, const GemmShape *dsh, const GroupTask *dtk, const GemmSeg *dsg,
+                    hipStream_t s) {
+  const GemmShape *sh = dsh + L.shape0;
+  const GroupTask *tk = dtk + L.task0;
+  const GemmSeg *sg = dsg + L.seg0;
+  if (L.tn == 16)
+    hipLaunchKernelGGL((k_cgemm_group<TAG, R, 16>), dim3(L.total), dim3(256), 0, s, sh, tk, L.ntask, sg, L.total);
+  else if (L.tn == 32)
+    hipLaunchKernelGGL((k_cgemm_group<TAG, R, 32>), dim3(L.total), dim3(256), 0, s, sh, tk, L.ntask, sg, L.total);
+  else
+    hipLaunchKernelGGL((k_cgemm_group<TAG, R, 64>), dim3(L.total), dim3(256), 0, s, sh, tk, L.ntask, sg, L.total);
+}
+
+void launch_group(const GroupLaunch &L, const GemmShape *dsh, const GroupTask *dtk, const GemmSeg *dsg,
+                  hipStream_t s) {
+#define GCASE(T)                                                                   \
+  case T:                                                                          \
+    if (L.prec) launch_group_t<T, float>(L, dsh, dtk, dsg, s);                     \
+    else launch_group_t<T, double>(L, dsh, dtk, dsg, s);                           \
+    break;
+  switch (L.tag) {
+    GCASE(0) GCASE(1) GCASE(2) GCASE(3) GCASE(8) GCASE(9)
+    case 4: launch_group_t<4, double>(L, dsh, dtk, dsg, s); break;
+    case 5: launch_group_t<5, double>(L, dsh, dtk, dsg, s); break;
+    case 6: launch_group_t<6, double>(L, dsh, dtk, dsg, s); break;
+    default: launch_group_t<7, double>(L, dsh, dtk, dsg, s);
+  }
+#undef GCASE
+}
+}  // namespace
+
+int sigma_group(int nsys, ccgf_ctx *const *ctxs, const int *parts, const int *Ks, const int *nvecs,
+                const cplx *const *xs, cplx *const *ys) {
+  ccgf_ctx *c0 = ctxs[0];
+  const int prec = c0->opt.precision;
+  hipStream_t s = c0->stream;
+  std::vector<SigmaPlan *> P(nsys, nullptr);
+  for (int i = 0; i < nsys; ++i) {
+    if (nvecs[i] <= 0) continue;
+    if (int rc = sigma_prepare(ctxs[i], parts[i], Ks[i], nvecs[i], prec, &P[i]))
+      return set_err(c0, rc, "system " + std::to_string(i) + ": " + ctxs[i]->err);
+  }
+  // the operands of each term, per system
+  struct Item {
+    const GemmPlan *plan;
+    const void *A, *B;
+    cplx *C;
+  };
+  auto xb = [&](int i) -> const void * { return prec ? (const void *)ctxs[i]->sig_x32 : (const void *)xs[i]; };
+  std::vector<std::pair<int, std::vector<Item>>> terms;  // (tag, items), in launch order
+  auto add = [&](int tag, int i, const GemmPlan &g, const void *A, const void *B, cplx *C) {
+    if (g.ntask == 0 || g.shape.M == 0 || g.shape.N == 0) return;
+    for (auto &t : terms)
+      if (t.first == tag) {
+        t.second.push_back({&g, A, B, C});
+        return;
+      }
+    terms.push_back({tag, {{&g, A, B, C}}});
+  };
+  for (int i = 0; i < nsys; ++i) {
+    if (!P[i]) continue;
+    ccgf_ctx *c = ctxs[i];
+    if (parts[i] == CCGF_PART_EA) {
+      const void *Wbig = prec ? (const void *)c->Wvvvv32 : (const void *)c->Wvvvv;
+      add(0, i, P[i]->g_big, Wbig, xb(i), ys[i]);
+    } else {
+      add(2, i, P[i]->g_big, prec ? (const void *)c->WooP32 : (const void *)c->WooP, xb(i), ys[i]);
+    }
+  }
+  for (int i = 0; i < nsys; ++i)
+    if (P[i] && parts[i] == CCGF_PART_EA) {
+      ccgf_ctx *c = ctxs[i];
+      const void *Wbig = prec ? (const void *)c->Wvvvv32 : (const void *)c->Wvvvv;
+      add(8, i, P[i]->g_bigt, Wbig, xb(i), ys[i]);
+    }
+  for (int i = 0; i < nsys; ++i)
+    if (P[i] && parts[i] == CCGF_PART_EA) {
+      ccgf_ctx *c = ctxs[i];
+      const void *Wbig = prec ? (const void *)c->Wvvvv32 : (const void *)c->Wvvvv;
+      add(9, i, P[i]->g_bigd, Wbig, xb(i), ys[i]);
+    }
+  for (int i = 0; i < nsys; ++i) {
+    if (!P[i]) continue;
+    ccgf_ctx *c = ctxs[i];
+    if (parts[i] == CCGF_PART_EA) {
+      add(1, i, P[i]->g_ovvo, prec ? (const void *)c->WvoPea32 : (const void *)c->WvoPea, xb(i), c->sig_tmp);
+      add(6, i, P[i]->g_red1, c->Wvovv, xs[i], c->sig_part);
+      add(6, i, P[i]->g_red2, c->Voovv, xs[i], c->sig_part);
+    } else {
+      add(3, i, P[i]->g_ovvo, prec ? (const void *)c->WvoP32 : (const void *)c->WvoP, xb(i), c->sig_tmp);
+      add(7, i, P[i]->g_red1, c->Wooov, xs[i], c->sig_part);
+      add(7, i, P[i]->g_red2, c->Voovv, xs[i], c->sig_part);
+    }
+  }
+  const size_t nfirst = terms.size();  // the terms above run before the antisymmetric fill
+  for (int i = 0; i < nsys; ++i) {
+    if (!P[i]) continue;
+    ccgf_ctx *c = ctxs[i];
+    if (parts[i] == CCGF_PART_EA) add(4, i, P[i]->g_r1, c->Wvvvo, xs[i], ys[i]);
+    else add(5, i, P[i]->g_r1, c->Wovoo, xs[i], ys[i]);
+  }
+  // tables of every launch, uploaded once
+  std::vector<GemmShape> shapes;
+  std::vector<GroupTask> tasks;
+  std::vector<GemmSeg> segs;
+  std::vector<GroupLaunch> launches;
+  for (auto &t : terms) {
+    const int tag = t.first;
+    const bool big = tag <= 3 || tag == 8 || tag == 9;
+    int maxN = 0;
+    for (const Item &it : t.second) maxN = std::max(maxN, it.plan->shape.N);
+    const int tn = big ? (maxN <= 16 ? 16 : maxN <= 32 ? 32 : 64) : 32;
+    GroupLaunch L{tag, tn, big ? prec : 0, shapes.size(), tasks.size(), segs.size(), 0, 0};
+    int tile = 0;
+    for (const Item &it : t.second) {
+      const GemmPlan &g = *it.plan;
+      const int si = (int)(shapes.size() - L.shape0), seg0 = (int)(segs.size() - L.seg0);
+      shapes.push_back(g.shape);
+      segs.insert(segs.end(), g.segs.begin(), g.segs.end());
+      const int tM = (g.shape.M + TM - 1) / TM, tN = (g.shape.N + tn - 1) / tn;
+      for (GemmTask k : g.tasks) {
+        k.seg_begin += seg0;
+        tasks.push_back(GroupTask{it.A, it.B, it.C, k, si, tile, tM, tN});
+        tile += tM * tN;
+      }
+    }
+    L.ntask = (int)(tasks.size() - L.task0);
+    L.total = tile;
+    launches.push_back(L);
+  }
+  const size_t bytes = shapes.size() * sizeof(GemmShape) + tasks.size() * sizeof(GroupTask) +
+                       segs.size() * sizeof(GemmSeg) + 3 * 256;
+  if (c0->grp_bytes < bytes) {
+    if (c0->grp_buf) {
+      hipStreamSynchronize(s);
+      for (auto &q : c0->allocs)
+        if (q == c0->grp_buf) q = nullptr;
+      hipFree(c0->grp_buf);
+    }
+    c0->grp_buf = dev_alloc(c0, bytes);
+    c0->grp_bytes = c0->grp_buf ? bytes : 0;
+    if (!c0->grp_buf) return set_err(c0, CCGF_ENOMEM, "no device memory for the grouped launch tables");
+  }
+  auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  char *base = (char *)c0->grp_buf;
+  GemmShape *dsh = (GemmShape *)base;
+  GroupTask *dtk = (GroupTask *)(base + align(shapes.size() * sizeof(GemmShape)));
+  GemmSeg *dsg = (GemmSeg *)((char *)dtk + align(tasks.size() * sizeof(GroupTask)));
+  // the previous grouped call has finished (it synchronised before returning)
+  if (hipMemcpy(dsh, shapes.data(), shapes.size() * sizeof(GemmShape), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dtk, tasks.data(), tasks.size() * sizeof(GroupTask), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dsg, segs.data(), segs.size() * sizeof(GemmSeg), hipMemcpyHostToDevice) != hipSuccess)
+    return hip_check(c0, hipGetLastError(), "grouped launch tables");
+  // the reduced-precision products read complex-float copies of the vectors
+  for (int i = 0; i < nsys; ++i)
+    if (P[i] && prec) {
+      const size_t tot = (size_t)nvecs[i] * P[i]->n;
+      hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, xs[i], ctxs[i]->sig_x32,
+                         tot);
+    }
+  for (size_t l = 0; l < nfirst; ++l) launch_group(launches[l], dsh, dtk, dsg, s);
+  // blocks left to antisymmetry, before the terms that accumulate into them
+  for (int i = 0; i < nsys; ++i)
+    if (P[i] && parts[i] == CCGF_PART_EA && P[i]->nfill > 0) {
+      const int no = ctxs[i]->no, nv = ctxs[i]->nv;
+      const long long b2 = (long long)no * nv * nv;
+      hipLaunchKernelGGL(k_vvvv_fill, dim3((unsigned)((b2 + 255) / 256), P[i]->nfill, std::min(nvecs[i], 64)),
+                         dim3(256), 0, s, ys[i], P[i]->n, nvecs[i], nv, b2, P[i]->d_fill, P[i]->d_fill + P[i]->nfill,
+                         P[i]->nfill);
+    }
+  for (size_t l = nfirst; l < launches.size(); ++l) launch_group(launches[l], dsh, dtk, dsg, s);
+  for (int i = 0; i < nsys; ++i) {
+    if (!P[i]) continue;
+    ccgf_ctx *c = ctxs[i];
+    const int nk = c->nk, no = c->no, nv = c->nv, K = Ks[i], nvec = nvecs[i];
+    const long long n = P[i]->n;
+    const unsigned gy = (unsigned)std::min(nvec, 65535);
+    if (parts[i] == CCGF_PART_EA) {
+      hipLaunchKernelGGL(k_r1_finish, dim3((unsigned)(((nv + no) * nvec + 3) / 4)), dim3(256), 0, s, 1, nk, no, nv, K,
+                         nv + no, nv, nvec, nk * nk * no, n, c->sig_part, xs[i], ys[i], c->sig_r1aux, std::max(no, nv),
+                         c->Foo, c->Fvv, c->Fov);
+      const long long tot = (long long)nk * nk * no * nv * nv;
+      hipLaunchKernelGGL(k_ea_local, dim3((unsigned)((tot + 255) / 256), gy), dim3(256), 0, s, nk, no, nv, K, nvec, n,
+                         c->kc3, xs[i], ys[i], c->sig_tmp, c->sig_r1aux, c->Foo, c->Fvv, c->t2);
+    } else {
+      hipLaunchKernelGGL(k_r1_finish, dim3((unsigned)(((nv + no) * nvec + 3) / 4)), dim3(256), 0, s, 0, nk, no, nv, K,
+                         no + nv, no, nvec, nk * nk * no, n, c->sig_part, xs[i], ys[i], c->sig_r1aux, std::max(no, nv),
+                         c->Foo, c->Fvv, c->Fov);
+      const long long tot = (long long)nk * nk * no * no * nv;
+      hipLaunchKernelGGL(k_ip_local, dim3((unsigned)((tot + 255) / 256), gy), dim3(256), 0, s, nk, no, nv, K, nvec, n,
+                         c->kc3, xs[i], ys[i], c->sig_tmp, c->sig_r1aux, c->Foo, c->Fvv, c->t2);
+    }
+  }
+  return hip_check(c0, hipGetLastError(), "grouped sigma launch");
 }

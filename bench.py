@@ -92,11 +92,19 @@ def form_precision(form):
     return "f64" if form == "plain_f64" else form.split("_")[-1]
 
 
+def kernel_source_sha():
+    """SHA-256 of the source of the sigma GEMM kernels (k_cgemm and its tile body, from
+    the MFMA arithmetic helpers to the BF16-split variant)."""
+    src = open(os.path.join(ROOT, "paper_2208_07478_amd", "csrc", "sigma.hip")).read()
+    a = src.index("// Real arithmetic of one GEMM variant")
+    b = src.index("// BF16-split variant of the same product")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()
+
+
 def stored_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summaries,
     or None when the kernel source changed since the counters were taken."""
-    src = os.path.join(ROOT, "paper_2208_07478_amd", "csrc", "sigma.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    sha = kernel_source_sha()
     pdir = os.path.join(ROOT, "profiles")
     if not os.path.isdir(pdir):
         return None

@@ -157,6 +157,8 @@ typedef struct {
   long long n_guess;         /* solves started from a guess (trained network or Krylov seed) */
   long long n_guess_rejected; /* guesses discarded, started from 0 instead: ||b - A x0|| was not
                                  below accept ||b|| (network) or ||b|| (Krylov seed) */
+  double big_bytes;          /* (timing) algorithmic HBM bytes of the big_launches: the W blocks each
+                                reads, once, the vectors' operand copy once, the output written once */
 } ccgf_stats;
 
 /* Validates the system (shapes, t2 and l2 antisymmetry, factor Hermiticity, each to

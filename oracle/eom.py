@@ -225,6 +225,30 @@ class EOMSystem:
     def sigma(self, part, K, x):
         return self.sigma_ip(K, x) if part == "ip" else self.sigma_ea(K, x)
 
+    def reduced_terms_abs(self, part, K, x):
+        """Elementwise sum of |operand| |r| over the sigma terms that the mixed forms take
+        as reduced-precision products, as a real full vector (zero on the one-quasiparticle
+        part, which stays in FP64): EA 1/2 W_abcd r_i^cd and (W_lbdi r_l^ad + F_bd r_i^ad)
+        taken before the (a, b) antisymmetriser, so that both of its images count; IP
+        1/2 W_mnij r_mn^a and W_maei r_mj^e likewise over (i, j).  The rounding error of a
+        product sum_k A_k B_k is at most a small multiple of sum_k |A_k| |B_k|, so a
+        multiple of this vector bounds those products' error elementwise a priori."""
+        r1, r2 = self.split(part, K, x)
+        ab = lambda t: t.like(np.abs(t.data))
+        ke = keinsum
+        if part == "ea":
+            S2 = (-1, 1, 1)
+            b = ke("abcd,icd->iab", ab(self.Wvvvv), ab(r2), out_signs=S2, out_const=K, alpha=0.5)
+            x2 = ke("lbdi,lad->iab", ab(self.Wovvo), ab(r2), out_signs=S2, out_const=K)
+            ke("bd,iad->iab", ab(self.Fvv), ab(r2), out_signs=S2, out_const=K, out=x2)
+            b = b + x2 + permute("iab->iba", x2)
+        else:
+            S2 = (1, 1, -1)
+            b = ke("mnij,mna->ija", ab(self.Woooo), ab(r2), out_signs=S2, out_const=K, alpha=0.5)
+            x2 = ke("maei,mje->ija", ab(self.Wovvo), ab(r2), out_signs=S2, out_const=K)
+            b = b + x2 + permute("ija->jia", x2)
+        return np.concatenate([np.zeros(r1.data.size), b.data.real.ravel()])
+
     # ---------------------------------------------------------- diagonal
     def diag(self, part, K):
         """Diagonal of M from the one-body blocks (the preconditioner D)."""

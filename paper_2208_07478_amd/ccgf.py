@@ -56,7 +56,7 @@ class Stats(ctypes.Structure):
                 ("big_flops", ctypes.c_double), ("sigma_ms", ctypes.c_double),
                 ("sigma_launches", ctypes.c_longlong), ("n_steps", ctypes.c_longlong),
                 ("n_reorth", ctypes.c_longlong), ("n_guess", ctypes.c_longlong),
-                ("n_guess_rejected", ctypes.c_longlong)]
+                ("n_guess_rejected", ctypes.c_longlong), ("big_bytes", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

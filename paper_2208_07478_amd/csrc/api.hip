@@ -286,7 +286,7 @@ static int solve_common(ccgf_ctx *c, int nkq, const int *kidx, int norb, const i
   ccgf_stats local{};
   ccgf_stats *S = st ? st : &local;
   std::memset(S, 0, sizeof(*S));
-  c->t_big_ms = c->t_big_flops = c->t_sigma_ms = 0;
+  c->t_big_ms = c->t_big_flops = c->t_big_bytes = c->t_sigma_ms = 0;
   c->t_big_launches = c->t_sigma_launches = 0;
   const size_t ntot = (size_t)nkq * norb * nw;
   std::vector<cplx> Gsum(ntot, mkc(0, 0)), Gplus(ntot, mkc(0, 0)), Gminus(ntot, mkc(0, 0));
@@ -388,6 +388,7 @@ static int solve_common(ccgf_ctx *c, int nkq, const int *kidx, int norb, const i
   S->big_ms = c->t_big_ms;
   S->big_launches = c->t_big_launches;
   S->big_flops = c->t_big_flops;
+  S->big_bytes = c->t_big_bytes;
   S->sigma_ms = c->t_sigma_ms;
   S->sigma_launches = c->t_sigma_launches;
   return status;
@@ -458,7 +459,7 @@ extern "C" int cc_gf_mor(ccgf_ctx *c, int nkq, const int *kidx, int norb, const 
   ccgf_stats local{};
   ccgf_stats *S = st ? st : &local;
   std::memset(S, 0, sizeof(*S));
-  c->t_big_ms = c->t_big_flops = c->t_sigma_ms = 0;
+  c->t_big_ms = c->t_big_flops = c->t_big_bytes = c->t_sigma_ms = 0;
   c->t_big_launches = c->t_sigma_launches = 0;
   const size_t ntot = (size_t)nkq * norb * nw;
   std::vector<cplx> Gsum(ntot, mkc(0, 0)), Gplus(ntot, mkc(0, 0)), Gminus(ntot, mkc(0, 0));
@@ -494,6 +495,7 @@ extern "C" int cc_gf_mor(ccgf_ctx *c, int nkq, const int *kidx, int norb, const 
   S->big_ms = c->t_big_ms;
   S->big_launches = c->t_big_launches;
   S->big_flops = c->t_big_flops;
+  S->big_bytes = c->t_big_bytes;
   S->sigma_ms = c->t_sigma_ms;
   S->sigma_launches = c->t_sigma_launches;
   return status;

@@ -20,6 +20,18 @@ __host__ __device__ inline cplx cmul(cplx a, cplx b) {
 }
 __host__ __device__ inline cplx cconj(cplx a) { return mkc(a.x, -a.y); }
 __host__ __device__ inline cplx cscale(cplx a, double s) { return mkc(a.x * s, a.y * s); }
+
+// One complex element split for the BF16 products: x = hi + lo to about 2^-16 relative,
+// hi = bf16(x), lo = bf16(x - hi), for the real and the imaginary part (8 bytes, the size
+// of a complex float, so that the split operands take the complex float copies' place)
+struct B3E {
+  __bf16 rh, rl, ih, il;
+};
+static_assert(sizeof(B3E) == 8, "split element layout");
+__device__ inline void split_bf(double x, __bf16 &h, __bf16 &l) {
+  h = (__bf16)(float)x;
+  l = (__bf16)(float)(x - (double)(float)h);
+}
 // acc += a * b
 __host__ __device__ inline void cfma(cplx &acc, cplx a, cplx b) {
   acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
@@ -238,7 +250,8 @@ struct ccgf_ctx {
   cplx *WvoP = nullptr;   // W_ovvo permuted to [kx][ki][km](x, i, m, e)
   cplx *WvoPea = nullptr; // the same with F_vv added on the blocks km = ki, m = i (EA operand)
   cplx *WooP = nullptr;   // W_oooo permuted to [ki][kj][km](i, j, m, n)
-  // complex-float copies of the GEMM operands for the mixed-precision products
+  // complex-float copies of the GEMM operands for the mixed-precision products (B3E split
+  // copies, the same size, for the BF16-split form)
   float2 *Wvvvv32 = nullptr, *WvoP32 = nullptr, *WooP32 = nullptr, *WvoPea32 = nullptr;
   std::vector<void *> allocs;
   // sigma workspace
@@ -247,7 +260,7 @@ struct ccgf_ctx {
   cplx *sig_r1aux = nullptr;  // per-RHS 3-body contraction (nvec x max(no, nv))
   size_t sig_r1aux_elems = 0;
   cplx *e_overlap = nullptr;  // [max(no, nv)] scratch of the e vectors (t2 overlap term)
-  float2 *sig_x32 = nullptr;  // complex float copy of the vectors (reduced-precision GEMMs)
+  float2 *sig_x32 = nullptr;  // complex float (or B3E split) copy of the vectors (reduced-precision GEMMs)
   size_t sig_x32_elems = 0;
   cplx *sig_part = nullptr;  // split-range partial sums of the 1h / 1p rows
   size_t sig_part_elems = 0;
@@ -272,11 +285,12 @@ struct ccgf_ctx {
     hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};  // sigma start, sigma end, big GEMM start, end
     int big = 0;           // count the big GEMM (EA products)
     double flops = 0;      // its algorithmic flops
+    double bytes = 0;      // and HBM bytes
     bool pending = false;
   };
   std::vector<TimedSigma> tring;
   int tnext = 0;
-  double t_big_ms = 0, t_big_flops = 0, t_sigma_ms = 0;
+  double t_big_ms = 0, t_big_flops = 0, t_big_bytes = 0, t_sigma_ms = 0;
   long long t_big_launches = 0, t_sigma_launches = 0;
 };
 

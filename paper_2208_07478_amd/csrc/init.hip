@@ -403,12 +403,22 @@ int build_hbar(ccgf_ctx *c) {
   // blocks that only fed the others
   release(c->Woooo); c->Woooo = nullptr;
   release(c->Wovvo); c->Wovvo = nullptr;
-  if (c->opt.precision != CCGF_PLAIN_F64) {  // FP32 operands of the big products (both mixed forms)
-    // complex-float copies of the GEMM operands (rounded once, here)
+  if (c->opt.precision != CCGF_PLAIN_F64) {  // reduced-precision operands of the big products
+    // complex-float copies of the GEMM operands (rounded once, here), or for the BF16-split
+    // form their split copies (four bf16 planes per element, the same size)
+    const bool split = c->opt.precision == CCGF_MIXED_BF16X3;
     auto to32 = [&](const cplx *src, size_t nel) -> float2 * {
       float2 *d = (float2 *)dev_alloc(c, nel * sizeof(float2));
       if (!d) return nullptr;
-      foreach_(s, nel, [=] __device__(size_t i) { d[i] = make_float2((float)src[i].x, (float)src[i].y); });
+      if (split)
+        foreach_(s, nel, [=] __device__(size_t i) {
+          B3E e;
+          split_bf(src[i].x, e.rh, e.rl);
+          split_bf(src[i].y, e.ih, e.il);
+          ((B3E *)d)[i] = e;
+        });
+      else
+        foreach_(s, nel, [=] __device__(size_t i) { d[i] = make_float2((float)src[i].x, (float)src[i].y); });
       return d;
     };
     c->Wvvvv32 = to32(c->Wvvvv, nv4 * (size_t)c->nwblk);

@@ -202,14 +202,14 @@ __device__ __forceinline__ void cgemm_tile(const GemmShape &sh, const GemmTask &
       }
 }
 
-// XCD-aware block order: consecutive logical tiles share an XCD (and its L2)
+// XCD-aware block order: the hardware hands block b to XCD b % 8, so XCD x runs blocks
+// x, x + 8, ...; give it the consecutive logical tiles [x q + min(x, r), ...) (q = total / 8,
+// r = total % 8: the first r XCDs take one more).  Tiles of one task that read the same
+// operand panel (its N tiles, its M tiles) then share an XCD and its L2.
 __device__ inline int xcd_block(int total) {
-  int bid = blockIdx.x;
-  if ((total & 7) == 0) {
-    const int per = total >> 3;
-    bid = (bid & 7) * per + (bid >> 3);
-  }
-  return bid;
+  const int bid = blockIdx.x, x = bid & 7, j = bid >> 3;
+  const int q = total >> 3, r = total & 7;
+  return x * q + min(x, r) + j;
 }
 
 template <int TAG, typename R, int TNT>
@@ -251,148 +251,147 @@ __global__ __launch_bounds__(256, TNT <= 48 ? 4 : 2) void k_cgemm_group(const Ge
                           (const typename Mf<R>::AE *)g.B, g.C, r / g.tilesN, r % g.tilesN);
 }
 
-// BF16-split variant of the same product for the mixed form: FP32 tiles in LDS,
-// each value split in registers into hi = bf16(x) and lo = bf16(x - hi), each
-// real product taken as hi*hi + hi*lo + lo*hi on the 16x16x32 BF16 MFMA with
-// FP32 accumulation (lane l feeds row (or column) l%16 and k = 8(l/16) .. +7;
-// item v of lane l is row 4(l/16)+v).  64x64 tiles, k-slabs of 32.
+// BF16-split variant of the same product for the mixed form.  Both operands are
+// stored pre-split, four bf16 planes per complex element (re hi, re lo, im hi, im lo
+// with hi = bf16(x) and lo = bf16(x - hi), so x = hi + lo to about 2^-16 relative):
+// W once when the context is built, the vectors once per product (k_to_b3).  Each
+// real product is taken as hi*hi + hi*lo + lo*hi on the 16x16x32 BF16 MFMA with FP32
+// accumulation, and the complex product from its four real products (the two cross
+// terms share an accumulator): twelve MFMAs per 16x16x32 step, no conversions in the
+// inner loop.  Lane l feeds row (or column) l%16 and k = 8(l/16) .. +7; item v of
+// lane l is row 4(l/16)+v.  Tiles and staging follow cgemm_tile, with k-slabs of 32.
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
-#define TKB 32
 
-struct Split8 {
-  v8bf h, l;
-};
-__device__ inline Split8 split8(const float *x) {
-  Split8 r;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    __bf16 h = (__bf16)x[i];
-    r.h[i] = h;
-    r.l[i] = (__bf16)(x[i] - (float)h);
-  }
-  return r;
-}
-__device__ inline v4f mm3(const Split8 &a, const Split8 &b, v4f c) {
-  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.h, c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.l, c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.l, b.h, c, 0, 0, 0);
-  return c;
-}
-
-template <int TAG>
-__global__ __launch_bounds__(256, 2) void k_cgemm_b3(GemmShape sh, const GemmTask *__restrict__ tasks,
-                                                     const GemmSeg *__restrict__ segs, const float2 *__restrict__ A,
-                                                     const float2 *__restrict__ B, cplx *__restrict__ C, int tilesM,
-                                                     int tilesN, int total) {
-  int bid = blockIdx.x;
-  if ((total & 7) == 0) {
-    int per = total >> 3;
-    bid = (bid & 7) * per + (bid >> 3);
-  }
-  const int per_task = tilesM * tilesN;
-  const int t = bid / per_task, r = bid % per_task;
-  const int tm = r / tilesN, tn = r % tilesN;
-  const GemmTask task = tasks[t];
-  __shared__ float Ar[TM][TKB + 1], Ai[TM][TKB + 1], Br[64][TKB + 1], Bi[64][TKB + 1];
+template <int TAG, int TNT>
+__device__ __forceinline__ void cgemm_b3_tile(const GemmShape &sh, const GemmTask &task,
+                                              const GemmSeg *__restrict__ segs, const B3E *__restrict__ A,
+                                              const B3E *__restrict__ B, cplx *__restrict__ C, int tm, int tn) {
+  constexpr int KS = 32, LD = KS + 8;  // k-slab; LDS row stride in bf16 (rows stay 16-byte aligned)
+  constexpr int RPP = 256 / KS;        // rows staged per pass of the block
+  constexpr int AJ = TM / RPP;         // A rows staged per thread
+  constexpr int NBJ = TNT / RPP;       // B rows staged per thread
+  constexpr bool NARROW = TNT <= 48;
+  constexpr int AM = NARROW ? 1 : 2;                // MFMA row tiles per wave
+  constexpr int BN = NARROW ? TNT / 16 : TNT / 32;  // MFMA column tiles per wave
+  __shared__ __attribute__((aligned(16))) __bf16 As[4][TM][LD];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[4][TNT][LD];
   const int tid = threadIdx.x;
-  // each thread stages column kt of rows rt + 8 j (j = 0..7) of both tiles
-  const int kt = tid & (TKB - 1), rt = tid >> 5;
-  long long aoff[8], boff[8];
-  bool aok[8], bok[8];
+  const int kt = tid & (KS - 1), rt = tid / KS;
+  long long aoff[AJ], boff[NBJ];
+  bool aok[AJ], bok[NBJ];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    int m = tm * TM + rt + 8 * j;
+  for (int j = 0; j < AJ; ++j) {
+    int m = tm * TM + rt + RPP * j;
     aok[j] = m < sh.M;
     aoff[j] = aok[j] ? imap(sh.am, sh.mtab ? sh.mtab[m] : m) : 0;
-    int n = tn * 64 + rt + 8 * j;
+  }
+#pragma unroll
+  for (int j = 0; j < NBJ; ++j) {
+    int n = tn * TNT + rt + RPP * j;
     bok[j] = n < sh.N;
     boff[j] = bok[j] ? imap(sh.bn, n) : 0;
   }
-  const int ksteps = (sh.K + TKB - 1) / TKB;
+  const int ksteps = (sh.K + KS - 1) / KS;
   const int nsteps = task.nseg * ksteps;
-  v4f P1[2][2], P2[2][2], P3[2][2];
+  v4f Prr[AM][BN], Pii[AM][BN], Px[AM][BN];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < AM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      P1[a][b] = (v4f){0, 0, 0, 0};
-      P2[a][b] = (v4f){0, 0, 0, 0};
-      P3[a][b] = (v4f){0, 0, 0, 0};
+    for (int b = 0; b < BN; ++b) {
+      Prr[a][b] = (v4f){0, 0, 0, 0};
+      Pii[a][b] = (v4f){0, 0, 0, 0};
+      Px[a][b] = (v4f){0, 0, 0, 0};
     }
-  float2 ra[8], rb[8];
+  B3E ra[AJ], rb[NBJ];
   auto load = [&](int step) {
     int s = step / ksteps;
-    int k = (step - s * ksteps) * TKB + kt;
+    int k = (step - s * ksteps) * KS + kt;
     GemmSeg sg = segs[task.seg_begin + s];
     const bool kok = k < sh.K;
     if (kok && sh.ktab) k = sh.ktab[k];
-    const float2 *Ap = A + sg.a_off + (kok ? imap(sh.ak, k) : 0);
-    const float2 *Bp = B + sg.b_off + (kok ? imap(sh.bk, k) : 0);
-    const float w = (float)sg.w;
+    const B3E *Ap = A + sg.a_off + (kok ? imap(sh.ak, k) : 0);
+    const B3E *Bp = B + sg.b_off + (kok ? imap(sh.bk, k) : 0);
+    const B3E z{0, 0, 0, 0};
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      ra[j] = (aok[j] && kok) ? Ap[aoff[j]] : float2{0, 0};
-      const float2 b = (bok[j] && kok) ? Bp[boff[j]] : float2{0, 0};
-      rb[j] = float2{b.x * w, b.y * w};
+    for (int j = 0; j < AJ; ++j) ra[j] = (aok[j] && kok) ? Ap[aoff[j]] : z;
+#pragma unroll
+    for (int j = 0; j < NBJ; ++j) rb[j] = (bok[j] && kok) ? Bp[boff[j]] : z;
+    if (sg.w != 1.0) {  // 1/2 (self-paired segments): exact on each part
+      const float w = (float)sg.w;
+#pragma unroll
+      for (int j = 0; j < NBJ; ++j) {
+        rb[j].rh = (__bf16)((float)rb[j].rh * w);
+        rb[j].rl = (__bf16)((float)rb[j].rl * w);
+        rb[j].ih = (__bf16)((float)rb[j].ih * w);
+        rb[j].il = (__bf16)((float)rb[j].il * w);
+      }
     }
   };
   const int wave = tid >> 6, lane = tid & 63;
-  const int rbase = (wave >> 1) * 32, cbase = (wave & 1) * 32;
+  const int rbase = NARROW ? wave * 16 : (wave >> 1) * 32;
+  const int cbase = NARROW ? 0 : (wave & 1) * (TNT / 2);
   const int lr = lane & 15, lk = lane >> 4;
   if (nsteps > 0) load(0);
   for (int step = 0; step < nsteps; ++step) {
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      Ar[rt + 8 * j][kt] = ra[j].x;
-      Ai[rt + 8 * j][kt] = ra[j].y;
-      Br[rt + 8 * j][kt] = rb[j].x;
-      Bi[rt + 8 * j][kt] = rb[j].y;
+    for (int j = 0; j < AJ; ++j) {
+      const int r = rt + RPP * j;
+      As[0][r][kt] = ra[j].rh;
+      As[1][r][kt] = ra[j].rl;
+      As[2][r][kt] = ra[j].ih;
+      As[3][r][kt] = ra[j].il;
+    }
+#pragma unroll
+    for (int j = 0; j < NBJ; ++j) {
+      const int r = rt + RPP * j;
+      Bs[0][r][kt] = rb[j].rh;
+      Bs[1][r][kt] = rb[j].rl;
+      Bs[2][r][kt] = rb[j].ih;
+      Bs[3][r][kt] = rb[j].il;
     }
     __syncthreads();
     if (step + 1 < nsteps) load(step + 1);
-    Split8 sa[2][3], sb[2][3];  // [tile][re, im, re + im]
+    v8bf fa[AM][4];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      float xr[8], xi[8], xs[8], yr[8], yi[8], ys[8];
+    for (int q = 0; q < AM; ++q)
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        xr[i] = Ar[rbase + q * 16 + lr][8 * lk + i];
-        xi[i] = Ai[rbase + q * 16 + lr][8 * lk + i];
-        xs[i] = xr[i] + xi[i];
-        yr[i] = Br[cbase + q * 16 + lr][8 * lk + i];
-        yi[i] = Bi[cbase + q * 16 + lr][8 * lk + i];
-        ys[i] = yr[i] + yi[i];
+      for (int p = 0; p < 4; ++p) fa[q][p] = *(const v8bf *)&As[p][rbase + q * 16 + lr][8 * lk];
+#pragma unroll
+    for (int b = 0; b < BN; ++b) {
+      v8bf fb[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) fb[p] = *(const v8bf *)&Bs[p][cbase + b * 16 + lr][8 * lk];
+#pragma unroll
+      for (int a = 0; a < AM; ++a) {
+        // planes: 0 re hi, 1 re lo, 2 im hi, 3 im lo
+        Prr[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][0], fb[0], Prr[a][b], 0, 0, 0);
+        Prr[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][0], fb[1], Prr[a][b], 0, 0, 0);
+        Prr[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][1], fb[0], Prr[a][b], 0, 0, 0);
+        Pii[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][2], fb[2], Pii[a][b], 0, 0, 0);
+        Pii[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][2], fb[3], Pii[a][b], 0, 0, 0);
+        Pii[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][3], fb[2], Pii[a][b], 0, 0, 0);
+        Px[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][0], fb[2], Px[a][b], 0, 0, 0);
+        Px[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][0], fb[3], Px[a][b], 0, 0, 0);
+        Px[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][1], fb[2], Px[a][b], 0, 0, 0);
+        Px[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][2], fb[0], Px[a][b], 0, 0, 0);
+        Px[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][2], fb[1], Px[a][b], 0, 0, 0);
+        Px[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a][3], fb[0], Px[a][b], 0, 0, 0);
       }
-      sa[q][0] = split8(xr);
-      sa[q][1] = split8(xi);
-      sa[q][2] = split8(xs);
-      sb[q][0] = split8(yr);
-      sb[q][1] = split8(yi);
-      sb[q][2] = split8(ys);
     }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        P1[a][b] = mm3(sa[a][0], sb[b][0], P1[a][b]);
-        P2[a][b] = mm3(sa[a][1], sb[b][1], P2[a][b]);
-        P3[a][b] = mm3(sa[a][2], sb[b][2], P3[a][b]);
-      }
   }
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < AM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < BN; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         int row = rbase + a * 16 + 4 * lk + v;
         int col = cbase + b * 16 + lr;
-        int m = tm * TM + row, n = tn * 64 + col;
+        int m = tm * TM + row, n = tn * TNT + col;
         if (m < sh.M && n < sh.N) {
           long long off = task.c_off + imap(sh.cm, sh.mtab ? sh.mtab[m] : m) + imap(sh.cn, n);
-          double p1 = P1[a][b][v], p2 = P2[a][b][v];
-          double re = p1 - p2, im = (double)P3[a][b][v] - p1 - p2;
+          const double re = (double)Prr[a][b][v] - (double)Pii[a][b][v], im = Px[a][b][v];
           cplx val = mkc(sh.alpha_re * re - sh.alpha_im * im, sh.alpha_re * im + sh.alpha_im * re);
           if (sh.accumulate) val = cadd(val, C[off]);
           C[off] = val;
@@ -400,13 +399,31 @@ __global__ __launch_bounds__(256, 2) void k_cgemm_b3(GemmShape sh, const GemmTas
       }
 }
 
-template <int TAG>
-static void launch_b3(const GemmPlan &plan, const void *A, const void *B, cplx *C, hipStream_t s) {
+template <int TAG, int TNT>
+__global__ __launch_bounds__(256, 2) void k_cgemm_b3(GemmShape sh, const GemmTask *__restrict__ tasks,
+                                                     const GemmSeg *__restrict__ segs, const B3E *__restrict__ A,
+                                                     const B3E *__restrict__ B, cplx *__restrict__ C, int tilesM,
+                                                     int tilesN, int total) {
+  const int bid = xcd_block(total);
+  const int per_task = tilesM * tilesN;
+  const int t = bid / per_task, r = bid % per_task;
+  cgemm_b3_tile<TAG, TNT>(sh, tasks[t], segs, A, B, C, r / tilesN, r % tilesN);
+}
+
+template <int TAG, int TNT>
+static void launch_b3t(const GemmPlan &plan, const void *A, const void *B, cplx *C, hipStream_t s) {
   const GemmShape &sh = plan.shape;
-  const int tilesM = (sh.M + TM - 1) / TM, tilesN = (sh.N + 63) / 64;
+  const int tilesM = (sh.M + TM - 1) / TM, tilesN = (sh.N + TNT - 1) / TNT;
   const long long total = (long long)plan.ntask * tilesM * tilesN;
-  hipLaunchKernelGGL((k_cgemm_b3<TAG>), dim3((unsigned)total), dim3(256), 0, s, sh, plan.d_tasks, plan.d_segs,
-                     (const float2 *)A, (const float2 *)B, C, tilesM, tilesN, (int)total);
+  hipLaunchKernelGGL((k_cgemm_b3<TAG, TNT>), dim3((unsigned)total), dim3(256), 0, s, sh, plan.d_tasks, plan.d_segs,
+                     (const B3E *)A, (const B3E *)B, C, tilesM, tilesN, (int)total);
+}
+template <int TAG>
+static void launch_b3(const GemmPlan &plan, const void *A, const void *B, cplx *C, hipStream_t s, int tn) {
+  if (tn == 16) launch_b3t<TAG, 16>(plan, A, B, C, s);
+  else if (tn == 32) launch_b3t<TAG, 32>(plan, A, B, C, s);
+  else if (tn == 48) launch_b3t<TAG, 48>(plan, A, B, C, s);
+  else launch_b3t<TAG, 64>(plan, A, B, C, s);  // (no 128-wide tile: it would spill)
 }
 
 template <int TAG, typename R, int TNT>
@@ -433,8 +450,8 @@ static void launch_wn(const GemmPlan &plan, const void *A, const void *B, cplx *
 }
 
 // prec 0: FP64 operands (A and B complex double); prec 1: FP32 (A complex float,
-// B the vectors' complex float copy); prec 2: BF16-split products from the FP32
-// operands (64-wide tiles only).  Tags 4 to 7 run in FP64 only.
+// B the vectors' complex float copy); prec 2: BF16-split products from the split
+// operands (A and the vectors' split copy, four bf16 planes per element).  Tags 4 to 7 run in FP64 only.
 // tn: N tile width (16, 32, 48, 64 or 128), chosen per plan in tuned_launch.
 void gemm_launch(int tag, const GemmPlan &plan, const void *A, const void *B, cplx *C, hipStream_t s, int prec,
                  int tn) {
@@ -442,7 +459,7 @@ void gemm_launch(int tag, const GemmPlan &plan, const void *A, const void *B, cp
   if (plan.ntask == 0 || sh.M == 0 || sh.N == 0) return;
 #define CASE(T)                                                                              \
   case T:                                                                                    \
-    if (prec == 2) launch_b3<T>(plan, A, B, C, s);                                           \
+    if (prec == 2) launch_b3<T>(plan, A, B, C, s, tn);                                       \
     else if (prec) launch_wn<T, float>(plan, A, B, C, s, tn);                                \
     else launch_wn<T, double>(plan, A, B, C, s, tn);                                         \
     break;
@@ -466,6 +483,13 @@ void gemm_launch(int tag, const GemmPlan &plan, const void *A, const void *B, cp
 // algorithmic flops of one launch (8 per complex multiply-add)
 static double plan_flops(const GemmPlan &p) {
   return 8.0 * p.shape.M * (double)p.shape.N * p.shape.K * (double)p.segs.size();
+}
+// algorithmic HBM bytes of one launch: every segment's A block once (complex double, or
+// 8 bytes per element in the reduced-precision forms), the vectors' operand copy once
+// (nx elements) and every task's output block written once (complex double)
+static double plan_bytes(const GemmPlan &p, double nx, int prec) {
+  const double ea = prec ? 8.0 : 16.0;
+  return ea * ((double)p.segs.size() * p.shape.M * p.shape.K + nx) + 16.0 * (double)p.ntask * p.shape.M * p.shape.N;
 }
 
 void plan_upload(ccgf_ctx *c, GemmPlan &p) {
@@ -953,7 +977,7 @@ __global__ __launch_bounds__(256) void k_ip_local(int nk, int no, int nv, int K,
 // autotune file when one is configured).
 static int tuned_launch(ccgf_ctx *c, int tag, GemmPlan &p, const void *A, const void *B, cplx *C, hipStream_t s,
                         int prec) {
-  if (p.tn[prec] == 0 && (c->opt.autotune < 0 || prec == 2)) p.tn[prec] = 64;
+  if (p.tn[prec] == 0 && c->opt.autotune < 0) p.tn[prec] = 64;
   // narrow batches of the big products (N <= 48): the narrowest tile that holds N, where the
   // MFMA work is least padding (the W operand is streamed once either way)
   const bool big = tag <= 3 || tag == 8 || tag == 9;
@@ -1019,6 +1043,16 @@ __global__ void k_to_f32(const cplx *__restrict__ x, float2 *__restrict__ y, siz
   if (i < tot) y[i] = float2{(float)x[i].x, (float)x[i].y};
 }
 
+// the split copy of the vectors for the BF16-split products
+__global__ void k_to_b3(const cplx *__restrict__ x, B3E *__restrict__ y, size_t tot) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= tot) return;
+  B3E e;
+  split_bf(x[i].x, e.rh, e.rl);
+  split_bf(x[i].y, e.ih, e.il);
+  y[i] = e;
+}
+
 // The launches of one sigma product on stream s (event records only when ts is set).
 static int sigma_enqueue(ccgf_ctx *c, SigmaPlan *P, int part, int K, int nvec, const cplx *x, cplx *y, int prec,
                          hipStream_t s, ccgf_ctx::TimedSigma *ts) {
@@ -1029,7 +1063,10 @@ static int sigma_enqueue(ccgf_ctx *c, SigmaPlan *P, int part, int K, int nvec, c
   const void *xb = x;
   if (prec) {
     const size_t tot = (size_t)nvec * n;
-    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, x, c->sig_x32, tot);
+    if (prec == 2)  // (the split copy has the complex float copy's size: four bf16 per element)
+      hipLaunchKernelGGL(k_to_b3, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, x, (B3E *)c->sig_x32, tot);
+    else
+      hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, x, c->sig_x32, tot);
     xb = c->sig_x32;
   }
   // fork: the side stream takes the terms that write other buffers than the big product's
@@ -1227,6 +1264,7 @@ int sigma_apply(ccgf_ctx *c, int part, int K, int nvec, const cplx *x, cplx *y, 
     // mixed form's FP64 true residuals go to the sigma totals alone)
     ts->big = part == CCGF_PART_EA && prec == c->opt.precision;
     ts->flops = ts->big ? plan_flops(P->g_big) : 0.0;
+    ts->bytes = ts->big ? plan_bytes(P->g_big, (double)nvec * P->n, prec) : 0.0;
     hipEventRecord(ts->e[0], s);
   }
   // (the coupling and reduction GEMMs always run in FP64)
@@ -1286,6 +1324,7 @@ void timing_harvest(ccgf_ctx *c) {
         c->t_big_ms += a;
         c->t_big_launches += 1;
         c->t_big_flops += r.flops;
+        c->t_big_bytes += r.bytes;
       }
     }
     r.pending = false;

@@ -77,3 +77,64 @@ def test_e_vectors_with_independent_lambda_match_bruteforce(no, nv, seed):
             # b does not depend on Lambda; e does
             assert np.allclose(E.b_vector(part, 0, p), E0.b_vector(part, 0, p), atol=0)
         assert max(np.abs(E.e_vector(part, 0, p) - E0.e_vector(part, 0, p)).max() for p in range(n)) > 1e-3
+
+
+def _zeroed(E, names):
+    """A shallow copy of E whose listed H-bar blocks are zero."""
+    import copy
+    Z = copy.copy(E)
+    for nm in names:
+        setattr(Z, nm, getattr(E, nm).like())
+    return Z
+
+
+def _abs_copy(E, names):
+    import copy
+    A = copy.copy(E)
+    for nm in names:
+        t = getattr(E, nm)
+        setattr(A, nm, t.like(np.abs(t.data) + 0j))
+    return A
+
+
+# the H-bar blocks that the reduced-precision products hold, per part
+_REDUCED = {"ea": ("Wvvvv", "Wovvo", "Fvv"), "ip": ("Woooo", "Wovvo")}
+_ALL = ("Foo", "Fov", "Fvv", "Woooo", "Wvvvv", "Wovvo", "Wooov", "Wovoo", "Wvovv", "Wvvvo", "Woovv")
+
+
+@pytest.mark.parametrize("part", ["ip", "ea"])
+def test_reduced_terms_abs_bounds_and_matches_the_terms(part):
+    """reduced_terms_abs is the |operand| |r| sum of exactly the sigma terms that hold the
+    reduced-precision blocks: (1) it bounds those terms (sigma minus sigma with the blocks
+    zeroed) elementwise; (2) with every block and r replaced by their absolute values it
+    equals them where the antisymmetriser adds nothing (the W_abcd / W_mnij term alone),
+    and (3) its exchange part splits into a term and its (a, b) / (i, j) image."""
+    s = synth.make_system((3, 1, 1), 2, 4, seed=21, t1_std=0.1, t2_std=0.1, eri_std=0.2)
+    E = eom.EOMSystem(s)
+    rng = np.random.default_rng(4)
+    n1 = E.no if part == "ip" else E.nv
+    for K in range(E.nk):
+        nu = len(E.unique_index(part, K)[0])
+        x = E.unpack(part, K, rng.normal(size=nu) + 1j * rng.normal(size=nu))
+        B = E.reduced_terms_abs(part, K, x)
+        assert np.all(B[:n1] == 0) and np.all(B >= 0)
+        d = E.sigma(part, K, x) - _zeroed(E, _REDUCED[part]).sigma(part, K, x)
+        assert np.all(np.abs(d[n1:]) <= B[n1:] * (1 + 1e-12) + 1e-15)
+        # (2) the pair-pair term alone, all blocks non-negative
+        A = _abs_copy(E, _ALL)
+        xa = np.abs(x) + 0j
+        big, exch = _REDUCED[part][0], _REDUCED[part][1:]
+        Ab = _zeroed(A, exch)
+        d2 = Ab.sigma(part, K, xa) - _zeroed(Ab, (big,)).sigma(part, K, xa)
+        B2 = Ab.reduced_terms_abs(part, K, xa)
+        assert np.allclose(d2[n1:].real, B2[n1:], rtol=1e-12, atol=1e-14) and B2[n1:].max() > 0
+        # (3) the exchange terms alone: sigma gives X - P(X), the bound X + P(X)
+        Ax = _zeroed(A, (big,))
+        d3 = (Ax.sigma(part, K, xa) - _zeroed(Ax, exch).sigma(part, K, xa)).real
+        B3 = Ax.reduced_terms_abs(part, K, xa)
+        X, PX = 0.5 * (B3 + d3), 0.5 * (B3 - d3)
+        spec = "iab->iba" if part == "ea" else "ija->jia"
+        _, x2 = E.split(part, K, X + 0j)
+        px = eom.permute(spec, x2)
+        assert np.allclose(px.data.real.ravel(), PX[n1:], rtol=1e-12, atol=1e-14)
+        assert np.all(X[n1:] >= -1e-14) and X[n1:].max() > 0

@@ -11,8 +11,9 @@ successive steps spread over the grid and over the orbitals (10 points per
 step; the three groups hold 2, 1 and 1 occupied orbitals).
 
 Forms:
-  * the headline form (default ``learned_mixed_f32``): FP32 sigma products with
-    FP64 refinement, starting each solve from the guess of a network trained
+  * the headline form (default ``learned_mixed_bf16x3``): sigma products from
+    BF16-split operands (hi + lo, three BF16 MFMA products per real product,
+    FP32 accumulation) with FP64 refinement, starting each solve from the guess of a network trained
     (outside the timed region, reported) on plain solves of all orbitals at the
     frequencies of the first --ntrain warmup steps (those solves are the
     warmup's work for those steps), and giving each solve the preconditioner
@@ -48,6 +49,7 @@ if ROOT not in sys.path:
 
 METRIC = "G(ω) points/sec at 1e-6 rel. error, learned+mixed vs plain FP64; MFMA util"
 PEAK = {"f64": 78.6e12, "f32": 157.3e12, "bf16x3": 2.5e15}
+HBM_PEAK = 8.0e12
 GEMM_NAME = {"f64": "k_cgemm<0, double>", "f32": "k_cgemm<0, float>", "bf16x3": "k_cgemm_b3<0>"}
 DTYPE = {"f64": "c128", "f32": "c64 sigma / c128 Krylov", "bf16x3": "bf16x3 sigma / c128 Krylov"}
 TARGET = 1e-6
@@ -63,7 +65,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="si_k333")
-    ap.add_argument("--form", default="learned_mixed_f32",
+    ap.add_argument("--form", default="learned_mixed_bf16x3",
                     help="headline form: [learned_]mixed_f32, [learned_]mixed_bf16x3 or plain_f64")
     ap.add_argument("--compare-steps", type=int, default=2,
                     help="timed steps also solved by plain FP64, by the headline without its network and "
@@ -81,9 +83,11 @@ def parse():
     ap.add_argument("--budget-s", type=float, default=430.0,
                     help="wall-clock budget: optional legs are skipped when they would exceed it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--probe", choices=["sigma", "copy"], default=None,
+    ap.add_argument("--probe", choices=["sigma", "ortho", "copy"], default=None,
                     help="counter-collection runs: 'sigma' applies 6 EA and 6 IP sigma products to a batch of "
-                         "--batch vectors; 'copy' copies a 1 GiB buffer once (HBM-traffic calibration)")
+                         "--batch vectors; 'ortho' runs one GMRES cycle of --probe-steps steps for ten EA "
+                         "right-hand sides (prints the Gram-Schmidt kernels' algorithmic bytes); 'copy' copies "
+                         "a 1 GiB buffer once (HBM-traffic calibration)")
     ap.add_argument("--probe-precision", default="f32")
     return ap.parse_args()
 
@@ -93,11 +97,11 @@ def form_precision(form):
 
 
 def kernel_source_sha():
-    """SHA-256 of the source of the sigma GEMM kernels (k_cgemm and its tile body, from
-    the MFMA arithmetic helpers to the BF16-split variant)."""
+    """SHA-256 of the source of the sigma GEMM kernels (k_cgemm, k_cgemm_b3 and their tile
+    bodies, from the MFMA arithmetic helpers to the launch helpers)."""
     src = open(os.path.join(ROOT, "paper_2208_07478_amd", "csrc", "sigma.hip")).read()
     a = src.index("// Real arithmetic of one GEMM variant")
-    b = src.index("// BF16-split variant of the same product")
+    b = src.index("template <int TAG, typename R, int TNT>\nstatic void launch_t(")
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
@@ -234,6 +238,25 @@ def main():
     opts = dict(tol=args.tol, restart_m=args.restart, maxiter=args.maxiter, max_batch=args.batch,
                 precond_eta=args.precond_eta)
     log(f"{args.workload}: {sysm.kmesh}, {sysm.nocc}+{sysm.nvir}")
+    if args.probe == "ortho":
+        # one cycle of L steps for B slots, no second Gram-Schmidt pass: per step j the basis
+        # is read twice over its j + 1 vectors (k_dots, k_sub_proj), and these two kernels
+        # read w four times (two norms, the dot, the update) and write it once
+        L, B = max(args.probe_steps, 1), 10
+        ctx = Context(sysm, precision=args.probe_precision, tol=1e-300, restart_m=L, maxiter=L, max_batch=B,
+                      precond_eta=args.precond_eta, reorth_ratio=1e-30)
+        ctx.solve([0], orbs[:B], [wstep[0]], eta, parts="ea", allow_noconv=True)
+        torch.cuda.synchronize()
+        ctx.close()
+        nk, no, nv = int(np.prod(sysm.kmesh)), sysm.nocc, sysm.nvir
+        nb = nv + no * (nk * nk * nv * nv - nk * nv) // 2   # unique EA amplitudes at any K
+        eb = 16 if args.probe_precision == "f64" else 8     # basis element bytes
+        basis = B * nb * eb * L * (L + 1)                   # both passes over the basis, all steps
+        wvec = B * nb * 16 * 5 * L
+        print(json.dumps({"probe": "ortho", "slots": B, "steps": L, "unique_len": nb, "basis_elem_bytes": eb,
+                          "precision": args.probe_precision, "basis_bytes": basis, "w_bytes": wvec,
+                          "algorithmic_bytes": basis + wvec}))
+        return
     if args.probe == "sigma":
         ctx = Context(sysm, precision=args.probe_precision, graphs=False, **opts)
         for part in ("ea", "ip"):
@@ -248,8 +271,8 @@ def main():
 
     def run_steps(ctx, steps, tag):
         """Solve the listed steps; returns (G [len(steps)][10], seconds, totals)."""
-        tot = {"big_ms": 0.0, "big_launches": 0, "big_flops": 0.0, "n_iterations": 0, "n_solves": 0,
-               "n_unconverged": 0, "n_sigma_ea": 0, "n_sigma_ip": 0, "n_guess": 0, "n_guess_rejected": 0,
+        tot = {"big_ms": 0.0, "big_launches": 0, "big_flops": 0.0, "big_bytes": 0.0, "n_iterations": 0,
+               "n_solves": 0, "n_unconverged": 0, "n_sigma_ea": 0, "n_sigma_ip": 0, "n_guess": 0, "n_guess_rejected": 0,
                "max_rel_residual": 0.0}
         Gs, secs = [], []
         for s in steps:
@@ -260,8 +283,8 @@ def main():
             secs.append(time.perf_counter() - t)
             Gs.append((Gm + Gp)[0, :, 0])
             for st in (sti, ste):
-                for k in ("big_ms", "big_launches", "big_flops", "n_iterations", "n_solves", "n_unconverged",
-                          "n_guess", "n_guess_rejected"):
+                for k in ("big_ms", "big_launches", "big_flops", "big_bytes", "n_iterations", "n_solves",
+                          "n_unconverged", "n_guess", "n_guess_rejected"):
                     tot[k] += st[k]
                 tot["max_rel_residual"] = max(tot["max_rel_residual"], st["max_rel_residual"])
             tot["n_sigma_ip"] += sti["n_sigma"]
@@ -286,11 +309,14 @@ def main():
         # path's first solves build their own plans)
         nwarm_plain = max(1, min(args.ntrain, args.warmup - 1 if args.warmup > 1 else 1))
         wtrain = sorted(set(wstep[:nwarm_plain]))
-        t1 = time.perf_counter()
-        learn = ctx.learn(0, orbs, wtrain, eta, probe=args.probe_steps, allow_noconv=True)
-        learn["seconds"] = time.perf_counter() - t1
-        learn["omega_train"] = wtrain
-        log(f"{form}: training at {len(wtrain)} frequencies {learn['seconds']:.1f} s")
+        learn = {"omega_train": wtrain, "seconds": 0.0}
+        for part in ("ip", "ea"):  # (one part per call: each prints when it is done)
+            t1 = time.perf_counter()
+            ls = ctx.learn(0, orbs, wtrain, eta, parts=part, probe=args.probe_steps, allow_noconv=True)
+            ls["seconds"] = time.perf_counter() - t1
+            learn[part] = ls
+            learn["seconds"] += ls["seconds"]
+            log(f"{form}: {part} networks trained at {len(wtrain)} frequencies in {ls['seconds']:.1f} s")
     run_steps(ctx, range(nwarm_plain, args.warmup), f"{form} warmup")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -352,9 +378,19 @@ def main():
         acc["max_rel_err"] = {k: pointwise_err(v, ref["G"]) for k, v in cmp_G.items()}
     meets = ref is not None and acc["max_rel_err"][form] <= TARGET and tot["n_unconverged"] == 0
     acc["meets_target"] = meets
-    roof = {"bound": "mfma", "kernel": GEMM_NAME[prec] + " (EA 1/2 W_abcd r_i^cd over the stored blocks ka < kb)",
-            "achieved": ach / 1e12, "peak": PEAK[prec] / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK[prec],
-            "avg_ms": avg_ms, "flops_per_launch": fl, "launches": tot["big_launches"]}
+    # the kernel's bound: its algorithmic flops at the matrix peak of its dtype against its
+    # algorithmic bytes (W blocks, vector copy and output once) at the HBM peak, per launch
+    by = tot["big_bytes"] / max(tot["big_launches"], 1)
+    hbm_bound = by / HBM_PEAK > fl / PEAK[prec]
+    kname = GEMM_NAME[prec] + " (EA 1/2 W_abcd r_i^cd over the stored blocks ka < kb)"
+    if hbm_bound:
+        achb = by / (avg_ms * 1e-3) if avg_ms > 0 else 0.0
+        roof = {"bound": "hbm", "kernel": kname, "achieved": achb / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": achb / HBM_PEAK, "flops_achieved_tflops": ach / 1e12}
+    else:
+        roof = {"bound": "mfma", "kernel": kname, "achieved": ach / 1e12, "peak": PEAK[prec] / 1e12,
+                "unit": "TFLOP/s", "frac": ach / PEAK[prec]}
+    roof.update({"avg_ms": avg_ms, "flops_per_launch": fl, "bytes_per_launch": by, "launches": tot["big_launches"]})
     tr = stored_traffic(GEMM_NAME[prec])
     roof["traffic"] = tr["bytes_per_launch"] if tr else None
     speed = None

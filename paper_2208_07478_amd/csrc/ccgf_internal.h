@@ -134,6 +134,7 @@ struct GemmPlan {
   int tn[3] = {0, 0, 0};        // N tile width picked by the autotuner per precision (0: not yet)
   int trials[3] = {0, 0, 0};    // timed trial launches so far
   float tms[3][3] = {};         // their times (64-wide, 32-wide, 128-wide)
+  bool pairs = false;           // k pairs (2k, 2k + 1) adjacent and 16-byte aligned in A and B
   int ntask;
   GemmTask *d_tasks;
   GemmSeg *d_segs;

@@ -14,6 +14,7 @@
 #include "ccgf_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -126,12 +127,19 @@ __device__ __forceinline__ void cgemm_tile(const GemmShape &sh, const GemmTask &
     const AE *Ap = A + sg.a_off + (kok ? imap(sh.ak, k) : 0);
     const AE *Bp = B + sg.b_off + (kok ? imap(sh.bk, k) : 0);
     const R w = (R)sg.w;  // 1 or 1/2: exact in either precision
+    // unconditional loads (an element outside the operand reads the operand's first one
+    // instead and is zeroed after the load): no branch around each load
 #pragma unroll
-    for (int j = 0; j < AJ; ++j) ra[j] = (aok[j] && kok) ? Ap[aoff[j]] : AE{0, 0};
+    for (int j = 0; j < AJ; ++j) {
+      const bool ok = aok[j] && kok;
+      const AE a = *(ok ? Ap + aoff[j] : A);
+      ra[j] = ok ? a : AE{0, 0};
+    }
 #pragma unroll
     for (int j = 0; j < NBJ; ++j) {
-      const AE b = (bok[j] && kok) ? Bp[boff[j]] : AE{0, 0};
-      rb[j] = AE{b.x * w, b.y * w};
+      const bool ok = bok[j] && kok;
+      const AE b = *(ok ? Bp + boff[j] : B);
+      rb[j] = ok ? AE{b.x * w, b.y * w} : AE{0, 0};
     }
   };
 
@@ -261,22 +269,35 @@ __global__ __launch_bounds__(256, TNT <= 48 ? 4 : 2) void k_cgemm_group(const Ge
 // inner loop.  Lane l feeds row (or column) l%16 and k = 8(l/16) .. +7; item v of
 // lane l is row 4(l/16)+v.  Tiles and staging follow cgemm_tile, with k-slabs of 32.
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+// the two bf16 values packed in a 32-bit word (low half first), each times w; exact for
+// w = 1/2 on normal values (the bf16 bits sit in the top half of an FP32 word)
+__device__ inline unsigned scale_bf2(unsigned x, float w) {
+  const float lo = __uint_as_float(x << 16) * w, hi = __uint_as_float(x & 0xffff0000u) * w;
+  return (__float_as_uint(lo) >> 16) | (__float_as_uint(hi) & 0xffff0000u);
+}
+__device__ inline __bf16 bf_lo(unsigned x) { return __builtin_bit_cast(__bf16, (unsigned short)(x & 0xffffu)); }
+__device__ inline __bf16 bf_hi(unsigned x) { return __builtin_bit_cast(__bf16, (unsigned short)(x >> 16)); }
 
-template <int TAG, int TNT>
+// PAIR: each thread stages the k pair (2 kt, 2 kt + 1) of its rows with one 16-byte load
+// and writes each plane's two values with one 4-byte LDS store (for operands whose k pairs
+// are adjacent and 16-byte aligned, GemmPlan::pairs); else one element and four 2-byte stores.
+template <int TAG, int TNT, bool PAIR>
 __device__ __forceinline__ void cgemm_b3_tile(const GemmShape &sh, const GemmTask &task,
                                               const GemmSeg *__restrict__ segs, const B3E *__restrict__ A,
                                               const B3E *__restrict__ B, cplx *__restrict__ C, int tm, int tn) {
   constexpr int KS = 32, LD = KS + 8;  // k-slab; LDS row stride in bf16 (rows stay 16-byte aligned)
-  constexpr int RPP = 256 / KS;        // rows staged per pass of the block
+  constexpr int KP = PAIR ? 2 : 1;     // k per thread
+  constexpr int RPP = 256 * KP / KS;   // rows staged per pass of the block
   constexpr int AJ = TM / RPP;         // A rows staged per thread
   constexpr int NBJ = TNT / RPP;       // B rows staged per thread
+  static_assert(NBJ >= 1, "tile narrower than a staging pass");
   constexpr bool NARROW = TNT <= 48;
   constexpr int AM = NARROW ? 1 : 2;                // MFMA row tiles per wave
   constexpr int BN = NARROW ? TNT / 16 : TNT / 32;  // MFMA column tiles per wave
   __shared__ __attribute__((aligned(16))) __bf16 As[4][TM][LD];
   __shared__ __attribute__((aligned(16))) __bf16 Bs[4][TNT][LD];
   const int tid = threadIdx.x;
-  const int kt = tid & (KS - 1), rt = tid / KS;
+  const int kt = tid & (KS / KP - 1), rt = tid / (KS / KP);
   long long aoff[AJ], boff[NBJ];
   bool aok[AJ], bok[NBJ];
 #pragma unroll
@@ -302,29 +323,59 @@ __device__ __forceinline__ void cgemm_b3_tile(const GemmShape &sh, const GemmTas
       Pii[a][b] = (v4f){0, 0, 0, 0};
       Px[a][b] = (v4f){0, 0, 0, 0};
     }
-  B3E ra[AJ], rb[NBJ];
+  // staged values: KP elements (KP x 8 bytes) per row and thread
+  typedef typename std::conditional<PAIR, uint4, uint2>::type SV;
+  SV ra[AJ], rb[NBJ];
   auto load = [&](int step) {
     int s = step / ksteps;
-    int k = (step - s * ksteps) * KS + kt;
+    int k = (step - s * ksteps) * KS + KP * kt;
     GemmSeg sg = segs[task.seg_begin + s];
-    const bool kok = k < sh.K;
+    const bool kok = k < sh.K;  // (with PAIR, K is even: k + 1 < K too)
     if (kok && sh.ktab) k = sh.ktab[k];
     const B3E *Ap = A + sg.a_off + (kok ? imap(sh.ak, k) : 0);
     const B3E *Bp = B + sg.b_off + (kok ? imap(sh.bk, k) : 0);
-    const B3E z{0, 0, 0, 0};
+    // unconditional loads (an element outside the operand reads the operand's first one
+    // instead and is zeroed after the load): no branch around each load
+    const SV z{};
 #pragma unroll
-    for (int j = 0; j < AJ; ++j) ra[j] = (aok[j] && kok) ? Ap[aoff[j]] : z;
+    for (int j = 0; j < AJ; ++j) {
+      const bool ok = aok[j] && kok;
+      const SV v = *(const SV *)(ok ? Ap + aoff[j] : A);
+      ra[j] = ok ? v : z;
+    }
 #pragma unroll
-    for (int j = 0; j < NBJ; ++j) rb[j] = (bok[j] && kok) ? Bp[boff[j]] : z;
-    if (sg.w != 1.0) {  // 1/2 (self-paired segments): exact on each part
+    for (int j = 0; j < NBJ; ++j) {
+      const bool ok = bok[j] && kok;
+      const SV v = *(const SV *)(ok ? Bp + boff[j] : B);
+      rb[j] = ok ? v : z;
+    }
+    if (sg.w != 1.0) {  // 1/2 (self-paired segments): exact on each bf16 value
       const float w = (float)sg.w;
 #pragma unroll
       for (int j = 0; j < NBJ; ++j) {
-        rb[j].rh = (__bf16)((float)rb[j].rh * w);
-        rb[j].rl = (__bf16)((float)rb[j].rl * w);
-        rb[j].ih = (__bf16)((float)rb[j].ih * w);
-        rb[j].il = (__bf16)((float)rb[j].il * w);
+        rb[j].x = scale_bf2(rb[j].x, w);
+        rb[j].y = scale_bf2(rb[j].y, w);
+        if constexpr (PAIR) {
+          rb[j].z = scale_bf2(rb[j].z, w);
+          rb[j].w = scale_bf2(rb[j].w, w);
+        }
       }
+    }
+  };
+  // one thread's staged values into the four planes of rows r (element e of the pair: word
+  // 2 e holds (re hi, re lo), word 2 e + 1 (im hi, im lo), low half first)
+  auto stage = [&](auto &P, int r, const SV &v) {
+    if constexpr (PAIR) {
+      const unsigned w0 = v.x, w1 = v.y, w2 = v.z, w3 = v.w;
+      *(unsigned *)&P[0][r][2 * kt] = (w0 & 0xffffu) | (w2 << 16);
+      *(unsigned *)&P[1][r][2 * kt] = (w0 >> 16) | (w2 & 0xffff0000u);
+      *(unsigned *)&P[2][r][2 * kt] = (w1 & 0xffffu) | (w3 << 16);
+      *(unsigned *)&P[3][r][2 * kt] = (w1 >> 16) | (w3 & 0xffff0000u);
+    } else {
+      P[0][r][kt] = bf_lo(v.x);
+      P[1][r][kt] = bf_hi(v.x);
+      P[2][r][kt] = bf_lo(v.y);
+      P[3][r][kt] = bf_hi(v.y);
     }
   };
   const int wave = tid >> 6, lane = tid & 63;
@@ -335,21 +386,9 @@ __device__ __forceinline__ void cgemm_b3_tile(const GemmShape &sh, const GemmTas
   for (int step = 0; step < nsteps; ++step) {
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < AJ; ++j) {
-      const int r = rt + RPP * j;
-      As[0][r][kt] = ra[j].rh;
-      As[1][r][kt] = ra[j].rl;
-      As[2][r][kt] = ra[j].ih;
-      As[3][r][kt] = ra[j].il;
-    }
+    for (int j = 0; j < AJ; ++j) stage(As, rt + RPP * j, ra[j]);
 #pragma unroll
-    for (int j = 0; j < NBJ; ++j) {
-      const int r = rt + RPP * j;
-      Bs[0][r][kt] = rb[j].rh;
-      Bs[1][r][kt] = rb[j].rl;
-      Bs[2][r][kt] = rb[j].ih;
-      Bs[3][r][kt] = rb[j].il;
-    }
+    for (int j = 0; j < NBJ; ++j) stage(Bs, rt + RPP * j, rb[j]);
     __syncthreads();
     if (step + 1 < nsteps) load(step + 1);
     v8bf fa[AM][4];
@@ -399,7 +438,7 @@ __device__ __forceinline__ void cgemm_b3_tile(const GemmShape &sh, const GemmTas
       }
 }
 
-template <int TAG, int TNT>
+template <int TAG, int TNT, bool PAIR>
 __global__ __launch_bounds__(256, 2) void k_cgemm_b3(GemmShape sh, const GemmTask *__restrict__ tasks,
                                                      const GemmSeg *__restrict__ segs, const B3E *__restrict__ A,
                                                      const B3E *__restrict__ B, cplx *__restrict__ C, int tilesM,
@@ -407,7 +446,7 @@ __global__ __launch_bounds__(256, 2) void k_cgemm_b3(GemmShape sh, const GemmTas
   const int bid = xcd_block(total);
   const int per_task = tilesM * tilesN;
   const int t = bid / per_task, r = bid % per_task;
-  cgemm_b3_tile<TAG, TNT>(sh, tasks[t], segs, A, B, C, r / tilesN, r % tilesN);
+  cgemm_b3_tile<TAG, TNT, PAIR>(sh, tasks[t], segs, A, B, C, r / tilesN, r % tilesN);
 }
 
 template <int TAG, int TNT>
@@ -415,8 +454,12 @@ static void launch_b3t(const GemmPlan &plan, const void *A, const void *B, cplx 
   const GemmShape &sh = plan.shape;
   const int tilesM = (sh.M + TM - 1) / TM, tilesN = (sh.N + TNT - 1) / TNT;
   const long long total = (long long)plan.ntask * tilesM * tilesN;
-  hipLaunchKernelGGL((k_cgemm_b3<TAG, TNT>), dim3((unsigned)total), dim3(256), 0, s, sh, plan.d_tasks, plan.d_segs,
-                     (const B3E *)A, (const B3E *)B, C, tilesM, tilesN, (int)total);
+  if (plan.pairs)
+    hipLaunchKernelGGL((k_cgemm_b3<TAG, TNT, true>), dim3((unsigned)total), dim3(256), 0, s, sh, plan.d_tasks,
+                       plan.d_segs, (const B3E *)A, (const B3E *)B, C, tilesM, tilesN, (int)total);
+  else
+    hipLaunchKernelGGL((k_cgemm_b3<TAG, TNT, false>), dim3((unsigned)total), dim3(256), 0, s, sh, plan.d_tasks,
+                       plan.d_segs, (const B3E *)A, (const B3E *)B, C, tilesM, tilesN, (int)total);
 }
 template <int TAG>
 static void launch_b3(const GemmPlan &plan, const void *A, const void *B, cplx *C, hipStream_t s, int tn) {
@@ -466,16 +509,16 @@ void gemm_launch(int tag, const GemmPlan &plan, const void *A, const void *B, cp
   switch (tag) {
     CASE(0) CASE(1) CASE(2) CASE(3) CASE(8) CASE(9)
     case 4:
-      launch_w<4, double>(plan, A, B, C, s, tn);
+      launch_wn<4, double>(plan, A, B, C, s, tn);
       break;
     case 6:
-      launch_w<6, double>(plan, A, B, C, s, tn);
+      launch_wn<6, double>(plan, A, B, C, s, tn);
       break;
     case 7:
-      launch_w<7, double>(plan, A, B, C, s, tn);
+      launch_wn<7, double>(plan, A, B, C, s, tn);
       break;
     default:
-      launch_w<5, double>(plan, A, B, C, s, tn);
+      launch_wn<5, double>(plan, A, B, C, s, tn);
   }
 #undef CASE
 }
@@ -492,7 +535,22 @@ static double plan_bytes(const GemmPlan &p, double nx, int prec) {
   return ea * ((double)p.segs.size() * p.shape.M * p.shape.K + nx) + 16.0 * (double)p.ntask * p.shape.M * p.shape.N;
 }
 
+// k pairs (2k, 2k + 1) adjacent under an index map with even offsets for even k
+static bool map_pairs(const IdxMap &m, int ext) {
+  if (m.s1 != 1) return false;
+  return m.L >= ext || (m.L % 2 == 0 && m.s0 % 2 == 0);
+}
+// every offset of an index map even
+static bool offs_even(const IdxMap &m, int ext) { return m.s1 % 2 == 0 && (m.L >= ext || m.s0 % 2 == 0); }
+
 void plan_upload(ccgf_ctx *c, GemmPlan &p) {
+  {  // can the BF16-split GEMM stage this plan's operands two k at a time (16-byte aligned pairs)?
+    const GemmShape &sh = p.shape;
+    bool ok = !sh.ktab && !sh.mtab && sh.K % 2 == 0 && map_pairs(sh.ak, sh.K) && map_pairs(sh.bk, sh.K) &&
+              offs_even(sh.am, sh.M) && offs_even(sh.bn, sh.N);
+    for (const GemmSeg &g : p.segs) ok = ok && g.a_off % 2 == 0 && g.b_off % 2 == 0;
+    p.pairs = ok;
+  }
   p.ntask = (int)p.tasks.size();
   p.d_tasks = (GemmTask *)dev_alloc(c, sizeof(GemmTask) * std::max<size_t>(1, p.tasks.size()));
   p.d_segs = (GemmSeg *)dev_alloc(c, sizeof(GemmSeg) * std::max<size_t>(1, p.segs.size()));
@@ -969,19 +1027,18 @@ __global__ __launch_bounds__(256) void k_ip_local(int nk, int no, int nv, int K,
   }
 }
 
-// Launch a plan with the N tile width the autotuner picked for its shape.  The big
-// products of narrow batches (N <= 48) take the narrowest tile that holds N without
-// trials.  Otherwise the first two launches of an unseen shape are timed trials of the 64- and 32-wide
+// Launch a plan with the N tile width the autotuner picked for its shape.  Products of
+// narrow batches (N <= 48) take the narrowest tile that holds N without trials.  Otherwise the first two launches of an unseen shape are timed trials of the 64- and 32-wide
 // variants (each does the real work); the 32-wide one is kept only if it is at
 // least 5% faster.  Choices are cached per shape in the context (and in the
 // autotune file when one is configured).
 static int tuned_launch(ccgf_ctx *c, int tag, GemmPlan &p, const void *A, const void *B, cplx *C, hipStream_t s,
                         int prec) {
   if (p.tn[prec] == 0 && c->opt.autotune < 0) p.tn[prec] = 64;
-  // narrow batches of the big products (N <= 48): the narrowest tile that holds N, where the
-  // MFMA work is least padding (the W operand is streamed once either way)
-  const bool big = tag <= 3 || tag == 8 || tag == 9;
-  if (p.tn[prec] == 0 && big && p.shape.N <= 48) p.tn[prec] = 16 * ((p.shape.N + 15) / 16);
+  // narrow batches (N <= 48): the narrowest tile that holds N, where the MFMA work is least
+  // padding (the A operand is streamed once either way); for the couplings and split-K rows
+  // N is the number of vectors itself
+  if (p.tn[prec] == 0 && p.shape.N <= 48) p.tn[prec] = 16 * ((p.shape.N + 15) / 16);
   if (p.tn[prec] == 0) {
     char key[160];
     std::snprintf(key, sizeof key, "t%d p%d M%d N%d K%d s%zu n%d", tag, prec, p.shape.M, p.shape.N, p.shape.K,
@@ -1462,7 +1519,7 @@ int sigma_group(int nsys, ccgf_ctx *const *ctxs, const int *parts, const int *Ks
     const bool big = tag <= 3 || tag == 8 || tag == 9;
     int maxN = 0;
     for (const Item &it : t.second) maxN = std::max(maxN, it.plan->shape.N);
-    const int tn = big ? (maxN <= 16 ? 16 : maxN <= 32 ? 32 : 64) : 32;
+    const int tn = maxN <= 16 ? 16 : maxN <= 32 ? 32 : big ? 64 : 32;
     GroupLaunch L{tag, tn, big ? prec : 0, shapes.size(), tasks.size(), segs.size(), 0, 0};
     int tile = 0;
     for (const Item &it : t.second) {

@@ -250,7 +250,7 @@ def main():
         ctx.close()
         nk, no, nv = int(np.prod(sysm.kmesh)), sysm.nocc, sysm.nvir
         nb = nv + no * (nk * nk * nv * nv - nk * nv) // 2   # unique EA amplitudes at any K
-        eb = 16 if args.probe_precision == "f64" else 8     # basis element bytes
+        eb = 16                                             # basis element bytes (complex double)
         basis = B * nb * eb * L * (L + 1)                   # both passes over the basis, all steps
         wvec = B * nb * 16 * 5 * L
         print(json.dumps({"probe": "ortho", "slots": B, "steps": L, "unique_len": nb, "basis_elem_bytes": eb,

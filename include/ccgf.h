@@ -80,8 +80,9 @@ typedef struct {
   const double *eps;         /* real [nk][nmo]: Fock diagonal (f_ov = 0) */
   const double *foo;         /* optional complex [nk][nocc][nocc]; NULL -> diag(eps) */
   const double *fvv;         /* optional complex [nk][nvir][nvir]; NULL -> diag(eps) */
-  int naux;                  /* factor rank per k-pair, >= 1 */
-  const double *eri_factor;  /* complex [nk][nk][naux][nmo][nmo] (see header comment) */
+  int naux;                  /* factor rank per k-pair, >= 1 (with eri_factor) */
+  const double *eri_factor;  /* complex [nk][nk][naux][nmo][nmo] (see header comment); or NULL and
+                                eri_blocks given */
   const double *t1;          /* complex [nk][nocc][nvir] */
   const double *t2;          /* complex [nk][nk][nk][nocc][nocc][nvir][nvir] */
   int mem_space;             /* CCGF_HOST or CCGF_DEVICE */
@@ -92,6 +93,12 @@ typedef struct {
    * left vectors e of Eq. 7. */
   const double *l1;
   const double *l2;
+  /* Alternative to eri_factor for small systems: the physicists' integrals as dense
+   * momentum blocks, complex [k1][k2][k3][nmo][nmo][nmo][nmo] = <p k1, q k2 | r k3, s k4>
+   * with k4 = k1 + k2 - k3, in the factor's normalisation.  Exactly one of eri_factor
+   * and eri_blocks is given.  Checked on the host (CCGF_EINVAL): <pq|rs> = conj(<rs|pq>)
+   * and <pq|rs> = <qp|sr> to 1e-10 of the largest element. */
+  const double *eri_blocks;
 } ccgf_system;
 
 typedef struct {
@@ -282,6 +289,19 @@ int cc_gf_set_options(ccgf_ctx *ctx, const ccgf_options *opt);
  * both.  Every cc_gf_learn call sets both again. */
 enum { CCGF_LEARN_GUESS = 1, CCGF_LEARN_PRECOND = 2 };
 int cc_gf_learn_enable(ccgf_ctx *ctx, int on);
+
+/* Persist the networks trained by cc_gf_learn (all parts and momenta) to a file at
+ * path, and read them back into a context of the same system shape (k-mesh, nocc,
+ * nvir: CCGF_EINVAL otherwise).  The file holds, per (part, K), the two networks'
+ * parameters, their feature scales, the training frequencies and orbitals, and the
+ * guess network's reduced basis Q (norb x rank vectors of the part's length, so it can
+ * be gigabytes at large meshes).  Loading replaces every model of the context and
+ * enables both networks (cc_gf_learn_enable).  Save: CCGF_ESTATE when nothing is
+ * trained; I/O failures give CCGF_EINVAL with the reason in cc_gf_last_error.  The
+ * format is this library's own (a magic tag and version first); host memory for one
+ * model's basis is used as staging. */
+int cc_gf_learn_save(ccgf_ctx *ctx, const char *path);
+int cc_gf_learn_load(ccgf_ctx *ctx, const char *path);
 
 /* Least-squares loss and its gradient for the network above, for checking the
  * training kernels: theta, X [N][din], T [N][dout], grad [nparams] are HOST

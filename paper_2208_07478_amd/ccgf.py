@@ -25,7 +25,8 @@ PRECISIONS = {"f64": PLAIN_F64, "plain_f64": PLAIN_F64, "f32": MIXED_F32, "mixed
 
 EXPORTS = ("cc_gf_init", "cc_gf_solve", "cc_gf_solve_matrix", "cc_gf_mor", "cc_gf_vector_size", "cc_gf_sigma",
            "cc_gf_sigma_group", "cc_gf_vectors",
-           "cc_gf_learn", "cc_gf_learn_enable", "cc_gf_set_options", "cc_gf_mlp_grad", "cc_gf_dyson_cas",
+           "cc_gf_learn", "cc_gf_learn_enable", "cc_gf_learn_save", "cc_gf_learn_load", "cc_gf_set_options",
+           "cc_gf_mlp_grad", "cc_gf_dyson_cas",
            "cc_gf_dyson_cas_noalloc", "cc_gf_dyson_last_error", "cc_gf_free", "cc_gf_last_error")
 MOR_MAX = 32
 
@@ -35,7 +36,7 @@ class System(ctypes.Structure):
                 ("eps", ctypes.c_void_p), ("foo", ctypes.c_void_p), ("fvv", ctypes.c_void_p),
                 ("naux", ctypes.c_int), ("eri_factor", ctypes.c_void_p), ("t1", ctypes.c_void_p),
                 ("t2", ctypes.c_void_p), ("mem_space", ctypes.c_int), ("l1", ctypes.c_void_p),
-                ("l2", ctypes.c_void_p)]
+                ("l2", ctypes.c_void_p), ("eri_blocks", ctypes.c_void_p)]
 
 
 class Options(ctypes.Structure):
@@ -128,6 +129,9 @@ def load(path: str = LIB_PATH):
     lib.cc_gf_set_options.restype = ctypes.c_int
     lib.cc_gf_learn_enable.argtypes = [vp, ctypes.c_int]
     lib.cc_gf_learn_enable.restype = ctypes.c_int
+    for fn in (lib.cc_gf_learn_save, lib.cc_gf_learn_load):
+        fn.argtypes = [vp, ctypes.c_char_p]
+        fn.restype = ctypes.c_int
     fp = ctypes.POINTER(ctypes.c_float)
     lib.cc_gf_mlp_grad.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, fp, ctypes.c_int, fp, fp, fp,
                                    ctypes.POINTER(ctypes.c_double)]
@@ -163,7 +167,9 @@ class Context:
     def __init__(self, system, *, tol=1e-10, restart_m=30, maxiter=2000, max_batch=64, stream=None,
                  timing=False, foo=None, fvv=None, l1=None, l2=None, precond_eta=0.0, recycle_k=0, precision="f64",
                  reorth_ratio=0.0, autotune=True, autotune_cache=None, graphs=True, restart_tail=0,
-                 seed_m=0):
+                 seed_m=0, eri_blocks=None):
+        """eri_blocks: dense <pq|rs> blocks [k1][k2][k3][nmo]^4 to use instead of the system's
+        ERI factor (small systems)."""
         lib = load()
         import torch  # device memory and streams only
         self._torch = torch
@@ -171,21 +177,23 @@ class Context:
             stream = torch.cuda.current_stream()
         self.stream = stream
         s = system
-        self._keep = [np.ascontiguousarray(np.asarray(s.eps, dtype=np.float64)), _c128(s.eri_factor),
-                      _c128(s.t1), _c128(s.t2)]
+        self._keep = [np.ascontiguousarray(np.asarray(s.eps, dtype=np.float64)),
+                      None if eri_blocks is not None else _c128(s.eri_factor), _c128(s.t1), _c128(s.t2)]
+        blocks_a = None if eri_blocks is None else _c128(eri_blocks)
         foo_a = None if foo is None else _c128(foo)
         fvv_a = None if fvv is None else _c128(fvv)
         l1_a = None if l1 is None else _c128(l1)
         l2_a = None if l2 is None else _c128(l2)
-        self._keep += [foo_a, fvv_a, l1_a, l2_a]
+        self._keep += [foo_a, fvv_a, l1_a, l2_a, blocks_a]
         cs = System()
         cs.kmesh = (ctypes.c_int * 3)(*[int(x) for x in s.kmesh])
         cs.nocc, cs.nvir = int(s.nocc), int(s.nvir)
         cs.eps = self._keep[0].ctypes.data
         cs.foo = None if foo_a is None else foo_a.ctypes.data
         cs.fvv = None if fvv_a is None else fvv_a.ctypes.data
-        cs.naux = int(self._keep[1].shape[2])
-        cs.eri_factor = self._keep[1].ctypes.data
+        cs.naux = 0 if blocks_a is not None else int(self._keep[1].shape[2])
+        cs.eri_factor = None if blocks_a is not None else self._keep[1].ctypes.data
+        cs.eri_blocks = None if blocks_a is None else blocks_a.ctypes.data
         cs.t1 = self._keep[2].ctypes.data
         cs.t2 = self._keep[3].ctypes.data
         cs.mem_space = HOST
@@ -331,6 +339,14 @@ class Context:
         g = on if guess is None else guess
         p = on if precond is None else precond
         self._check(load().cc_gf_learn_enable(self._h, (1 if g else 0) | (2 if p else 0)))
+
+    def learn_save(self, path):
+        """Write the trained networks (every part and K) to path."""
+        self._check(load().cc_gf_learn_save(self._h, os.fsencode(path)))
+
+    def learn_load(self, path):
+        """Replace this context's networks by those saved at path (same system shape)."""
+        self._check(load().cc_gf_learn_load(self._h, os.fsencode(path)))
 
     def mor(self, kidx: Sequence[int], orbs: Sequence[int], wexp_ip, wexp_ea, omega, eta: float, parts="both",
             allow_noconv=False):

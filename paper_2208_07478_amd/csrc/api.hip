@@ -75,6 +75,31 @@ static int validate_host(ccgf_ctx *c, const ccgf_system *s) {
       return set_err(c, CCGF_EINVAL, std::string(name) + " is not antisymmetric under i<->j / a<->b (max deviation " +
                                          std::to_string(dev) + ")");
   }
+  if (!s->eri_factor) {  // dense blocks: <pq|rs> = conj(<rs|pq>) and <pq|rs> = <qp|sr>
+    const double *D = s->eri_blocks;
+    auto off = [&](int k1, int k2, int k3, int p, int q, int r, int t) {
+      return ((((((size_t)k1 * nk + k2) * nk + k3) * nmo + p) * nmo + q) * nmo + r) * nmo + t;
+    };
+    double amax = 0, dev = 0;
+    for (int k1 = 0; k1 < nk; ++k1)
+      for (int k2 = 0; k2 < nk; ++k2)
+        for (int k3 = 0; k3 < nk; ++k3) {
+          const int k4 = c->kc3_h[((size_t)k1 * nk + k2) * nk + k3];
+          for (int p = 0; p < nmo; ++p)
+            for (int q = 0; q < nmo; ++q)
+              for (int r = 0; r < nmo; ++r)
+                for (int t = 0; t < nmo; ++t) {
+                  const size_t o = off(k1, k2, k3, p, q, r, t), h = off(k3, k4, k1, r, t, p, q),
+                               x = off(k2, k1, k4, q, p, t, r);
+                  amax = std::fmax(amax, std::fabs(D[2 * o]) + std::fabs(D[2 * o + 1]));
+                  dev = std::fmax(dev, std::fabs(D[2 * o] - D[2 * h]) + std::fabs(D[2 * o + 1] + D[2 * h + 1]));
+                  dev = std::fmax(dev, std::fabs(D[2 * o] - D[2 * x]) + std::fabs(D[2 * o + 1] - D[2 * x + 1]));
+                }
+        }
+    if (dev > 1e-10 * std::fmax(amax, 1e-300) && dev > 0)
+      return set_err(c, CCGF_EINVAL, "eri_blocks violate <pq|rs> = conj(<rs|pq>) or <pq|rs> = <qp|sr>");
+    return CCGF_OK;
+  }
   const double *A = s->eri_factor;
   double amax = 0, dev = 0;
   for (int k1 = 0; k1 < nk; ++k1)
@@ -99,9 +124,10 @@ extern "C" int cc_gf_init(const ccgf_system *s, const ccgf_options *opt, ccgf_ct
   for (int d = 0; d < 3; ++d)
     if (s->kmesh[d] < 1) return set_err(nullptr, CCGF_EINVAL, "kmesh entries must be >= 1");
   if (s->nocc < 1 || s->nvir < 1) return set_err(nullptr, CCGF_EINVAL, "nocc and nvir must be >= 1");
-  if (s->naux < 1) return set_err(nullptr, CCGF_EINVAL, "naux must be >= 1");
-  if (!s->eps || !s->eri_factor || !s->t1 || !s->t2)
-    return set_err(nullptr, CCGF_EINVAL, "eps, eri_factor, t1 and t2 are required");
+  if ((s->eri_factor == nullptr) == (s->eri_blocks == nullptr))
+    return set_err(nullptr, CCGF_EINVAL, "give exactly one of eri_factor and eri_blocks");
+  if (s->eri_factor && s->naux < 1) return set_err(nullptr, CCGF_EINVAL, "naux must be >= 1");
+  if (!s->eps || !s->t1 || !s->t2) return set_err(nullptr, CCGF_EINVAL, "eps, t1 and t2 are required");
   if (s->mem_space != CCGF_HOST && s->mem_space != CCGF_DEVICE)
     return set_err(nullptr, CCGF_EINVAL, "mem_space must be CCGF_HOST or CCGF_DEVICE");
   if ((s->l1 == nullptr) != (s->l2 == nullptr))
@@ -131,7 +157,7 @@ extern "C" int cc_gf_init(const ccgf_system *s, const ccgf_options *opt, ccgf_ct
   c->no = s->nocc;
   c->nv = s->nvir;
   c->nmo = s->nocc + s->nvir;
-  c->naux = s->naux;
+  c->naux = s->eri_factor ? s->naux : 0;
   const int nk = c->nk, no = c->no, nv = c->nv, nmo = c->nmo;
   // momentum table k1 + k2 - k3
   c->kc3_h.resize((size_t)nk * nk * nk);
@@ -167,6 +193,7 @@ extern "C" int cc_gf_init(const ccgf_system *s, const ccgf_options *opt, ccgf_ct
   };
   size_t n_t1 = (size_t)nk * no * nv, n_t2 = (size_t)nk * nk * nk * no * no * nv * nv;
   size_t n_fac = (size_t)nk * nk * c->naux * nmo * nmo;
+  size_t n_dense = (size_t)nk * nk * nk * nmo * nmo * nmo * nmo;
   c->kc3 = (int *)dev_alloc(c, sizeof(int) * c->kc3_h.size());
   if (c->kc3) hipMemcpy(c->kc3, c->kc3_h.data(), sizeof(int) * c->kc3_h.size(), hipMemcpyHostToDevice);
   c->t1 = upload(s->t1, sizeof(cplx) * n_t1);
@@ -177,7 +204,8 @@ extern "C" int cc_gf_init(const ccgf_system *s, const ccgf_options *opt, ccgf_ct
     c->l2 = upload(s->l2, sizeof(cplx) * n_t2);
     lam_ok = c->l1 && c->l2;
   }
-  c->fac = upload(s->eri_factor, sizeof(cplx) * n_fac);
+  if (s->eri_factor) c->fac = upload(s->eri_factor, sizeof(cplx) * n_fac);
+  else c->eri_dense = upload(s->eri_blocks, sizeof(cplx) * n_dense);
   // Fock blocks: given, or diag(eps)
   std::vector<cplx> hfoo((size_t)nk * no * no, mkc(0, 0)), hfvv((size_t)nk * nv * nv, mkc(0, 0));
   std::vector<double> heps((size_t)nk * nmo);
@@ -195,7 +223,7 @@ extern "C" int cc_gf_init(const ccgf_system *s, const ccgf_options *opt, ccgf_ct
     if (s->fvv) hipMemcpy(c->fvv, s->fvv, sizeof(cplx) * hfvv.size(), kind);
     else hipMemcpy(c->fvv, hfvv.data(), sizeof(cplx) * hfvv.size(), hipMemcpyHostToDevice);
   }
-  if (!c->kc3 || !c->t1 || !c->t2 || !c->fac || !c->foo || !c->fvv || !lam_ok) {
+  if (!c->kc3 || !c->t1 || !c->t2 || (!c->fac && !c->eri_dense) || !c->foo || !c->fvv || !lam_ok) {
     g_init_err = "device allocation or upload failed";
     free_all(c);
     delete c;
@@ -571,6 +599,168 @@ extern "C" int cc_gf_learn_enable(ccgf_ctx *c, int on) {
   if (on < 0 || on > (CCGF_LEARN_GUESS | CCGF_LEARN_PRECOND))
     return set_err(c, CCGF_EINVAL, "on must be a mask of CCGF_LEARN_GUESS and CCGF_LEARN_PRECOND");
   c->learn_on = on;
+  return CCGF_OK;
+}
+
+// ---------------------------------------------------------------- trained networks on disk
+static const char kNetMagic[8] = {'C', 'C', 'G', 'F', 'N', 'E', 'T', '1'};
+static const int kNetVersion = 1;
+
+static void free_model(LearnModel &M) {
+  if (M.Q) hipFree(M.Q);
+  if (M.theta) hipFree(M.theta);
+  if (M.theta_p) hipFree(M.theta_p);
+  M.Q = nullptr;
+  M.theta = M.theta_p = nullptr;
+}
+
+extern "C" int cc_gf_learn_save(ccgf_ctx *c, const char *path) {
+  if (!c) return CCGF_ESTATE;
+  if (!path) return set_err(c, CCGF_EINVAL, "path is NULL");
+  if (c->models.empty()) return set_err(c, CCGF_ESTATE, "no trained networks to save (call cc_gf_learn)");
+  if (int rc = hip_check(c, hipStreamSynchronize(c->stream), "learn_save")) return rc;
+  FILE *f = std::fopen(path, "wb");
+  if (!f) return set_err(c, CCGF_EINVAL, std::string("cannot open ") + path + " for writing");
+  bool ok = true;
+  auto put = [&](const void *p, size_t b) { ok = ok && (b == 0 || std::fwrite(p, 1, b, f) == b); };
+  put(kNetMagic, 8);
+  const int hdr[5] = {kNetVersion, c->nk, c->no, c->nv, (int)c->models.size()};
+  put(hdr, sizeof hdr);
+  for (const LearnModel &M : c->models) {
+    const int iv[11] = {M.part, M.K, M.norb, M.ntrain, M.R, M.din, M.dout, M.hidden, M.mode, M.pdin, M.pdout};
+    const double dv[4] = {M.accept, M.wscale, M.wstep, M.pbase};
+    put(iv, sizeof iv);
+    put(dv, sizeof dv);
+    put(M.orbs.data(), sizeof(int) * M.norb);
+    put(M.occ.data(), sizeof(int) * M.norb);
+    put(M.fpp.data(), sizeof(double) * M.norb);
+    put(M.wtrain.data(), sizeof(double) * M.ntrain);
+    put(M.scale.data(), sizeof(double) * M.norb);
+    put(M.C.data(), sizeof(cplx) * M.C.size());
+    const long long n = vec_len(c, M.part);
+    put(&n, sizeof n);
+    std::vector<cplx> hq((size_t)M.R * n);  // one orbital's basis at a time
+    for (int b = 0; b < M.norb && ok; ++b) {
+      ok = hipMemcpy(hq.data(), M.Q + (size_t)b * hq.size(), sizeof(cplx) * hq.size(), hipMemcpyDeviceToHost) ==
+           hipSuccess;
+      put(hq.data(), sizeof(cplx) * hq.size());
+    }
+    const long long np = mlp_nparams(M.din, M.hidden, M.dout);
+    const long long npp = M.theta_p ? mlp_nparams(M.pdin, M.hidden, M.pdout) : 0;
+    std::vector<float> th((size_t)std::max(np, npp));
+    put(&np, sizeof np);
+    ok = ok && hipMemcpy(th.data(), M.theta, sizeof(float) * np, hipMemcpyDeviceToHost) == hipSuccess;
+    put(th.data(), sizeof(float) * np);
+    put(&npp, sizeof npp);
+    if (npp) {
+      ok = ok && hipMemcpy(th.data(), M.theta_p, sizeof(float) * npp, hipMemcpyDeviceToHost) == hipSuccess;
+      put(th.data(), sizeof(float) * npp);
+    }
+  }
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) return set_err(c, CCGF_EINVAL, std::string("writing ") + path + " failed");
+  return CCGF_OK;
+}
+
+extern "C" int cc_gf_learn_load(ccgf_ctx *c, const char *path) {
+  if (!c) return CCGF_ESTATE;
+  if (!path) return set_err(c, CCGF_EINVAL, "path is NULL");
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return set_err(c, CCGF_EINVAL, std::string("cannot open ") + path);
+  bool ok = true;
+  auto get = [&](void *p, size_t b) { ok = ok && (b == 0 || std::fread(p, 1, b, f) == b); };
+  std::string why;
+  char magic[8];
+  int hdr[5] = {0, 0, 0, 0, 0};
+  get(magic, 8);
+  get(hdr, sizeof hdr);
+  if (ok && (std::memcmp(magic, kNetMagic, 8) != 0 || hdr[0] != kNetVersion)) why = "not a network file of this version";
+  else if (ok && (hdr[1] != c->nk || hdr[2] != c->no || hdr[3] != c->nv))
+    why = "the networks were trained on another system shape";
+  else if (ok && (hdr[4] < 1 || hdr[4] > 2 * c->nk)) why = "bad model count";
+  std::vector<LearnModel> models;
+  auto fail = [&](const std::string &m) {
+    for (LearnModel &M : models) free_model(M);
+    std::fclose(f);
+    return set_err(c, CCGF_EINVAL, std::string(path) + ": " + m);
+  };
+  if (!ok) return fail("truncated header");
+  if (!why.empty()) return fail(why);
+  for (int q = 0; q < hdr[4]; ++q) {
+    models.emplace_back();
+    LearnModel &M = models.back();
+    int iv[11];
+    double dv[4];
+    get(iv, sizeof iv);
+    get(dv, sizeof dv);
+    if (!ok) return fail("truncated model header");
+    M.part = iv[0], M.K = iv[1], M.norb = iv[2], M.ntrain = iv[3], M.R = iv[4], M.din = iv[5], M.dout = iv[6];
+    M.hidden = iv[7], M.mode = iv[8], M.pdin = iv[9], M.pdout = iv[10];
+    M.accept = dv[0], M.wscale = dv[1], M.wstep = dv[2], M.pbase = dv[3];
+    if ((M.part != CCGF_PART_IP && M.part != CCGF_PART_EA) || M.K < 0 || M.K >= c->nk || M.norb < 1 ||
+        M.norb > c->nmo || M.ntrain < 1 || M.ntrain > 32 || M.R < 1 || M.R > 4096 || M.din < 1 || M.dout < 1 ||
+        M.hidden < 1 || M.hidden > 4096 || M.pdin < 0 || M.pdout < 0 || M.dout > 4096 || M.din > 4096)
+      return fail("model dimensions out of range");
+    M.orbs.resize(M.norb);
+    M.occ.resize(M.norb);
+    M.fpp.resize(M.norb);
+    M.wtrain.resize(M.ntrain);
+    M.scale.resize(M.norb);
+    M.C.resize((size_t)M.norb * M.ntrain * M.R);
+    get(M.orbs.data(), sizeof(int) * M.norb);
+    get(M.occ.data(), sizeof(int) * M.norb);
+    get(M.fpp.data(), sizeof(double) * M.norb);
+    get(M.wtrain.data(), sizeof(double) * M.ntrain);
+    get(M.scale.data(), sizeof(double) * M.norb);
+    get(M.C.data(), sizeof(cplx) * M.C.size());
+    long long n = 0;
+    get(&n, sizeof n);
+    if (!ok) return fail("truncated model");
+    if (n != vec_len(c, M.part)) return fail("vector length differs from this system's");
+    for (int b = 0; b < M.norb; ++b)
+      if (M.orbs[b] < 0 || M.orbs[b] >= c->nmo) return fail("orbital index out of range");
+    std::vector<cplx> hq((size_t)M.R * n);
+    if (hipMalloc(&M.Q, sizeof(cplx) * hq.size() * M.norb) != hipSuccess) {
+      (void)hipGetLastError();
+      M.Q = nullptr;
+      return fail("device allocation of the basis failed");
+    }
+    for (int b = 0; b < M.norb && ok; ++b) {
+      get(hq.data(), sizeof(cplx) * hq.size());
+      ok = ok && hipMemcpy(M.Q + (size_t)b * hq.size(), hq.data(), sizeof(cplx) * hq.size(),
+                           hipMemcpyHostToDevice) == hipSuccess;
+    }
+    long long np = 0, npp = 0;
+    get(&np, sizeof np);
+    if (!ok || np != mlp_nparams(M.din, M.hidden, M.dout)) return fail("bad guess-network parameters");
+    std::vector<float> th((size_t)np);
+    get(th.data(), sizeof(float) * np);
+    if (!ok || hipMalloc(&M.theta, sizeof(float) * np) != hipSuccess ||
+        hipMemcpy(M.theta, th.data(), sizeof(float) * np, hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail("reading or uploading the guess network failed");
+    }
+    get(&npp, sizeof npp);
+    if (!ok || (npp != 0 && npp != mlp_nparams(M.pdin, M.hidden, M.pdout)))
+      return fail("bad preconditioner-network parameters");
+    if (npp) {
+      th.resize((size_t)npp);
+      get(th.data(), sizeof(float) * npp);
+      if (!ok || hipMalloc(&M.theta_p, sizeof(float) * npp) != hipSuccess ||
+          hipMemcpy(M.theta_p, th.data(), sizeof(float) * npp, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail("reading or uploading the preconditioner network failed");
+      }
+    }
+  }
+  std::fclose(f);
+  if (int rc = hip_check(c, hipStreamSynchronize(c->stream), "learn_load")) {
+    for (LearnModel &M : models) free_model(M);
+    return rc;
+  }
+  for (LearnModel &M : c->models) free_model(M);
+  c->models = std::move(models);
+  c->learn_on = CCGF_LEARN_GUESS | CCGF_LEARN_PRECOND;
   return CCGF_OK;
 }
 

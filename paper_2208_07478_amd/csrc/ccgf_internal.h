@@ -248,6 +248,7 @@ struct ccgf_ctx {
   long long nwblk = 0;
   cplx *Woooo = nullptr, *Wooov = nullptr, *Wovoo = nullptr, *Wovvo = nullptr;
   cplx *Wvovv = nullptr, *Wvvvo = nullptr, *Wvvvv = nullptr, *Voovv = nullptr;
+  cplx *eri_dense = nullptr;  // dense <pq|rs> blocks [k1][k2][k3][p][q][r][s] when given instead of the factor
   cplx *WvoP = nullptr;   // W_ovvo permuted to [kx][ki][km](x, i, m, e)
   cplx *WvoPea = nullptr; // the same with F_vv added on the blocks km = ki, m = i (EA operand)
   cplx *WooP = nullptr;   // W_oooo permuted to [ki][kj][km](i, j, m, n)

@@ -39,16 +39,22 @@ __device__ inline I7 dec(size_t i, int nk, int n1, int n2, int n3, int n4) {
   return r;
 }
 
-// Antisymmetrised <p k1, q k2 || r k3, s k4> from the factor (global orbital indices).
+// Antisymmetrised <p k1, q k2 || r k3, s k4> = <pq|rs> - <pq|sr> (global orbital indices)
+// from the factor, or from the dense blocks D when those were given instead.
 struct Eri {
   const cplx *A;
   int nk, naux, nmo;
   KTab kt;
+  const cplx *D;
   __device__ inline cplx fac(int ka, int kb, int L, int p, int r) const {
     return A[((((size_t)ka * nk + kb) * naux + L) * nmo + p) * nmo + r];
   }
+  __device__ inline cplx dense(int k1, int k2, int k3, int p, int q, int r, int s) const {
+    return D[((((((size_t)k1 * nk + k2) * nk + k3) * nmo + p) * nmo + q) * nmo + r) * nmo + s];
+  }
   __device__ inline cplx operator()(int k1, int k2, int k3, int p, int q, int r, int s) const {
     int k4 = kt.c3(k1, k2, k3);
+    if (D) return csub(dense(k1, k2, k3, p, q, r, s), dense(k1, k2, k4, p, q, s, r));
     cplx acc = mkc(0, 0);
     for (int L = 0; L < naux; ++L) {
       cfma(acc, fac(k1, k3, L, p, r), fac(k2, k4, L, q, s));
@@ -92,7 +98,7 @@ int build_hbar(ccgf_ctx *c) {
   const int nk = c->nk, no = c->no, nv = c->nv, nmo = c->nmo;
   hipStream_t s = c->stream;
   KTab kt{nk, c->kc3};
-  Eri eri{c->fac, nk, c->naux, nmo, kt};
+  Eri eri{c->fac, nk, c->naux, nmo, kt, c->eri_dense};
 
   // ---- bare antisymmetrised integral classes (o = occupied, v = virtual)
   auto cls = [&](const char *spec) {

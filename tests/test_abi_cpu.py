@@ -116,3 +116,61 @@ def test_options_and_new_entry_points_are_checked_on_the_host():
         assert lib.cc_gf_mlp_grad(din, hid, dout, None, N, None, None, None, None) == ccgf.EINVAL
     one = (ctypes.c_float * 64)()
     assert lib.cc_gf_mlp_grad(3, 4, 2, None, 3, one, one, one, None) == ccgf.EINVAL
+
+
+def dense_eri(s):
+    """<p k1, q k2 | r k3, s k4> = sum_L A[k1][k3][L][p][r] A[k2][k4][L][q][s] (the factor's
+    definition), k4 = k1 + k2 - k3, as dense blocks [k1][k2][k3][p][q][r][s]."""
+    from oracle.ktensor import KMesh
+    mesh = KMesh(s.kmesh)
+    nk, n = mesh.nk, s.nocc + s.nvir
+    A = s.eri_factor
+    D = np.zeros((nk, nk, nk, n, n, n, n), dtype=np.complex128)
+    for k1 in range(nk):
+        for k2 in range(nk):
+            for k3 in range(nk):
+                k4 = mesh.lin([(1, k1), (1, k2), (-1, k3)])
+                D[k1, k2, k3] = np.einsum("Lpr,Lqs->pqrs", A[k1, k3], A[k2, k4])
+    return D
+
+
+def test_eri_blocks_are_checked_on_the_host():
+    """Dense ERI blocks instead of the factor: exactly one of the two, and the blocks
+    must be Hermitian (<pq|rs> = conj(<rs|pq>)) and symmetric under particle exchange."""
+    lib = ccgf.load()
+    s = synth.make_system((2, 1, 1), 2, 3, seed=1)
+    h = ctypes.c_void_p()
+    D = dense_eri(s)
+    # the factor's own blocks pass both symmetries (checked here in numpy)
+    from oracle.ktensor import KMesh
+    mesh = KMesh(s.kmesh)
+    for k1 in range(mesh.nk):
+        for k2 in range(mesh.nk):
+            for k3 in range(mesh.nk):
+                k4 = mesh.lin([(1, k1), (1, k2), (-1, k3)])
+                assert np.allclose(D[k1, k2, k3], D[k3, k4, k1].transpose(2, 3, 0, 1).conj(), atol=1e-14)
+                assert np.allclose(D[k1, k2, k3], D[k2, k1, k4].transpose(1, 0, 3, 2), atol=1e-14)
+    # both given
+    cs, keep = _system_struct(s)
+    keep.append(D)
+    cs.eri_blocks = D.ctypes.data
+    assert lib.cc_gf_init(ctypes.byref(cs), None, ctypes.byref(h)) == ccgf.EINVAL
+    assert b"exactly one" in lib.cc_gf_last_error(None)
+    # neither
+    cs, keep = _system_struct(s)
+    cs.eri_factor = None
+    assert lib.cc_gf_init(ctypes.byref(cs), None, ctypes.byref(h)) == ccgf.EINVAL
+    # blocks that break Hermiticity
+    Db = D.copy()
+    Db[0, 1, 0, 0, 2, 1, 3] += 0.2
+    cs, keep = _system_struct(s)
+    keep.append(Db)
+    cs.eri_factor, cs.naux, cs.eri_blocks = None, 0, Db.ctypes.data
+    assert lib.cc_gf_init(ctypes.byref(cs), None, ctypes.byref(h)) == ccgf.EINVAL
+    assert b"eri_blocks" in lib.cc_gf_last_error(None)
+
+
+def test_network_files_need_a_context():
+    lib = ccgf.load()
+    assert lib.cc_gf_learn_save(None, b"/tmp/x") == ccgf.ESTATE
+    assert lib.cc_gf_learn_load(None, b"/tmp/x") == ccgf.ESTATE

@@ -116,3 +116,46 @@ def test_learned_preconditioner_gain_and_fallback():
     finally:
         ctx.close()
         torch.cuda.synchronize()
+
+
+def test_trained_networks_survive_save_and_load(tmp_path):
+    """cc_gf_learn_save / cc_gf_learn_load: a fresh context of the same system that loads
+    the file solves exactly like the context that trained (same G bit for bit, same
+    iterations); another system shape and a foreign file are refused."""
+    import torch
+    from paper_2208_07478_amd.ccgf import CCGFError, Context
+    case = dict(kmesh=(2, 1, 1), nocc=2, nvir=5, seed=12)
+    s = synth.make_system(t1_std=0.05, t2_std=0.05, eri_std=0.1, **case)
+    eta = 0.005
+    window = np.linspace(-0.28, 0.18, 9)
+    orbs = list(range(s.nocc + s.nvir))
+    path = tmp_path / "nets.bin"
+    opts = dict(tol=1e-10, restart_m=60, maxiter=20000, max_batch=128, precond_eta=0.4)
+    a = Context(s, **opts)
+    b = Context(s, **opts)
+    try:
+        with pytest.raises(CCGFError):
+            a.learn_save(path)  # nothing trained yet
+        a.learn(0, orbs, window[0::2], eta, epochs=200, seed=3, probe=20)
+        a.learn_save(path)
+        b.learn_load(path)
+        ra = a.solve([0], orbs, window[1::2], eta)
+        rb = b.solve([0], orbs, window[1::2], eta)
+        print("iterations", ra[3]["n_iterations"], rb[3]["n_iterations"], "guesses", ra[3]["n_guess"], flush=True)
+        assert ra[3]["n_iterations"] == rb[3]["n_iterations"] and ra[3]["n_guess"] == rb[3]["n_guess"]
+        assert np.array_equal(ra[0], rb[0])
+    finally:
+        a.close()
+        b.close()
+    s2 = synth.make_system(t1_std=0.05, t2_std=0.05, eri_std=0.1, kmesh=(2, 1, 1), nocc=2, nvir=6, seed=12)
+    c = Context(s2, **opts)
+    try:
+        with pytest.raises(CCGFError, match="another system shape"):
+            c.learn_load(path)
+        junk = tmp_path / "junk.bin"
+        junk.write_bytes(b"not a network file")
+        with pytest.raises(CCGFError):
+            c.learn_load(junk)
+    finally:
+        c.close()
+        torch.cuda.synchronize()

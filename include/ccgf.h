@@ -65,9 +65,13 @@ enum { CCGF_HOST = 0, CCGF_DEVICE = 1 };
 enum { CCGF_PART_IP = 1, CCGF_PART_EA = 2, CCGF_PART_BOTH = 3 };
 /* Arithmetic of the sigma products inside the Krylov steps.  The residuals that
  * decide convergence, the Arnoldi orthogonalisation, the Hessenberg least squares
- * and the solution updates are FP64 in every mode; in the mixed mode the FP64
+ * and the solution updates are FP64 in every mode; in the mixed modes the FP64
  * true residual restarts every cycle, so the restarted solve is an iterative
- * refinement and still reaches tol. */
+ * refinement and still reaches tol.  CCGF_MIXED_F32: the big products from
+ * complex-float operands on FP32 MFMA.  CCGF_MIXED_BF16X3: from operands split
+ * into bf16 hi + lo (x = hi + lo to about 2^-16), three BF16 MFMA products per
+ * real product (hi hi + hi lo + lo hi) with FP32 accumulation; both operand copies
+ * take 8 bytes per complex element. */
 enum { CCGF_PLAIN_F64 = 0, CCGF_MIXED_F32 = 1, CCGF_MIXED_BF16X3 = 2 };
 
 /* One periodic system.  All pointers are borrowed for the duration of

@@ -211,7 +211,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only (the solves of different K, orbitals "
-                                   "and frequencies are independent; see DESIGN.md for sharding); use --gpus 1"}))
+                                   "and frequencies are independent: sharding them over GPUs needs no exchange "
+                                   "but the final gather of G); use --gpus 1"}))
         sys.exit(2)
     import torch
 

@@ -1,6 +1,7 @@
 // C ABI of the CCGF library: argument checking, upload, context life cycle and
 // the frequency / orbital / momentum loops of cc_gf_solve (Eqs. 6, 7, 9).
 #include <chrono>
+#include <exception>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -614,7 +615,7 @@ static void free_model(LearnModel &M) {
   M.theta = M.theta_p = nullptr;
 }
 
-extern "C" int cc_gf_learn_save(ccgf_ctx *c, const char *path) {
+static int learn_save_impl(ccgf_ctx *c, const char *path) {
   if (!c) return CCGF_ESTATE;
   if (!path) return set_err(c, CCGF_EINVAL, "path is NULL");
   if (c->models.empty()) return set_err(c, CCGF_ESTATE, "no trained networks to save (call cc_gf_learn)");
@@ -662,7 +663,7 @@ extern "C" int cc_gf_learn_save(ccgf_ctx *c, const char *path) {
   return CCGF_OK;
 }
 
-extern "C" int cc_gf_learn_load(ccgf_ctx *c, const char *path) {
+static int learn_load_impl(ccgf_ctx *c, const char *path) {
   if (!c) return CCGF_ESTATE;
   if (!path) return set_err(c, CCGF_EINVAL, "path is NULL");
   FILE *f = std::fopen(path, "rb");
@@ -717,6 +718,8 @@ extern "C" int cc_gf_learn_load(ccgf_ctx *c, const char *path) {
     get(&n, sizeof n);
     if (!ok) return fail("truncated model");
     if (n != vec_len(c, M.part)) return fail("vector length differs from this system's");
+    if ((double)M.R * (double)n * sizeof(cplx) > 64.0 * (double)(1ull << 30))
+      return fail("basis staging above 64 GiB per orbital");
     for (int b = 0; b < M.norb; ++b)
       if (M.orbs[b] < 0 || M.orbs[b] >= c->nmo) return fail("orbital index out of range");
     std::vector<cplx> hq((size_t)M.R * n);
@@ -762,6 +765,23 @@ extern "C" int cc_gf_learn_load(ccgf_ctx *c, const char *path) {
   c->models = std::move(models);
   c->learn_on = CCGF_LEARN_GUESS | CCGF_LEARN_PRECOND;
   return CCGF_OK;
+}
+
+// (no C++ exception crosses the ABI: host allocations that fail report CCGF_ENOMEM)
+extern "C" int cc_gf_learn_save(ccgf_ctx *c, const char *path) {
+  try {
+    return learn_save_impl(c, path);
+  } catch (const std::exception &e) {
+    return set_err(c, CCGF_ENOMEM, std::string("learn_save: ") + e.what());
+  }
+}
+
+extern "C" int cc_gf_learn_load(ccgf_ctx *c, const char *path) {
+  try {
+    return learn_load_impl(c, path);
+  } catch (const std::exception &e) {
+    return set_err(c, CCGF_ENOMEM, std::string("learn_load: ") + e.what());
+  }
 }
 
 extern "C" void cc_gf_free(ccgf_ctx *c) {

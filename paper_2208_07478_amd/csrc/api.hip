@@ -118,7 +118,7 @@ static int validate_host(ccgf_ctx *c, const ccgf_system *s) {
   return CCGF_OK;
 }
 
-extern "C" int cc_gf_init(const ccgf_system *s, const ccgf_options *opt, ccgf_ctx **out) {
+static int cc_gf_init_impl(const ccgf_system *s, const ccgf_options *opt, ccgf_ctx **out) {
   if (!out) return set_err(nullptr, CCGF_EINVAL, "out is NULL");
   *out = nullptr;
   if (!s) return set_err(nullptr, CCGF_EINVAL, "system is NULL");
@@ -249,7 +249,7 @@ extern "C" int cc_gf_vector_size(const ccgf_ctx *c, int part, long long *n) {
   return CCGF_OK;
 }
 
-extern "C" int cc_gf_sigma(ccgf_ctx *c, int part, int K, int nvec, const double *x, double *y) {
+static int cc_gf_sigma_impl(ccgf_ctx *c, int part, int K, int nvec, const double *x, double *y) {
   if (!c) return CCGF_ESTATE;
   if (part != CCGF_PART_IP && part != CCGF_PART_EA) return set_err(c, CCGF_EINVAL, "part must be IP or EA");
   if (K < 0 || K >= c->nk) return set_err(c, CCGF_EINVAL, "K out of range");
@@ -260,7 +260,7 @@ extern "C" int cc_gf_sigma(ccgf_ctx *c, int part, int K, int nvec, const double 
   return hip_check(c, hipStreamSynchronize(c->stream), "cc_gf_sigma");
 }
 
-extern "C" int cc_gf_sigma_group(int nsys, ccgf_ctx *const *ctxs, const int *parts, const int *K, const int *nvec,
+static int cc_gf_sigma_group_impl(int nsys, ccgf_ctx *const *ctxs, const int *parts, const int *K, const int *nvec,
                                  const double *const *x, double *const *y) {
   if (nsys < 1 || !ctxs || !ctxs[0]) return CCGF_ESTATE;
   ccgf_ctx *c0 = ctxs[0];
@@ -286,7 +286,7 @@ extern "C" int cc_gf_sigma_group(int nsys, ccgf_ctx *const *ctxs, const int *par
   return hip_check(c0, hipStreamSynchronize(c0->stream), "cc_gf_sigma_group");
 }
 
-extern "C" int cc_gf_vectors(ccgf_ctx *c, int part, int K, int p, double *b, double *e) {
+static int cc_gf_vectors_impl(ccgf_ctx *c, int part, int K, int p, double *b, double *e) {
   if (!c) return CCGF_ESTATE;
   if (part != CCGF_PART_IP && part != CCGF_PART_EA) return set_err(c, CCGF_EINVAL, "part must be IP or EA");
   if (K < 0 || K >= c->nk || p < 0 || p >= c->nmo) return set_err(c, CCGF_EINVAL, "K or p out of range");
@@ -423,7 +423,7 @@ static int solve_common(ccgf_ctx *c, int nkq, const int *kidx, int norb, const i
   return status;
 }
 
-extern "C" int cc_gf_solve(ccgf_ctx *c, int nkq, const int *kidx, int norb, const int *orbs, int nw,
+static int cc_gf_solve_impl(ccgf_ctx *c, int nkq, const int *kidx, int norb, const int *orbs, int nw,
                            const double *omega, double eta, int parts, double *G, double *Gp, double *Gm,
                            ccgf_stats *st) {
   if (!c) return CCGF_ESTATE;
@@ -431,7 +431,7 @@ extern "C" int cc_gf_solve(ccgf_ctx *c, int nkq, const int *kidx, int norb, cons
   return solve_common(c, nkq, kidx, norb, orbs, nw, omega, eta, parts, G, Gp, Gm, nullptr, nullptr, nullptr, st);
 }
 
-extern "C" int cc_gf_solve_matrix(ccgf_ctx *c, int nkq, const int *kidx, int norb, const int *orbs, int nw,
+static int cc_gf_solve_matrix_impl(ccgf_ctx *c, int nkq, const int *kidx, int norb, const int *orbs, int nw,
                                   const double *omega, double eta, int parts, double *G, double *Gp, double *Gm,
                                   double *dos, ccgf_stats *st) {
   if (!c) return CCGF_ESTATE;
@@ -460,7 +460,7 @@ extern "C" int cc_gf_solve_matrix(ccgf_ctx *c, int nkq, const int *kidx, int nor
   return rc;
 }
 
-extern "C" int cc_gf_mor(ccgf_ctx *c, int nkq, const int *kidx, int norb, const int *orbs, int nexp_ip,
+static int cc_gf_mor_impl(ccgf_ctx *c, int nkq, const int *kidx, int norb, const int *orbs, int nexp_ip,
                          const double *wexp_ip, int nexp_ea, const double *wexp_ea, int nw, const double *omega,
                          double eta, int parts, double *G, double *Gp, double *Gm, ccgf_stats *st) {
   if (!c) return CCGF_ESTATE;
@@ -530,7 +530,7 @@ extern "C" int cc_gf_mor(ccgf_ctx *c, int nkq, const int *kidx, int norb, const 
   return status;
 }
 
-extern "C" int cc_gf_learn(ccgf_ctx *c, int parts, int K, int norb, const int *orbs, int ntrain, const double *wtr,
+static int cc_gf_learn_impl(ccgf_ctx *c, int parts, int K, int norb, const int *orbs, int ntrain, const double *wtr,
                            double eta, const ccgf_learn_options *opt, ccgf_learn_stats *st) {
   if (!c) return CCGF_ESTATE;
   if (parts < 1 || parts > 3) return set_err(c, CCGF_EINVAL, "parts must be CCGF_PART_IP, _EA or _BOTH");
@@ -573,7 +573,7 @@ extern "C" int cc_gf_learn(ccgf_ctx *c, int parts, int K, int norb, const int *o
   return status;
 }
 
-extern "C" int cc_gf_set_options(ccgf_ctx *c, const ccgf_options *opt) {
+static int cc_gf_set_options_impl(ccgf_ctx *c, const ccgf_options *opt) {
   if (!c) return CCGF_ESTATE;
   if (!opt) return set_err(c, CCGF_EINVAL, "options are NULL");
   ccgf_options o = *opt;
@@ -675,7 +675,8 @@ static int learn_load_impl(ccgf_ctx *c, const char *path) {
   int hdr[5] = {0, 0, 0, 0, 0};
   get(magic, 8);
   get(hdr, sizeof hdr);
-  if (ok && (std::memcmp(magic, kNetMagic, 8) != 0 || hdr[0] != kNetVersion)) why = "not a network file of this version";
+  if (ok && (std::memcmp(magic, kNetMagic, 8) != 0 || hdr[0] != kNetVersion))
+    why = "not a network file of this version";
   else if (ok && (hdr[1] != c->nk || hdr[2] != c->no || hdr[3] != c->nv))
     why = "the networks were trained on another system shape";
   else if (ok && (hdr[4] < 1 || hdr[4] > 2 * c->nk)) why = "bad model count";
@@ -768,19 +769,100 @@ static int learn_load_impl(ccgf_ctx *c, const char *path) {
 }
 
 // (no C++ exception crosses the ABI: host allocations that fail report CCGF_ENOMEM)
+extern "C" int cc_gf_init(const ccgf_system *s, const ccgf_options *opt, ccgf_ctx **out) {
+  try {
+    return cc_gf_init_impl(s, opt, out);
+  } catch (const std::exception &ex) {
+    return set_err(nullptr, CCGF_ENOMEM, std::string("cc_gf_init: ") + ex.what());
+  }
+}
+
+extern "C" int cc_gf_sigma(ccgf_ctx *c, int part, int K, int nvec, const double *x, double *y) {
+  try {
+    return cc_gf_sigma_impl(c, part, K, nvec, x, y);
+  } catch (const std::exception &ex) {
+    return set_err(c, CCGF_ENOMEM, std::string("cc_gf_sigma: ") + ex.what());
+  }
+}
+
+extern "C" int cc_gf_sigma_group(int nsys, ccgf_ctx *const *ctxs, const int *parts, const int *K, const int *nvec,
+                                 const double *const *x, double *const *y) {
+  try {
+    return cc_gf_sigma_group_impl(nsys, ctxs, parts, K, nvec, x, y);
+  } catch (const std::exception &ex) {
+    return set_err(nullptr, CCGF_ENOMEM, std::string("cc_gf_sigma_group: ") + ex.what());
+  }
+}
+
+extern "C" int cc_gf_vectors(ccgf_ctx *c, int part, int K, int p, double *b, double *e) {
+  try {
+    return cc_gf_vectors_impl(c, part, K, p, b, e);
+  } catch (const std::exception &ex) {
+    return set_err(c, CCGF_ENOMEM, std::string("cc_gf_vectors: ") + ex.what());
+  }
+}
+
+extern "C" int cc_gf_solve(ccgf_ctx *c, int nkq, const int *kidx, int norb, const int *orbs, int nw,
+                           const double *omega, double eta, int parts, double *G, double *Gp, double *Gm,
+                           ccgf_stats *st) {
+  try {
+    return cc_gf_solve_impl(c, nkq, kidx, norb, orbs, nw, omega, eta, parts, G, Gp, Gm, st);
+  } catch (const std::exception &ex) {
+    return set_err(c, CCGF_ENOMEM, std::string("cc_gf_solve: ") + ex.what());
+  }
+}
+
+extern "C" int cc_gf_solve_matrix(ccgf_ctx *c, int nkq, const int *kidx, int norb, const int *orbs, int nw,
+                                  const double *omega, double eta, int parts, double *G, double *Gp, double *Gm,
+                                  double *dos, ccgf_stats *st) {
+  try {
+    return cc_gf_solve_matrix_impl(c, nkq, kidx, norb, orbs, nw, omega, eta, parts, G, Gp, Gm, dos, st);
+  } catch (const std::exception &ex) {
+    return set_err(c, CCGF_ENOMEM, std::string("cc_gf_solve_matrix: ") + ex.what());
+  }
+}
+
+extern "C" int cc_gf_mor(ccgf_ctx *c, int nkq, const int *kidx, int norb, const int *orbs, int nexp_ip,
+                         const double *wexp_ip, int nexp_ea, const double *wexp_ea, int nw, const double *omega,
+                         double eta, int parts, double *G, double *Gp, double *Gm, ccgf_stats *st) {
+  try {
+    return cc_gf_mor_impl(c, nkq, kidx, norb, orbs, nexp_ip, wexp_ip, nexp_ea, wexp_ea, nw, omega, eta, parts, G,
+                          Gp, Gm, st);
+  } catch (const std::exception &ex) {
+    return set_err(c, CCGF_ENOMEM, std::string("cc_gf_mor: ") + ex.what());
+  }
+}
+
+extern "C" int cc_gf_learn(ccgf_ctx *c, int parts, int K, int norb, const int *orbs, int ntrain, const double *wtr,
+                           double eta, const ccgf_learn_options *opt, ccgf_learn_stats *st) {
+  try {
+    return cc_gf_learn_impl(c, parts, K, norb, orbs, ntrain, wtr, eta, opt, st);
+  } catch (const std::exception &ex) {
+    return set_err(c, CCGF_ENOMEM, std::string("cc_gf_learn: ") + ex.what());
+  }
+}
+
+extern "C" int cc_gf_set_options(ccgf_ctx *c, const ccgf_options *opt) {
+  try {
+    return cc_gf_set_options_impl(c, opt);
+  } catch (const std::exception &ex) {
+    return set_err(c, CCGF_ENOMEM, std::string("cc_gf_set_options: ") + ex.what());
+  }
+}
+
 extern "C" int cc_gf_learn_save(ccgf_ctx *c, const char *path) {
   try {
     return learn_save_impl(c, path);
-  } catch (const std::exception &e) {
-    return set_err(c, CCGF_ENOMEM, std::string("learn_save: ") + e.what());
+  } catch (const std::exception &ex) {
+    return set_err(c, CCGF_ENOMEM, std::string("learn_save: ") + ex.what());
   }
 }
 
 extern "C" int cc_gf_learn_load(ccgf_ctx *c, const char *path) {
   try {
     return learn_load_impl(c, path);
-  } catch (const std::exception &e) {
-    return set_err(c, CCGF_ENOMEM, std::string("learn_load: ") + e.what());
+  } catch (const std::exception &ex) {
+    return set_err(c, CCGF_ENOMEM, std::string("learn_load: ") + ex.what());
   }
 }
 

@@ -54,7 +54,7 @@ typedef struct ccgf_ctx ccgf_ctx;
 enum {
   CCGF_OK = 0,
   CCGF_EINVAL = -1,       /* bad argument, shape or symmetry */
-  CCGF_ENOMEM = -2,       /* device allocation failed */
+  CCGF_ENOMEM = -2,       /* device (or host working) allocation failed; no C++ exception leaves the library */
   CCGF_EDEVICE = -3,      /* HIP runtime error */
   CCGF_ENOCONV = -4,      /* some solve missed the tolerance; G still written */
   CCGF_ESTATE = -5,       /* call out of order (e.g. NULL context) */

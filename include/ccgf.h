@@ -100,8 +100,8 @@ typedef struct {
   /* Alternative to eri_factor for small systems: the physicists' integrals as dense
    * momentum blocks, complex [k1][k2][k3][nmo][nmo][nmo][nmo] = <p k1, q k2 | r k3, s k4>
    * with k4 = k1 + k2 - k3, in the factor's normalisation.  Exactly one of eri_factor
-   * and eri_blocks is given.  Checked on the host (CCGF_EINVAL): <pq|rs> = conj(<rs|pq>)
-   * and <pq|rs> = <qp|sr> to 1e-10 of the largest element. */
+   * and eri_blocks is given.  Checked when given in host memory (CCGF_EINVAL):
+   * <pq|rs> = conj(<rs|pq>) and <pq|rs> = <qp|sr> to 1e-10 of the largest element. */
   const double *eri_blocks;
 } ccgf_system;
 
